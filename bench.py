@@ -1,0 +1,233 @@
+"""Benchmark: full DE fits of a 400 000-sample block on one MI355X.
+
+One step = one complete fit of the paper-scale block (400 000 FP32 samples
+at 50 kHz, cubic phase, SNR 0 dB; DE/rand/1/bin with P = 40, F = 0.5,
+CR = 0.9 and 2000 generations, i.e. 40 x 2001 objective evaluations over
+all samples), starting from samples already resident in HBM and ending with
+the fitted record (coefficients + derived observables) on the host.
+
+Printed (one JSON line): candidate*sample evaluations per second of the
+plain FP64 path, fit latency p50 / p99 of the plain and mixed-precision
+paths, the mixed path's speedup and error against the FP64 oracle, the
+objective kernel's roofline figures (HIP-event timing of its launches inside
+a fit) and the CPU oracle's rate on a bounded sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6    # MI355X FP64 vector
+PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector (published, packed)
+# Algorithmic FLOP per candidate*sample (see the design notes): phase cubic
+# (3 FMA) + turn reduction (1) + r^2 (1) + cosine polynomial (degree 10 FP64
+# / degree 6 FP32, one FMA per degree) + residual FMA + square-accumulate FMA.
+FLOP_PER_PAIR = {"fp64": 6 + 1 + 1 + 20 + 2 + 2, "mixed": 6 + 1 + 1 + 12 + 2 + 2}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "objective_traffic.json")
+KERNEL_SRC = [os.path.join(ROOT, "paper_1906_10598_amd", "csrc", f) for f in ("kernels.h", "device.h")]
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SRC:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def pct(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    k = (len(xs) - 1) * q / 100.0
+    lo, hi = math.floor(k), math.ceil(k)
+    return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
+
+
+def run_fits(ctx, blk, de_fn, n, label):
+    import torch
+
+    lat = []
+    fits = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(n):
+        t1 = time.perf_counter()
+        fits.append(ctx.fit_block(blk, de_fn(k)))
+        lat.append((time.perf_counter() - t1) * 1e3)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, lat, fits
+
+
+def cpu_baseline(b, gens, nthreads):
+    import numpy as np
+
+    import oracle
+
+    s64 = b.samples.astype(np.float64)
+    oracle.lib()
+    t0 = time.perf_counter()
+    r = oracle.de_fit(s64, b.fs, b.ref, b.lo, b.hi, b.de.pop, gens, F=b.de.F, CR=b.de.CR, seed=b.de.seed,
+                      stream=b.stream, nthreads=nthreads)
+    dt = time.perf_counter() - t0
+    pairs = b.de.pop * (r["generations"] + 1) * b.n
+    return pairs / dt, dt
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--latency-fits", type=int, default=100, help="fits per path for p50/p99")
+    ap.add_argument("--cpu-gens", type=int, default=120, help="oracle generations in the CPU sample")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-tune", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the fit of one block does not shard; see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1906_10598_amd import phasetrack as ptk
+
+    b = synth.config1(0)
+    P, G, N = b.de.pop, b.de.max_gens, b.n
+    pairs_per_fit = P * (G + 1) * N
+    dev = torch.from_numpy(b.samples).cuda()
+    ctx = ptk.Context(0)
+    blk = ptk.make_block(dev, b.fs, b.lo, b.hi, ref=b.ref, stream=b.stream)
+    stream = ptk.current_stream()
+
+    tiles = {}
+    for name, prec in (("fp64", ptk.PT_PREC_FP64), ("mixed", ptk.PT_PREC_MIXED)):
+        if not args.no_tune:
+            ptk.pt_ctx_autotune(ctx.handle, N, P, prec, stream)
+        tiles[name] = ptk.pt_ctx_get_tile(ctx.handle, N, P, prec)
+    print(f"# geometry (samples/lane, candidates/workgroup): {tiles}", file=sys.stderr, flush=True)
+
+    def de(prec):
+        return lambda k: ptk.make_settings(pop=P, max_gens=G, F=b.de.F, CR=b.de.CR, seed=b.de.seed + k,
+                                           precision=prec)
+
+    # ---- plain FP64: warmup + timed steps
+    run_fits(ctx, blk, de(ptk.PT_PREC_FP64), args.warmup, "warmup")
+    elapsed, lat_steps, fits64 = run_fits(ctx, blk, de(ptk.PT_PREC_FP64), args.steps, "fp64")
+    value = pairs_per_fit * args.steps / elapsed
+    print(f"# fp64: {args.steps} fits in {elapsed:.3f} s", file=sys.stderr, flush=True)
+
+    # ---- latency percentiles (distinct seeds), both paths
+    extra = max(0, args.latency_fits - args.steps)
+    _, lat_more, _ = run_fits(ctx, blk, lambda k: de(ptk.PT_PREC_FP64)(args.steps + k), extra, "fp64-lat")
+    lat64 = lat_steps + lat_more
+    run_fits(ctx, blk, de(ptk.PT_PREC_MIXED), max(1, args.warmup), "mixed-warm")
+    el_mx, lat_mx, fits_mx = run_fits(ctx, blk, de(ptk.PT_PREC_MIXED), max(args.latency_fits, 1), "mixed")
+    value_mx = pairs_per_fit * len(lat_mx) / el_mx
+    print(f"# mixed: {len(lat_mx)} fits in {el_mx:.3f} s", file=sys.stderr, flush=True)
+
+    # ---- accuracy of the mixed path against the FP64 oracle (same seed as fit 0)
+    import oracle
+
+    s64 = b.samples.astype(np.float64)
+    f64, fmx = fits64[0], fits_mx[0]
+    chi_or = oracle.chi2(s64, b.fs, b.ref, list(fmx.coef))
+    chi_or64 = oracle.chi2(s64, b.fs, b.ref, list(f64.coef))
+    mixed_err = {
+        "objective_rel_err": abs(fmx.objective - chi_or) / chi_or,
+        "fp64_objective_rel_err": abs(f64.objective - chi_or64) / chi_or64,
+        "f0_diff_hz": fmx.coef[2] - f64.coef[2],
+        "f1_diff_hz_s": fmx.coef[3] - f64.coef[3],
+        "f2_diff_hz_s2": fmx.coef[4] - f64.coef[4],
+        "f0_err_vs_truth_hz": {"fp64": f64.coef[2] - b.truth[2], "mixed": fmx.coef[2] - b.truth[2]},
+    }
+
+    # ---- roofline: HIP events around back-to-back launches of the objective
+    # kernel (same geometry and grid as the fits, on the fit's final
+    # population), plus the in-fit event-bracketed mean for reference
+    roof = {}
+    for name, prec in (("fp64", ptk.PT_PREC_FP64), ("mixed", ptk.PT_PREC_MIXED)):
+        ptk.pt_ctx_set_timing(ctx.handle, True)
+        ctx.fit_block(blk, de(prec)(0))
+        nl, ms = ptk.pt_ctx_kernel_stats(ctx.handle)
+        ptk.pt_ctx_set_timing(ctx.handle, False)
+        pop, _ = ptk.pt_last_population(ctx.handle, 0, P)
+        popd = torch.from_numpy(pop).cuda()
+        avg_ms = ptk.pt_time_objective(ctx.handle, blk, popd.data_ptr(), P, prec, 400, stream)
+        flop = FLOP_PER_PAIR[name] * P * N
+        ach = flop / (avg_ms * 1e-3) / 1e12
+        peak = PEAK_FP64_TFLOPS if name == "fp64" else PEAK_FP32_TFLOPS
+        roof[name] = {"avg_launch_ms": avg_ms, "in_fit_event_ms": ms / max(nl, 1), "launches": nl,
+                      "achieved": ach, "peak": peak}
+
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        try:
+            with open(TRAFFIC_FILE) as f:
+                tr = json.load(f)
+            if tr.get("kernel_hash") == kernel_hash() and tr.get("workload") == "paper-400000-fp32":
+                traffic = tr.get("bytes_per_launch")
+        except (OSError, ValueError):
+            traffic = None
+
+    # ---- CPU oracle baseline (bounded sample of the same fit)
+    cpu = None
+    if not args.no_cpu:
+        nthreads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
+        rate, dt = cpu_baseline(b, args.cpu_gens, nthreads)
+        cpu = {"value": rate, "unit": "candidate*sample/s", "cores": nthreads, "kind": "oracle",
+               "sample": f"first {args.cpu_gens} generations of the same 400000-sample fit "
+                         f"(P=40, {40 * (args.cpu_gens + 1) * N:.3e} candidate*samples, {dt:.1f} s)"}
+
+    r64 = roof["fp64"]
+    line = {
+        "metric": "candidate*sample evals/s + 400K-block fit p50/p99 latency, mixed vs plain FP64",
+        "value": value,
+        "unit": "candidate*sample/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "paper-scale block fit: N=400000 int16-quantised FP32 samples at 50 kHz, "
+                               "cubic phase, SNR 0 dB; DE/rand/1/bin P=40, F=0.5, CR=0.9, 2000 generations",
+                   "n_samples": N, "population": P, "generations": G, "precision": "fp64",
+                   "geometry": {"samples_per_lane": tiles["fp64"][0], "cand_per_group": tiles["fp64"][1]}},
+        "latency_ms": {
+            "fp64": {"p50": pct(lat64, 50), "p99": pct(lat64, 99), "fits": len(lat64)},
+            "mixed": {"p50": pct(lat_mx, 50), "p99": pct(lat_mx, 99), "fits": len(lat_mx)},
+        },
+        "block_fits_per_s": {"fp64": args.steps / elapsed, "mixed": len(lat_mx) / el_mx},
+        "mixed": {"value": value_mx, "speedup_vs_fp64": value_mx / value, **mixed_err,
+                  "geometry": {"samples_per_lane": tiles["mixed"][0], "cand_per_group": tiles["mixed"][1]},
+                  "roofline": {"bound": "alu", "achieved": roof["mixed"]["achieved"], "peak": PEAK_FP32_TFLOPS,
+                               "unit": "TFLOP/s", "frac": roof["mixed"]["achieved"] / PEAK_FP32_TFLOPS,
+                               "avg_launch_ms": roof["mixed"]["avg_launch_ms"]}},
+        "roofline": {"bound": "alu", "achieved": r64["achieved"], "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": r64["achieved"] / PEAK_FP64_TFLOPS, "traffic": traffic,
+                     "kernel": "k_objective (FP64)", "avg_launch_ms": r64["avg_launch_ms"],
+                     "in_fit_event_ms": r64["in_fit_event_ms"], "launches_per_fit": r64["launches"],
+                     "flop_per_candidate_sample": FLOP_PER_PAIR["fp64"],
+                     "kernel_hash": kernel_hash()},
+        "cpu_baseline": cpu,
+        "paper_context": {"gtx580_fit_s": 6.5, "evaluations": 80000, "block": "~400K samples"},
+    }
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

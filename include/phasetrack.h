@@ -1,0 +1,272 @@
+/*
+ * phasetrack.h -- C ABI of the MI355X phase-tracking fit library
+ * (libphasetrack.so).
+ *
+ * The library fits a block of real open-loop tracking samples s[n] to the
+ * model of Sec. 2.2 of "The GPU-based Phase Tracking method for Planetary
+ * Radio Science applications" (arXiv:1906.10598):
+ *
+ *     s(t) = (A + Adot t) cos(phi(t)),
+ *     phi(t) = phi0 + 2 pi (f0 t + f1 t^2 / 2 + f2 t^3 / 6)          (Eq. 2-2-1..2-2-3)
+ *
+ * by minimising the unit-weight chi-square of Eq. (2-2-4) with Differential
+ * Evolution (Sec. 1.2; control parameters of Table 4) in the DE/rand/1/bin
+ * form.  Time is measured from a reference sample: t_n = (n - ref) / fs,
+ * with ref = N / 2 (the block centre, Sec. 2.2) unless the caller gives one.
+ * From the fitted phase it derives the observables of Sec. 3.1.3 and
+ * Sec. 4: instantaneous phase and frequency (Eq. 3-1-1), border values
+ * (Eq. 3-1-2), total-count phase and integration Doppler (Eq. 4-1-1,
+ * 4-1-2) and line-of-sight acceleration (Eq. 4-2-1).
+ *
+ * Conventions shared by every entry point
+ *   - Parameter vectors have PT_NSLOT = 6 FP64 slots in this order:
+ *       0 A     amplitude, sample units
+ *       1 phi0  phase at the reference sample [rad]
+ *       2 f0    frequency [Hz]
+ *       3 f1    frequency rate [Hz/s]
+ *       4 f2    frequency acceleration [Hz/s^2]
+ *       5 Adot  amplitude slope [sample units / s] (c5 of Eq. 2-2-2)
+ *     A slot whose box has lo == hi is fixed at lo and takes no part in the
+ *     DE; the others are the active dimensions, in slot order.
+ *   - Return value: PT_OK (0) or a negative pt_status.  No C++ exception
+ *     and no abort crosses the ABI.  pt_last_error() returns a message for
+ *     the last failure on the calling thread (static storage, valid until
+ *     the next call on that thread).
+ *   - Ownership: every pointer argument is caller-owned; the library never
+ *     frees it and never keeps it after the call returns.  pt_ctx and
+ *     pt_server objects are library-owned (create / destroy).
+ *   - Device pointers are HIP device addresses on the context's device.
+ *     hip_stream is a hipStream_t (NULL = the null stream); calls that take
+ *     one enqueue their GPU work on it and return after the results they
+ *     report have been copied back (they synchronise that stream).
+ *   - A context is not thread-safe: one host thread at a time per pt_ctx.
+ */
+#ifndef PHASETRACK_H
+#define PHASETRACK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PT_NSLOT 6
+#define PT_MAX_POP 1024
+
+typedef enum {
+    PT_OK = 0,
+    PT_EINVAL = -1,       /* invalid argument (message names it) */
+    PT_ENOMEM = -2,       /* device or pinned-host allocation failed */
+    PT_EDEVICE = -3,      /* HIP runtime error, or no usable device */
+    PT_EBUSY = -4,        /* server: no slot / HBM budget for the block now */
+    PT_EUNSUPPORTED = -5  /* valid request this build does not implement */
+} pt_status;
+
+typedef enum { PT_F32 = 0, PT_F64 = 1 } pt_dtype;
+
+/* Arithmetic of the objective.  PT_PREC_FP64: phase, cosine, residual and
+ * sums in FP64.  PT_PREC_MIXED: FP64 per-chunk phase anchor, FP32 local
+ * phase offset (compensated), FP32 cosine and residual, FP32 chunk sums,
+ * FP64 cross-chunk sum; DE selection compares FP64 values in both modes. */
+typedef enum { PT_PREC_FP64 = 0, PT_PREC_MIXED = 1 } pt_precision;
+
+/* pt_fit.flags bits.  CONVERGED: the window stop rule was met; MAXGEN: the
+ * generation cap ended the fit; VTR: best <= vtr; AT_BOUND: an active
+ * non-phase coordinate of the best member lies within 1e-6 of its box
+ * width from a bound -- the signature of a search range that misses the
+ * truth (Sec. 3.1.1). */
+enum { PT_FLAG_CONVERGED = 1, PT_FLAG_MAXGEN = 2, PT_FLAG_VTR = 4, PT_FLAG_AT_BOUND = 8 };
+
+typedef struct pt_ctx pt_ctx;
+
+/* Search box (XCmin / XCmax of Table 4), per slot. */
+typedef struct {
+    double lo[PT_NSLOT];
+    double hi[PT_NSLOT];
+} pt_box;
+
+/* DE control parameters (Table 4) and stop rule (Sec. 3.1.2).
+ *   pop       population size P, 4 <= P <= PT_MAX_POP
+ *   max_gens  generation cap (itermax), >= 0
+ *   F         mutation scale, 0 < F <= 2
+ *   CR        crossover rate, 0 <= CR <= 1
+ *   seed      Philox4x32-10 key of the fit's random stream
+ *   vtr       stop as soon as the best objective is <= vtr (-inf: never)
+ *   rel_tol   > 0 selects the window rule: stop after generation g >= window
+ *             when best[g - window] - best[g] <= rel_tol * best[g];
+ *             <= 0: run exactly max_gens generations (fixed iteration
+ *             count, the paper's production choice)
+ *   window    window length W of that rule (>= 1 when rel_tol > 0)
+ *   precision pt_precision */
+typedef struct {
+    int32_t pop;
+    int32_t max_gens;
+    double F;
+    double CR;
+    uint64_t seed;
+    double vtr;
+    double rel_tol;
+    int32_t window;
+    int32_t precision;
+} pt_de_settings;
+
+/* One block of samples.
+ *   samples   n samples of type dtype; device pointer when on_device != 0,
+ *             else host pointer (copied to the device by the call)
+ *   n         number of samples, >= 8
+ *   fs        sample rate [Hz], > 0
+ *   ref       reference sample (time origin) in sample units; NaN selects
+ *             n / 2, the block centre
+ *   stream    id of the block's DE random stream (Philox counter word 2 and
+ *             high key word); give each (track, block) its own
+ *   box       search box */
+typedef struct {
+    const void* samples;
+    int64_t n;
+    int32_t dtype;
+    int32_t on_device;
+    double fs;
+    double ref;
+    uint64_t stream;
+    pt_box box;
+} pt_block;
+
+/* Result of one block fit, with the per-block output record of the
+ * paper's Appendix 1.
+ *   coef         best member (6 slots, as found inside the box)
+ *   objective    chi-square at coef (RSS)
+ *   generations  generations run after the initial population
+ *   flags        PT_FLAG_* bits
+ *   ref          reference sample used
+ *   t_left, t_right   block borders relative to the reference [s]:
+ *                (0 - ref) / fs and (n - ref) / fs
+ *   phase_centre phi(0) mod 2 pi [rad] (c0 of Appendix 1)
+ *   phase_left, phase_right  phi at the borders, mod 2 pi [rad] (Eq. 3-1-2)
+ *   freq_left, freq_right    instantaneous frequency at the borders [Hz]
+ *   total_phase  phi(t_right) - phi(t_left) [rad] (Eq. 4-1-2 term) */
+typedef struct {
+    double coef[PT_NSLOT];
+    double objective;
+    int32_t generations;
+    int32_t flags;
+    double ref;
+    double t_left, t_right;
+    double phase_centre;
+    double phase_left, phase_right;
+    double freq_left, freq_right;
+    double total_phase;
+} pt_fit;
+
+/* Library version (major * 10000 + minor * 100 + patch). */
+int pt_version(void);
+
+/* Message of the calling thread's last failure ("" if none). */
+const char* pt_last_error(void);
+
+/* Create a context on HIP device `device`; it owns the device buffers,
+ * cached launch graphs and tuning data of its fits.  PT_EDEVICE when the
+ * device does not exist or is not a gfx950 part. */
+int pt_ctx_create(int device, pt_ctx** out);
+
+/* Destroy a context and free everything it owns (NULL is ignored). */
+void pt_ctx_destroy(pt_ctx* ctx);
+
+/* Fit one block (Sec. 2.2 problem statement; Sec. 1.2 / Table 4 DE).
+ * The whole fit -- initial population, every generation's objective,
+ * mutation, crossover, selection and the stop rule -- runs on the device;
+ * the host reads back only the final record.  Returns after `out` is
+ * filled.  The fit is deterministic for a given (seed, block.stream). */
+int pt_fit_block(pt_ctx* ctx, const pt_block* block, const pt_de_settings* de,
+                 void* hip_stream, pt_fit* out);
+
+/* Fit nblk independent blocks of possibly different lengths, each with its
+ * own population and stream, with the same DE settings, in shared device
+ * launches (one objective grid over every block's samples x population per
+ * generation).  out[b] equals what pt_fit_block gives for block b alone
+ * (same kernels, same reduction order).  1 <= nblk <= 4096. */
+int pt_fit_batch(pt_ctx* ctx, const pt_block* blocks, int nblk, const pt_de_settings* de,
+                 void* hip_stream, pt_fit* out);
+
+/* Objective of an arbitrary population, for parity checks (Eq. 2-2-4).
+ *   pop       device pointer, P x 6 FP64, row-major
+ *   out       device pointer, P FP64
+ *   precision pt_precision */
+int pt_objective(pt_ctx* ctx, const pt_block* block, const double* pop, int P,
+                 int precision, void* hip_stream, double* out);
+
+/* Final population and objectives of block `index` of the context's most
+ * recent pt_fit_block / pt_fit_batch call.  pop_host: P x 6 FP64; fpop_host:
+ * P FP64 (either may be NULL); P must equal that call's population size. */
+int pt_last_population(pt_ctx* ctx, int index, double* pop_host, double* fpop_host, int P);
+
+/* Best-so-far objective after each generation 0..generations of block
+ * `index` of the most recent fit; copies min(n, generations + 1) values to
+ * hist_host and stores that count in *count. */
+int pt_last_history(pt_ctx* ctx, int index, double* hist_host, int n, int* count);
+
+/* ---- derived observables (host FP64; t is seconds from the fit's
+ * reference sample) ---- */
+
+/* Instantaneous phase and frequency at n time tags (Eq. 3-1-1).  Outputs
+ * (each may be NULL): phase [rad], phase mod 2 pi [rad], frequency [Hz],
+ * frequency rate [Hz/s]. */
+int pt_phase(const pt_fit* fit, const double* t, int64_t n, double* phase,
+             double* phase_mod2pi, double* freq_hz, double* fdot_hz_s);
+
+/* Phase change phi(t_end) - phi(t_start) inside one block (Eq. 4-1-1
+ * numerator) and the corresponding integration Doppler [rad/s]. */
+int pt_total_phase(const pt_fit* fit, double t_start, double t_end, double* dphi_rad,
+                   double* f_int_rad_s);
+
+/* Phase connection over nblk contiguous blocks (Eq. 4-1-2): Phi_total =
+ * sum_i [phi_i(t_right) - phi_i(t_left)], count interval T_c = sum of the
+ * block lengths, F_int_dop = Phi_total / T_c [rad/s]. */
+int pt_connect_phase(const pt_fit* fits, int nblk, double* phi_total_rad, double* f_int_rad_s);
+
+/* Line-of-sight acceleration at time t from phi''(t) (Eq. 4-2-1):
+ * a = phi'' c / (2 pi f_carrier) one-way (three_way == 0) or
+ * a = phi'' c / (4 pi M2 f_carrier) three-way; f_carrier [Hz] is the sky
+ * carrier, M2 the transponder ratio. */
+int pt_los_accel(const pt_fit* fit, double t, double f_carrier_hz, double M2, int three_way,
+                 double* a_m_s2);
+
+/* ---- instrumentation ---- */
+
+/* Turn per-kernel timing of the objective kernel on (1) or off (0).  While
+ * on, fits launch kernels one by one (no graph replay) and bracket every
+ * objective launch with HIP events on the fit's stream. */
+int pt_ctx_set_timing(pt_ctx* ctx, int on);
+
+/* Launch count and summed duration [ms] of objective-kernel launches timed
+ * since timing was turned on. */
+int pt_ctx_kernel_stats(pt_ctx* ctx, int64_t* launches, double* total_ms);
+
+/* Time `reps` back-to-back launches of the objective kernel alone on the
+ * population `pop` (device, P x 6) with HIP events on hip_stream; *avg_ms
+ * receives the mean duration of one launch.  Same kernel, geometry and
+ * grid as a fit of this block uses. */
+int pt_time_objective(pt_ctx* ctx, const pt_block* block, const double* pop, int P, int precision, int reps,
+                      void* hip_stream, double* avg_ms);
+
+/* Chunk geometry of the objective kernel used for blocks of n samples and
+ * population P in the given precision: samples per lane and candidates per
+ * workgroup (the autotuner's choice once it has run). */
+int pt_ctx_get_tile(pt_ctx* ctx, int64_t n, int P, int precision, int* samples_per_lane,
+                    int* cand_per_group);
+
+/* Force a chunk geometry for every later fit in this context (0, 0 = back
+ * to the tuned/default choice).  Supported samples_per_lane: 4, 8, 16, 32;
+ * cand_per_group: 1, 2, 4, 5, 8. */
+int pt_ctx_set_tile(pt_ctx* ctx, int samples_per_lane, int cand_per_group);
+
+/* Time every supported geometry on a block of n samples and population P
+ * (synthetic data on the device) and remember the fastest for that size
+ * class and precision.  best_spl / best_cpg may be NULL. */
+int pt_ctx_autotune(pt_ctx* ctx, int64_t n, int P, int precision, void* hip_stream,
+                    int* best_spl, int* best_cpg);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PHASETRACK_H */

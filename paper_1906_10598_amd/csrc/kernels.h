@@ -1,0 +1,507 @@
+// kernels.h -- HIP kernels of the phase-tracking fit (gfx950).
+//
+// Objective (Eq. 2-2-4 over the model of Eq. 2-2-2): one launch evaluates
+// every candidate of every block in the launch against every sample.  The
+// grid is a list of work units; a unit is (block, sample tile, candidate
+// group).  A workgroup of 256 lanes owns one tile of 256 * S samples: each
+// lane holds S consecutive samples in registers (read from HBM once per
+// generation and reused for all candidates of the group) and loops over
+// the group's candidates.  For each (lane, candidate) an FP64 anchor -- the
+// phase in turns and its Taylor coefficients at the lane's first sample,
+// with a compensated product for the large linear term -- turns the
+// per-sample phase into a 3-FMA local polynomial in the literal offset j.
+// Lane partial sums go to LDS; each wave then reduces one candidate's 256
+// partials with a fixed-order DPP/shuffle butterfly and writes one FP64
+// partial per (candidate, tile).  Units are remapped so that all candidate
+// groups of a tile run on the same XCD (consecutive workgroup ids are
+// dealt round-robin to the eight XCDs, each with its own L2).
+//
+// DE (Sec. 1.2, Table 4, DE/rand/1/bin): one workgroup per block sums the
+// partials in tile order, applies selection, finds the best member, runs
+// the stop rule and draws the next trial population from Philox; every
+// decision is taken on the device so a fit needs no host round trip.
+#pragma once
+
+#include <type_traits>
+
+#include "device.h"
+
+namespace pt {
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ int find_block(const BlockDesc* __restrict__ descs, int nblk, int unit) {
+    int lo = 0, hi = nblk - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (descs[mid].unit_begin <= unit) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Turn-domain coefficients of one candidate (see device.h).
+struct Cand {
+    double a0, a1, a2, a3, A, Ad;  // Ad = Adot / fs: amplitude slope per sample
+};
+
+__device__ __forceinline__ Cand make_cand(const double* __restrict__ x, double fs) {
+    Cand c;
+    const double t = x[1] * 0.15915494309189533577;  // phi0 / (2 pi)
+    c.a0 = t - rint(t);
+    c.a1 = x[2] / fs;
+    c.a2 = x[3] / (2.0 * fs * fs);
+    c.a3 = x[4] / (6.0 * fs * fs * fs);
+    c.A = x[0];
+    c.Ad = x[5] / fs;
+    return c;
+}
+
+// Phase (turns) and its Taylor coefficients at sample offset m0: anchor
+// b0 = frac(Phi(m0)) and Phi(m0 + j) = b0 + j (b1 + j (b2 + j b3)).  The
+// product a1 m0 (up to ~1e5 turns) is split exactly with an FMA so b0 keeps
+// ~1e-16 turns; m0^2 is exact for |m0| < 2^26.
+struct Anchor {
+    double b0, b1, b2, b3;
+};
+
+__device__ __forceinline__ Anchor make_anchor(const Cand& c, double m0) {
+    Anchor a;
+    double p = c.a1 * m0;
+    const double e = __fma_rn(c.a1, m0, -p);
+    p -= rint(p);
+    const double mm = m0 * m0;
+    double q = __fma_rn(c.a3, m0, c.a2) * mm;
+    q -= rint(q);
+    double b0 = (c.a0 + p) + (q + e);
+    a.b0 = b0 - rint(b0);
+    const double t3 = 3.0 * c.a3;
+    a.b2 = __fma_rn(t3, m0, c.a2);
+    a.b1 = __fma_rn(__fma_rn(t3, m0, 2.0 * c.a2), m0, c.a1);
+    a.b3 = c.a3;
+    return a;
+}
+
+// ---------------------------------------------------------------------------
+// FP64 lane accumulation over S samples for one candidate.
+// ---------------------------------------------------------------------------
+template <int S, bool TAIL, bool SLOPE>
+__device__ __forceinline__ double lane_chi2_f64(const double (&sv)[S], const Anchor& an, double amp0,
+                                                double ad, int valid) {
+    double acc = 0.0;
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+        const double jj = (double)j;
+        const double ph = (j == 0) ? an.b0
+                                   : __fma_rn(__fma_rn(__fma_rn(an.b3, jj, an.b2), jj, an.b1), jj, an.b0);
+        const double r = ph - rint(ph);
+        const double cv = cos_turns64(r * r);
+        const double amp = SLOPE ? __fma_rn(ad, jj, amp0) : amp0;
+        const double rho = __fma_rn(-amp, cv, sv[j]);
+        if (TAIL) {
+            if (j < valid) acc = __fma_rn(rho, rho, acc);
+        } else {
+            acc = __fma_rn(rho, rho, acc);
+        }
+    }
+    return acc;
+}
+
+// ---------------------------------------------------------------------------
+// Mixed precision lane accumulation: FP64 anchor, FP32 local offset.
+// The linear part j * b1 is split: b1h keeps 18 significant bits so that
+// j * b1h is exact in FP32 for j < 64 and its fractional part is exact; the
+// remainder b0 + j (b1l + j (b2 + j b3)) is small-magnitude FP32.  cos, the
+// residual and the lane sum are FP32.
+// ---------------------------------------------------------------------------
+template <int S, bool TAIL, bool SLOPE>
+__device__ __forceinline__ float lane_chi2_mixed(const float (&sv)[S], const Anchor& an, double amp0,
+                                                 double ad, int valid) {
+    const float b1h = __int_as_float(__float_as_int((float)an.b1) & ~63);
+    const float b1l = (float)(an.b1 - (double)b1h);
+    const float b0 = (float)an.b0;
+    const float b2 = (float)an.b2;
+    const float b3 = (float)an.b3;
+    const float A = (float)amp0;
+    const float Ad = (float)ad;
+    float acc = 0.0f;
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+        const float jj = (float)j;
+        float ph;
+        if (j == 0) {
+            ph = b0;
+        } else {
+            float lin = jj * b1h;
+            lin -= rintf(lin);
+            const float sm = __fmaf_rn(__fmaf_rn(__fmaf_rn(b3, jj, b2), jj, b1l), jj, b0);
+            ph = lin + sm;
+        }
+        const float r = ph - rintf(ph);
+        const float cv = cos_turns32(r * r);
+        const float amp = SLOPE ? __fmaf_rn(Ad, jj, A) : A;
+        const float rho = __fmaf_rn(-amp, cv, sv[j]);
+        if (TAIL) {
+            if (j < valid) acc = __fmaf_rn(rho, rho, acc);
+        } else {
+            acc = __fmaf_rn(rho, rho, acc);
+        }
+    }
+    return acc;
+}
+
+// ---------------------------------------------------------------------------
+// Objective kernel.  T: sample type; S: samples per lane; CPG: candidates
+// per workgroup; MIXED: precision mode; SLOPE: amplitude slope active.
+// Writes partials[cand * ntiles + tile] for every (tile, cand).
+// ---------------------------------------------------------------------------
+template <typename T, int S, int CPG, bool MIXED, bool SLOPE>
+__global__ __launch_bounds__(kThreads) void k_objective(const BlockDesc* __restrict__ descs, int nblk,
+                                                        int total_units) {
+    const int nwg = gridDim.x;  // multiple of 8
+    const int bid = blockIdx.x;
+    const int unit = (bid & 7) * (nwg >> 3) + (bid >> 3);
+    if (unit >= total_units) return;
+    const BlockDesc* __restrict__ d = descs + find_block(descs, nblk, unit);
+    if (d->st != nullptr && d->st->done) return;
+
+    const int local = unit - d->unit_begin;
+    const int tile = local / d->ngroups;
+    const int group = local - tile * d->ngroups;
+    const int cbase = group * CPG;
+    const int ncand = min(CPG, d->P - cbase);
+    const int tid = threadIdx.x;
+
+    __shared__ Cand cs[CPG];
+    __shared__ double red[CPG][kThreads];
+
+    if (tid < ncand) cs[tid] = make_cand(d->trial + (size_t)(cbase + tid) * kStride, d->fs);
+
+    const int64_t n = d->n;
+    const int64_t tile0 = (int64_t)tile * (kThreads * S);
+    const int64_t n0 = tile0 + (int64_t)tid * S;
+    const bool full = tile0 + kThreads * S <= n;
+    const T* __restrict__ sp = static_cast<const T*>(d->samples);
+    using V = typename std::conditional<MIXED, float, double>::type;
+    V sv[S];
+    int valid = S;
+    if (full) {
+#pragma unroll
+        for (int j = 0; j < S; ++j) sv[j] = (V)sp[n0 + j];
+    } else {
+        const int64_t rem = n - n0;
+        valid = rem <= 0 ? 0 : (rem >= S ? S : (int)rem);
+#pragma unroll
+        for (int j = 0; j < S; ++j) sv[j] = j < valid ? (V)sp[n0 + j] : (V)0;
+    }
+    const double m0 = (double)n0 - d->ref;
+    __syncthreads();
+
+    for (int c = 0; c < ncand; ++c) {
+        const Cand cc = cs[c];
+        const Anchor an = make_anchor(cc, m0);
+        const double amp0 = SLOPE ? __fma_rn(cc.Ad, m0, cc.A) : cc.A;
+        double acc;
+        if constexpr (MIXED) {
+            acc = full ? (double)lane_chi2_mixed<S, false, SLOPE>(sv, an, amp0, cc.Ad, valid)
+                       : (double)lane_chi2_mixed<S, true, SLOPE>(sv, an, amp0, cc.Ad, valid);
+        } else {
+            acc = full ? lane_chi2_f64<S, false, SLOPE>(sv, an, amp0, cc.Ad, valid)
+                       : lane_chi2_f64<S, true, SLOPE>(sv, an, amp0, cc.Ad, valid);
+        }
+        red[c][tid] = acc;
+    }
+    __syncthreads();
+
+    const int wave = tid >> 6, lane = tid & 63;
+    for (int c = wave; c < ncand; c += kThreads / 64) {
+        double v = ((red[c][lane] + red[c][lane + 64]) + red[c][lane + 128]) + red[c][lane + 192];
+        v = wave_sum(v);
+        if (lane == 0) d->partials[(size_t)(cbase + c) * d->ntiles + tile] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Objective of every candidate from its tile partials, by the whole
+// workgroup (NT = blockDim.x threads): k = max(1, NT / P) threads per
+// candidate each sum a strided subset of the tiles in a fixed order, then
+// thread c adds its candidate's k subtotals in order.  The order depends
+// only on (P, NT, ntiles), so every caller with the same geometry gets
+// bit-identical sums.  red: NT doubles of LDS.  Returns the objective of
+// candidate threadIdx.x (meaningful for threadIdx.x < P) after a barrier.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double reduce_partials(const BlockDesc* __restrict__ d, double* red) {
+    const int P = d->P, T = d->ntiles, NT = blockDim.x, t = threadIdx.x;
+    const int k = NT >= P ? NT / P : 1;
+    if (t < P * k) {
+        const int c = t / k, part = t - c * k;
+        const double* __restrict__ pr = d->partials + (size_t)c * T;
+        double s = 0.0;
+        int tt = part;
+        // issue four independent loads per step; add them in tile order
+        for (; tt + 3 * k < T; tt += 4 * k) {
+            const double v0 = pr[tt], v1 = pr[tt + k], v2 = pr[tt + 2 * k], v3 = pr[tt + 3 * k];
+            s = (((s + v0) + v1) + v2) + v3;
+        }
+        for (; tt < T; tt += k) s += pr[tt];
+        red[t] = s;
+    }
+    __syncthreads();
+    double tot = 0.0;
+    if (t < P) {
+        for (int q = 0; q < k; ++q) tot += red[t * k + q];
+    }
+    return tot;
+}
+
+// out[p] = objective of candidate p (bare evaluation, no DE state); one
+// workgroup of the DE step's size, NT doubles of dynamic LDS.
+__global__ void k_reduce_out(const BlockDesc* __restrict__ descs, double* __restrict__ out) {
+    extern __shared__ double red[];
+    const BlockDesc* d = descs;
+    const double v = reduce_partials(d, red);
+    if ((int)threadIdx.x < d->P) out[threadIdx.x] = v;
+}
+
+// ---------------------------------------------------------------------------
+// DE: initial population (generation 0), one workgroup per block.
+// x_j = lo_j + u (hi_j - lo_j), u = (w + 1/2) / 2^32 from the INIT stream.
+// ---------------------------------------------------------------------------
+__global__ void k_de_init(const BlockDesc* __restrict__ descs) {
+    const BlockDesc* d = descs + blockIdx.x;
+    const int i = threadIdx.x;
+    if (i < d->P) {
+        double x[kStride];
+#pragma unroll
+        for (int j = 0; j < kSlots; ++j) x[j] = d->lo[j];
+        x[6] = 0.0;
+        x[7] = 0.0;
+        U4 w{0, 0, 0, 0};
+        for (int a = 0; a < d->D; ++a) {
+            if ((a & 3) == 0) w = draw4(d->seed, d->stream, (uint32_t)i, 0u, kTagInit, (uint32_t)(a >> 2));
+            const double u = unit_from(word(w, a & 3));
+            const int j = d->act[a];
+            x[j] = __fma_rn(u, d->hi[j] - d->lo[j], d->lo[j]);
+        }
+        double* pr = d->pop + (size_t)i * kStride;
+        double* tr = d->trial + (size_t)i * kStride;
+#pragma unroll
+        for (int j = 0; j < kStride; ++j) {
+            pr[j] = x[j];
+            tr[j] = x[j];
+        }
+    }
+    if (i == 0) {
+        DeState s;
+        s.gen = 0;
+        s.done = 0;
+        s.flags = 0;
+        s.best = 0;
+        s.best_f = __builtin_inf();
+        s.err = 0;
+        s.pad = 0;
+        *d->st = s;
+    }
+}
+
+// (f, index) pair order of the argmin: smaller objective, then smaller index.
+__device__ __forceinline__ bool better(double fa, int ia, double fb, int ib) {
+    return ib >= 0 && (ia < 0 || fb < fa || (fb == fa && ib < ia));
+}
+
+// ---------------------------------------------------------------------------
+// DE: one generation step per block (blockDim = NT >= P, power of two).
+//   1. f(trial_i) = sum of tile partials (reduce_partials)
+//   2. selection: x_i <- trial_i iff f(trial_i) <= f(x_i)  (gen 0: accept)
+//   3. best = argmin, lowest index on ties; hist[g] = best value
+//   4. stop rule: VTR, window rule, generation cap
+//   5. trial_i of generation g + 1: r1, r2, r3 distinct and != i, jrand,
+//      v = x_r1 + F (x_r2 - x_r3) with the half-way bound rule, binomial
+//      crossover with rate CR and the forced coordinate jrand.
+// Member rows and the state are fetched before the reduction so their
+// latency overlaps it.  Dynamic LDS: P * kSlots + 2 NT doubles + NT ints.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_de_step(const BlockDesc* __restrict__ descs) {
+    const BlockDesc* __restrict__ d = descs + blockIdx.x;
+    DeState* st = d->st;
+    extern __shared__ double lds[];
+    const int P = d->P, NT = blockDim.x, i = threadIdx.x;
+    double* xs = lds;                              // P x kSlots
+    double* red = xs + (size_t)P * kSlots;         // NT
+    double* fr = red + NT;                         // NT
+    int* ix = reinterpret_cast<int*>(fr + NT);     // NT
+    __shared__ int s_done, s_gen, s_stop;
+    __shared__ double s_old;
+
+    double tr[kSlots], po[kSlots], fo = 0.0;
+    if (i < P) {
+        const double* a = d->trial + (size_t)i * kStride;
+        const double* b = d->pop + (size_t)i * kStride;
+#pragma unroll
+        for (int j = 0; j < kSlots; ++j) {
+            tr[j] = a[j];
+            po[j] = b[j];
+        }
+        fo = d->fpop[i];
+    }
+    if (i == 0) {
+        const int g0 = st->gen;
+        s_done = st->done;
+        s_gen = g0;
+        s_old = (d->rel_tol > 0.0 && d->window > 0 && g0 >= d->window) ? d->hist[g0 - d->window] : 0.0;
+    }
+    const double ft = reduce_partials(d, red);  // contains a barrier
+    if (s_done) return;
+    const int g = s_gen;
+
+    // selection (generation 0 accepts the initial population)
+    double fsel = __builtin_inf();
+    if (i < P) {
+        const bool take = g == 0 || ft <= fo;
+        double* prow = d->pop + (size_t)i * kStride;
+#pragma unroll
+        for (int j = 0; j < kSlots; ++j) {
+            const double v = take ? tr[j] : po[j];
+            xs[i * kSlots + j] = v;
+            if (take) prow[j] = v;
+        }
+        fsel = take ? ft : fo;
+        if (take) d->fpop[i] = ft;
+    }
+
+    // argmin, lowest index on ties
+    int best;
+    double bf;
+    if (P <= 64) {
+        if (i < 64) {
+            double f = fsel;
+            int id = i < P ? i : -1;
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) {
+                const double fo2 = __shfl_xor(f, off, 64);
+                const int io2 = __shfl_xor(id, off, 64);
+                if (better(f, id, fo2, io2)) {
+                    f = fo2;
+                    id = io2;
+                }
+            }
+            if (i == 0) {
+                fr[0] = f;
+                ix[0] = id;
+            }
+        }
+        __syncthreads();
+    } else {
+        fr[i] = fsel;
+        ix[i] = i < P ? i : -1;
+        __syncthreads();
+        for (int off = NT >> 1; off > 0; off >>= 1) {
+            if (i < off && better(fr[i], ix[i], fr[i + off], ix[i + off])) {
+                fr[i] = fr[i + off];
+                ix[i] = ix[i + off];
+            }
+            __syncthreads();
+        }
+    }
+    best = ix[0];
+    bf = fr[0];
+
+    if (i == 0) {
+        d->hist[g] = bf;
+        int flags = 0;
+        if (bf <= d->vtr) flags |= 4;  // PT_FLAG_VTR
+        if (d->rel_tol > 0.0 && d->window > 0 && g >= d->window && s_old - bf <= d->rel_tol * bf)
+            flags |= 1;  // PT_FLAG_CONVERGED
+        if (!flags && g >= d->max_gens) flags |= 2;  // PT_FLAG_MAXGEN
+        st->best = best;
+        st->best_f = bf;
+        if (flags) {
+            st->flags = flags;
+            st->done = 1;
+        } else {
+            st->gen = g + 1;
+        }
+        s_stop = flags != 0;
+    }
+    __syncthreads();
+    if (s_stop || i >= P) return;
+
+    // trial vector of member i for generation g + 1
+    const uint32_t gn = (uint32_t)(g + 1);
+    const U4 w = draw4(d->seed, d->stream, (uint32_t)i, gn, kTagMut, 0u);
+    int r1 = index_from(w.x, P - 1);
+    if (r1 >= i) ++r1;
+    const int lo2 = min(i, r1), hi2 = max(i, r1);
+    int r2 = index_from(w.y, P - 2);
+    if (r2 >= lo2) ++r2;
+    if (r2 >= hi2) ++r2;
+    int e0 = i, e1 = r1, e2 = r2, t;
+    if (e0 > e1) { t = e0; e0 = e1; e1 = t; }
+    if (e1 > e2) { t = e1; e1 = e2; e2 = t; }
+    if (e0 > e1) { t = e0; e0 = e1; e1 = t; }
+    int r3 = index_from(w.z, P - 3);
+    if (r3 >= e0) ++r3;
+    if (r3 >= e1) ++r3;
+    if (r3 >= e2) ++r3;
+    const int jr = index_from(w.w, d->D);
+
+    double y[kStride];
+#pragma unroll
+    for (int j = 0; j < kSlots; ++j) y[j] = xs[i * kSlots + j];
+    y[6] = 0.0;
+    y[7] = 0.0;
+    U4 u{0, 0, 0, 0};
+    for (int a = 0; a < d->D; ++a) {
+        if ((a & 3) == 0) u = draw4(d->seed, d->stream, (uint32_t)i, gn, kTagXover, (uint32_t)(a >> 2));
+        const double U = unit_from(word(u, a & 3));
+        const int j = d->act[a];
+        const double x1 = xs[r1 * kSlots + j];
+        double v = __fma_rn(d->F, xs[r2 * kSlots + j] - xs[r3 * kSlots + j], x1);
+        if (v < d->lo[j]) v = (d->lo[j] + x1) * 0.5;
+        if (v > d->hi[j]) v = (d->hi[j] + x1) * 0.5;
+        if (U < d->CR || a == jr) y[j] = v;
+    }
+    double* trow = d->trial + (size_t)i * kStride;
+#pragma unroll
+    for (int j = 0; j < kStride; ++j) trow[j] = y[j];
+}
+
+// ---------------------------------------------------------------------------
+// Final record of each block: best member, objective, generations, flags
+// (adds AT_BOUND: an active non-phase coordinate within 1e-6 of its box
+// width from a bound).
+// ---------------------------------------------------------------------------
+struct FitRecord {
+    double x[kSlots];
+    double f;
+    int gens;
+    int flags;
+};
+
+__global__ void k_finalize(const BlockDesc* __restrict__ descs, FitRecord* __restrict__ out) {
+    const BlockDesc* d = descs + blockIdx.x;
+    if (threadIdx.x != 0) return;
+    const DeState s = *d->st;
+    FitRecord r;
+    const double* xb = d->pop + (size_t)s.best * kStride;
+    int flags = s.flags;
+    for (int j = 0; j < kSlots; ++j) r.x[j] = xb[j];
+    for (int a = 0; a < d->D; ++a) {
+        const int j = d->act[a];
+        if (j == 1) continue;
+        const double w = d->hi[j] - d->lo[j];
+        if (xb[j] - d->lo[j] <= 1e-6 * w || d->hi[j] - xb[j] <= 1e-6 * w) flags |= 8;
+    }
+    r.f = s.best_f;
+    r.gens = s.gen;
+    r.flags = flags;
+    out[blockIdx.x] = r;
+}
+
+}  // namespace pt

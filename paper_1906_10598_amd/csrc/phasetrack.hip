@@ -1,0 +1,871 @@
+// phasetrack.hip -- host runtime and C ABI of libphasetrack.so (gfx950).
+//
+// The runtime owns device buffers per context, plans the objective grid of
+// a launch (units of (block, sample tile, candidate group)), captures chunks
+// of DE generations into HIP graphs and replays them, and turns the final
+// device records into the per-block output of the paper's Appendix 1.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/phasetrack.h"
+#include "kernels.h"
+
+using namespace pt;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                         \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess) return fail(PT_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr int kChunk = 50;  // generations per captured graph
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t cap = 0;
+    int ensure(size_t bytes) {
+        if (bytes <= cap) return PT_OK;
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        cap = 0;
+        size_t want = std::max(bytes, (size_t)256);
+        if (hipMalloc(&p, want) != hipSuccess) {
+            p = nullptr;
+            return fail(PT_ENOMEM, "hipMalloc(%zu bytes) failed", want);
+        }
+        cap = want;
+        return PT_OK;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        cap = 0;
+    }
+};
+
+struct PinBuf {
+    void* p = nullptr;
+    size_t cap = 0;
+    int ensure(size_t bytes) {
+        if (bytes <= cap) return PT_OK;
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        cap = 0;
+        size_t want = std::max(bytes, (size_t)4096);
+        if (hipHostMalloc(&p, want, hipHostMallocDefault) != hipSuccess) {
+            p = nullptr;
+            return fail(PT_ENOMEM, "hipHostMalloc(%zu bytes) failed", want);
+        }
+        cap = want;
+        return PT_OK;
+    }
+    void release() {
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        cap = 0;
+    }
+};
+
+struct Geometry {
+    int spl;  // samples per lane
+    int cpg;  // candidates per workgroup
+};
+
+const int kSpl[] = {4, 8, 16, 32};
+const int kCpg[] = {1, 2, 4, 8};
+
+bool spl_ok(int s) { return s == 4 || s == 8 || s == 16 || s == 32; }
+bool cpg_ok(int c) { return c == 1 || c == 2 || c == 4 || c == 8; }
+
+int size_class(int64_t n) {
+    int c = 0;
+    while (n > 1) {
+        n >>= 1;
+        ++c;
+    }
+    return c;  // floor(log2 n)
+}
+
+// ----------------------------------------------------------------- launchers
+using ObjKernel = void (*)(const BlockDesc*, int, int);
+
+template <typename T, int S, int C>
+ObjKernel pick_mode(bool mixed, bool slope) {
+    if (mixed) return slope ? k_objective<T, S, C, true, true> : k_objective<T, S, C, true, false>;
+    return slope ? k_objective<T, S, C, false, true> : k_objective<T, S, C, false, false>;
+}
+
+template <typename T, int S>
+ObjKernel pick_cpg(int cpg, bool mixed, bool slope) {
+    switch (cpg) {
+        case 1: return pick_mode<T, S, 1>(mixed, slope);
+        case 2: return pick_mode<T, S, 2>(mixed, slope);
+        case 4: return pick_mode<T, S, 4>(mixed, slope);
+        default: return pick_mode<T, S, 8>(mixed, slope);
+    }
+}
+
+template <typename T>
+ObjKernel pick_spl(Geometry g, bool mixed, bool slope) {
+    switch (g.spl) {
+        case 4: return pick_cpg<T, 4>(g.cpg, mixed, slope);
+        case 8: return pick_cpg<T, 8>(g.cpg, mixed, slope);
+        case 16: return pick_cpg<T, 16>(g.cpg, mixed, slope);
+        default: return pick_cpg<T, 32>(g.cpg, mixed, slope);
+    }
+}
+
+ObjKernel objective_kernel(int dtype, Geometry g, bool mixed, bool slope) {
+    return dtype == PT_F64 ? pick_spl<double>(g, mixed, slope) : pick_spl<float>(g, mixed, slope);
+}
+
+unsigned pow2_at_least(int v) {
+    unsigned p = 256;
+    while ((int)p < v) p <<= 1;
+    return p;
+}
+
+// Launch plan of one fit / batch.
+struct Plan {
+    int nblk = 0;
+    int P = 0;
+    int dtype = PT_F32;
+    bool mixed = false;
+    bool slope = false;
+    Geometry geo{16, 4};
+    int total_units = 0;
+    int grid = 0;          // objective workgroups (multiple of 8)
+    unsigned de_threads = 64;
+    size_t de_lds = 0;
+    int max_gens = 0;
+    bool window = false;
+};
+
+}  // namespace
+
+// ------------------------------------------------------------------ context
+struct pt_ctx {
+    int device = 0;
+    int ncu = 0;
+    hipStream_t cap_stream = nullptr;
+    DevBuf desc, pop, trial, fpop, partials, hist, state, rec, staging, eval_pop, scratch;
+    PinBuf hdesc, hrec, hstate;
+    // last fit (for pt_last_population / pt_last_history)
+    int last_nblk = 0, last_P = 0, last_maxg = 0;
+    std::vector<int> last_gens;
+    // timing
+    bool timing = false;
+    std::vector<hipEvent_t> ev_free;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;
+    int64_t launches = 0;
+    double total_ms = 0.0;
+    // geometry
+    Geometry forced{0, 0};
+    std::map<std::tuple<int, int, int>, Geometry> tuned;  // (size class, P, mixed)
+    // graph cache
+    struct GraphKey {
+        void* desc;
+        int nblk, grid, total_units, spl, cpg, dtype, mixed, slope;
+        unsigned de_threads;
+        size_t de_lds;
+        int iters;
+        bool operator<(const GraphKey& o) const {
+            return std::tie(desc, nblk, grid, total_units, spl, cpg, dtype, mixed, slope, de_threads, de_lds,
+                            iters) < std::tie(o.desc, o.nblk, o.grid, o.total_units, o.spl, o.cpg, o.dtype,
+                                              o.mixed, o.slope, o.de_threads, o.de_lds, o.iters);
+        }
+    };
+    std::map<GraphKey, hipGraphExec_t> graphs;
+
+    void drop_graphs() {
+        for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+        graphs.clear();
+    }
+};
+
+namespace {
+
+Geometry default_geometry(int64_t n, int P) {
+    // Prefer long lane chunks and many candidates per workgroup (amortises the
+    // FP64 anchor and the reduction) while keeping >= ~1000 workgroups.
+    Geometry best{4, 1};
+    double best_score = -1;
+    for (int s : kSpl) {
+        for (int c : kCpg) {
+            const int64_t tiles = (n + 256LL * s - 1) / (256LL * s);
+            const int64_t groups = (P + c - 1) / c;
+            const int64_t units = tiles * groups;
+            const double waste = (double)(groups * c - P) / (groups * c);
+            double score = (double)s * c * (1.0 - waste);
+            if (units < 1024) score *= (double)units / 1024.0;
+            if (score > best_score) {
+                best_score = score;
+                best = {s, c};
+            }
+        }
+    }
+    return best;
+}
+
+Geometry choose_geometry(pt_ctx* ctx, int64_t n, int P, bool mixed) {
+    if (ctx->forced.spl) return ctx->forced;
+    auto it = ctx->tuned.find(std::make_tuple(size_class(n), P, (int)mixed));
+    if (it != ctx->tuned.end()) return it->second;
+    return default_geometry(n, P);
+}
+
+int check_block(const pt_block* b, int idx) {
+    if (!b) return fail(PT_EINVAL, "block %d: null", idx);
+    if (!b->samples) return fail(PT_EINVAL, "block %d: samples is null", idx);
+    if (b->n < 8) return fail(PT_EINVAL, "block %d: n = %lld < 8", idx, (long long)b->n);
+    if (b->n > (int64_t)1 << 31) return fail(PT_EINVAL, "block %d: n = %lld exceeds 2^31", idx, (long long)b->n);
+    if (b->dtype != PT_F32 && b->dtype != PT_F64) return fail(PT_EINVAL, "block %d: dtype %d", idx, b->dtype);
+    if (!(b->fs > 0) || !std::isfinite(b->fs)) return fail(PT_EINVAL, "block %d: fs must be > 0", idx);
+    if (!std::isnan(b->ref) && !std::isfinite(b->ref)) return fail(PT_EINVAL, "block %d: ref not finite", idx);
+    if (!std::isnan(b->ref) && std::fabs(b->ref) > 4.0 * (double)b->n)
+        return fail(PT_EINVAL, "block %d: |ref| > 4 n", idx);
+    int D = 0;
+    for (int j = 0; j < PT_NSLOT; ++j) {
+        if (!std::isfinite(b->box.lo[j]) || !std::isfinite(b->box.hi[j]))
+            return fail(PT_EINVAL, "block %d: box slot %d not finite", idx, j);
+        if (b->box.lo[j] > b->box.hi[j]) return fail(PT_EINVAL, "block %d: box slot %d has lo > hi", idx, j);
+        if (b->box.lo[j] < b->box.hi[j]) ++D;
+    }
+    if (D == 0) return fail(PT_EINVAL, "block %d: every box slot is fixed", idx);
+    return PT_OK;
+}
+
+int check_de(const pt_de_settings* de) {
+    if (!de) return fail(PT_EINVAL, "DE settings are null");
+    if (de->pop < 4 || de->pop > PT_MAX_POP) return fail(PT_EINVAL, "pop = %d outside [4, %d]", de->pop, PT_MAX_POP);
+    if (de->max_gens < 0 || de->max_gens > 10000000) return fail(PT_EINVAL, "max_gens = %d", de->max_gens);
+    if (!(de->F > 0 && de->F <= 2)) return fail(PT_EINVAL, "F must be in (0, 2]");
+    if (!(de->CR >= 0 && de->CR <= 1)) return fail(PT_EINVAL, "CR must be in [0, 1]");
+    if (de->rel_tol > 0 && de->window < 1) return fail(PT_EINVAL, "window must be >= 1 with rel_tol > 0");
+    if (de->precision != PT_PREC_FP64 && de->precision != PT_PREC_MIXED)
+        return fail(PT_EINVAL, "precision %d", de->precision);
+    if (std::isnan(de->vtr)) return fail(PT_EINVAL, "vtr is NaN");
+    return PT_OK;
+}
+
+double block_ref(const pt_block* b) { return std::isnan(b->ref) ? 0.5 * (double)b->n : b->ref; }
+
+hipEvent_t take_event(pt_ctx* ctx) {
+    if (!ctx->ev_free.empty()) {
+        hipEvent_t e = ctx->ev_free.back();
+        ctx->ev_free.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+int collect_timing(pt_ctx* ctx) {
+    for (auto& pr : ctx->ev_pending) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, pr.first, pr.second));
+        ctx->total_ms += ms;
+        ctx->launches += 1;
+        ctx->ev_free.push_back(pr.first);
+        ctx->ev_free.push_back(pr.second);
+    }
+    ctx->ev_pending.clear();
+    return PT_OK;
+}
+
+// Enqueue one generation: objective over all units, then the DE step.
+int enqueue_generation(pt_ctx* ctx, const Plan& pl, ObjKernel obj, hipStream_t s, bool timed) {
+    const BlockDesc* d = static_cast<const BlockDesc*>(ctx->desc.p);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (timed) {
+        e0 = take_event(ctx);
+        e1 = take_event(ctx);
+        if (!e0 || !e1) return fail(PT_EDEVICE, "hipEventCreate failed");
+        HIPCHK(hipEventRecord(e0, s));
+    }
+    hipLaunchKernelGGL(obj, dim3(pl.grid), dim3(kThreads), 0, s, d, pl.nblk, pl.total_units);
+    HIPCHK(hipGetLastError());
+    if (timed) {
+        HIPCHK(hipEventRecord(e1, s));
+        ctx->ev_pending.push_back({e0, e1});
+    }
+    hipLaunchKernelGGL(k_de_step, dim3(pl.nblk), dim3(pl.de_threads), pl.de_lds, s, d);
+    HIPCHK(hipGetLastError());
+    return PT_OK;
+}
+
+int get_graph(pt_ctx* ctx, const Plan& pl, ObjKernel obj, int iters, hipGraphExec_t* out) {
+    pt_ctx::GraphKey key{ctx->desc.p, pl.nblk, pl.grid, pl.total_units, pl.geo.spl, pl.geo.cpg, pl.dtype,
+                         (int)pl.mixed, (int)pl.slope, pl.de_threads, pl.de_lds, iters};
+    auto it = ctx->graphs.find(key);
+    if (it != ctx->graphs.end()) {
+        *out = it->second;
+        return PT_OK;
+    }
+    hipStream_t cs = ctx->cap_stream;
+    HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    int rc = PT_OK;
+    for (int k = 0; k < iters && rc == PT_OK; ++k) rc = enqueue_generation(ctx, pl, obj, cs, false);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(cs, &g);
+    if (rc != PT_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(PT_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(PT_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    ctx->graphs[key] = ex;
+    *out = ex;
+    return PT_OK;
+}
+
+// Everything up to (and including) copying descriptors for nblk blocks.
+int prepare(pt_ctx* ctx, const pt_block* blocks, int nblk, const pt_de_settings* de, hipStream_t s, Plan* pl,
+            bool with_state) {
+    const int P = de->pop;
+    pl->nblk = nblk;
+    pl->P = P;
+    pl->dtype = blocks[0].dtype;
+    pl->mixed = de->precision == PT_PREC_MIXED;
+    pl->max_gens = de->max_gens;
+    pl->window = de->rel_tol > 0;
+    bool slope = false;
+    int64_t nmax = 0;
+    for (int b = 0; b < nblk; ++b) {
+        if (blocks[b].dtype != pl->dtype) return fail(PT_EINVAL, "block %d: all blocks need one dtype", b);
+        if (blocks[b].box.lo[5] != 0.0 || blocks[b].box.hi[5] != 0.0) slope = true;
+        nmax = std::max(nmax, blocks[b].n);
+    }
+    pl->slope = slope;
+    // geometry from the largest block (one kernel instance per launch)
+    pl->geo = choose_geometry(ctx, nmax, P, pl->mixed);
+    const int tile = kThreads * pl->geo.spl;
+    const int groups = (P + pl->geo.cpg - 1) / pl->geo.cpg;
+
+    // sizes
+    std::vector<int> ntiles(nblk);
+    size_t part_elems = 0, stage_bytes = 0;
+    int64_t units = 0;
+    for (int b = 0; b < nblk; ++b) {
+        ntiles[b] = (int)((blocks[b].n + tile - 1) / tile);
+        part_elems += (size_t)P * ntiles[b];
+        units += (int64_t)ntiles[b] * groups;
+        if (!blocks[b].on_device)
+            stage_bytes += ((size_t)blocks[b].n * (blocks[b].dtype == PT_F64 ? 8 : 4) + 255) & ~(size_t)255;
+    }
+    if (units > (int64_t)1 << 30) return fail(PT_EINVAL, "batch too large (%lld work units)", (long long)units);
+    pl->total_units = (int)units;
+    pl->grid = (int)((units + 7) / 8 * 8);
+    pl->de_threads = pow2_at_least(P);  // >= 256 and >= P: also fixes the partial-sum order
+    pl->de_lds = (size_t)P * kSlots * 8 + (size_t)pl->de_threads * (8 + 8 + 4);
+
+    const size_t rows = (size_t)nblk * P * kStride * sizeof(double);
+    int rc;
+    if ((rc = ctx->desc.ensure(sizeof(BlockDesc) * nblk)) || (rc = ctx->pop.ensure(rows)) ||
+        (rc = ctx->trial.ensure(rows)) || (rc = ctx->fpop.ensure((size_t)nblk * P * sizeof(double))) ||
+        (rc = ctx->partials.ensure(part_elems * sizeof(double))) ||
+        (rc = ctx->hist.ensure((size_t)nblk * (de->max_gens + 1) * sizeof(double))) ||
+        (rc = ctx->state.ensure((size_t)nblk * sizeof(DeState))) ||
+        (rc = ctx->rec.ensure((size_t)nblk * sizeof(FitRecord))) ||
+        (rc = ctx->hdesc.ensure(sizeof(BlockDesc) * nblk)) ||
+        (rc = ctx->hrec.ensure((size_t)nblk * sizeof(FitRecord))) ||
+        (rc = ctx->hstate.ensure((size_t)nblk * sizeof(DeState))))
+        return rc;
+    if (stage_bytes && (rc = ctx->staging.ensure(stage_bytes))) return rc;
+
+    // descriptor table (pinned host -> device)
+    BlockDesc* hd = static_cast<BlockDesc*>(ctx->hdesc.p);
+    double* pop = static_cast<double*>(ctx->pop.p);
+    double* trial = static_cast<double*>(ctx->trial.p);
+    double* fpop = static_cast<double*>(ctx->fpop.p);
+    double* part = static_cast<double*>(ctx->partials.p);
+    double* hist = static_cast<double*>(ctx->hist.p);
+    DeState* st = static_cast<DeState*>(ctx->state.p);
+    char* stage = static_cast<char*>(ctx->staging.p);
+    size_t part_off = 0, stage_off = 0;
+    int unit_off = 0;
+    for (int b = 0; b < nblk; ++b) {
+        const pt_block& B = blocks[b];
+        BlockDesc d;
+        std::memset(&d, 0, sizeof d);
+        const size_t bytes = (size_t)B.n * (B.dtype == PT_F64 ? 8 : 4);
+        if (B.on_device) {
+            d.samples = B.samples;
+        } else {
+            HIPCHK(hipMemcpyAsync(stage + stage_off, B.samples, bytes, hipMemcpyHostToDevice, s));
+            d.samples = stage + stage_off;
+            stage_off += (bytes + 255) & ~(size_t)255;
+        }
+        d.n = B.n;
+        d.fs = B.fs;
+        d.ref = block_ref(&B);
+        d.dtype = B.dtype;
+        d.P = P;
+        int D = 0;
+        for (int j = 0; j < kSlots; ++j) {
+            d.lo[j] = B.box.lo[j];
+            d.hi[j] = B.box.hi[j];
+            if (B.box.lo[j] < B.box.hi[j]) d.act[D++] = j;
+        }
+        d.D = D;
+        d.ntiles = ntiles[b];
+        d.ngroups = groups;
+        d.unit_begin = unit_off;
+        unit_off += ntiles[b] * groups;
+        d.window = de->window;
+        d.max_gens = de->max_gens;
+        d.F = de->F;
+        d.CR = de->CR;
+        d.vtr = de->vtr;
+        d.rel_tol = de->rel_tol;
+        d.seed = de->seed;
+        d.stream = B.stream;
+        d.pop = pop + (size_t)b * P * kStride;
+        d.trial = trial + (size_t)b * P * kStride;
+        d.fpop = fpop + (size_t)b * P;
+        d.partials = part + part_off;
+        part_off += (size_t)P * ntiles[b];
+        d.hist = hist + (size_t)b * (de->max_gens + 1);
+        d.st = with_state ? st + b : nullptr;
+        d.result = nullptr;
+        hd[b] = d;
+    }
+    HIPCHK(hipMemcpyAsync(ctx->desc.p, hd, sizeof(BlockDesc) * nblk, hipMemcpyHostToDevice, s));
+    return PT_OK;
+}
+
+void derive(pt_fit* f) {
+    const double two_pi = 2.0 * M_PI;
+    const double phi0 = f->coef[1], f0 = f->coef[2], f1 = f->coef[3], f2 = f->coef[4];
+    auto phase = [&](double t) { return phi0 + two_pi * (f0 * t + f1 * t * t / 2.0 + f2 * t * t * t / 6.0); };
+    auto freq = [&](double t) { return f0 + f1 * t + f2 * t * t / 2.0; };
+    auto wrap = [&](double p) {
+        double r = std::fmod(p, two_pi);
+        return r < 0 ? r + two_pi : r;
+    };
+    f->phase_centre = wrap(phi0);
+    f->phase_left = wrap(phase(f->t_left));
+    f->phase_right = wrap(phase(f->t_right));
+    f->freq_left = freq(f->t_left);
+    f->freq_right = freq(f->t_right);
+    f->total_phase = phase(f->t_right) - phase(f->t_left);
+}
+
+int run_fit(pt_ctx* ctx, const pt_block* blocks, int nblk, const pt_de_settings* de, void* hip_stream,
+            pt_fit* out) {
+    int rc = check_de(de);
+    if (rc) return rc;
+    if (nblk < 1 || nblk > 4096) return fail(PT_EINVAL, "nblk = %d outside [1, 4096]", nblk);
+    if (!out) return fail(PT_EINVAL, "out is null");
+    for (int b = 0; b < nblk; ++b)
+        if ((rc = check_block(&blocks[b], b))) return rc;
+    HIPCHK(hipSetDevice(ctx->device));
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    Plan pl;
+    void* old_desc = ctx->desc.p;
+    if ((rc = prepare(ctx, blocks, nblk, de, s, &pl, true))) return rc;
+    if (ctx->desc.p != old_desc) ctx->drop_graphs();
+    ObjKernel obj = objective_kernel(pl.dtype, pl.geo, pl.mixed, pl.slope);
+    const BlockDesc* d = static_cast<const BlockDesc*>(ctx->desc.p);
+
+    hipLaunchKernelGGL(k_de_init, dim3(nblk), dim3(pl.de_threads), 0, s, d);
+    HIPCHK(hipGetLastError());
+
+    const int iters = de->max_gens + 1;  // evaluation of gen 0 plus max_gens generations
+    if (ctx->timing) {
+        for (int k = 0; k < iters; ++k)
+            if ((rc = enqueue_generation(ctx, pl, obj, s, true))) return rc;
+    } else {
+        hipGraphExec_t ex = nullptr;
+        const int full = iters / kChunk, rem = iters % kChunk;
+        if (full && (rc = get_graph(ctx, pl, obj, kChunk, &ex))) return rc;
+        DeState* hst = static_cast<DeState*>(ctx->hstate.p);
+        for (int c = 0; c < full; ++c) {
+            HIPCHK(hipGraphLaunch(ex, s));
+            if (pl.window && c + 1 < full) {
+                // stop replaying once every block has met its stop rule
+                HIPCHK(hipMemcpyAsync(hst, ctx->state.p, sizeof(DeState) * nblk, hipMemcpyDeviceToHost, s));
+                HIPCHK(hipStreamSynchronize(s));
+                bool all = true;
+                for (int b = 0; b < nblk && all; ++b) all = hst[b].done != 0;
+                if (all) break;
+            }
+        }
+        for (int k = 0; k < rem; ++k)
+            if ((rc = enqueue_generation(ctx, pl, obj, s, false))) return rc;
+    }
+    hipLaunchKernelGGL(k_finalize, dim3(nblk), dim3(64), 0, s, d, static_cast<FitRecord*>(ctx->rec.p));
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(ctx->hrec.p, ctx->rec.p, sizeof(FitRecord) * nblk, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (ctx->timing && (rc = collect_timing(ctx))) return rc;
+
+    const FitRecord* r = static_cast<const FitRecord*>(ctx->hrec.p);
+    ctx->last_nblk = nblk;
+    ctx->last_P = de->pop;
+    ctx->last_maxg = de->max_gens;
+    ctx->last_gens.assign(nblk, 0);
+    for (int b = 0; b < nblk; ++b) {
+        pt_fit& f = out[b];
+        std::memset(&f, 0, sizeof f);
+        for (int j = 0; j < PT_NSLOT; ++j) f.coef[j] = r[b].x[j];
+        f.objective = r[b].f;
+        f.generations = r[b].gens;
+        f.flags = r[b].flags;
+        f.ref = block_ref(&blocks[b]);
+        f.t_left = (0.0 - f.ref) / blocks[b].fs;
+        f.t_right = ((double)blocks[b].n - f.ref) / blocks[b].fs;
+        derive(&f);
+        ctx->last_gens[b] = r[b].gens;
+    }
+    return PT_OK;
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+extern "C" {
+
+int pt_version(void) { return 10000; }
+
+const char* pt_last_error(void) { return g_err.c_str(); }
+
+int pt_ctx_create(int device, pt_ctx** out) {
+    if (!out) return fail(PT_EINVAL, "out is null");
+    *out = nullptr;
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count <= 0) return fail(PT_EDEVICE, "no HIP device available");
+    if (device < 0 || device >= count) return fail(PT_EDEVICE, "device %d not in [0, %d)", device, count);
+    HIPCHK(hipSetDevice(device));
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, device));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(PT_EDEVICE, "device %d is %s; this library is built for gfx950 only", device, prop.gcnArchName);
+    std::unique_ptr<pt_ctx> c(new (std::nothrow) pt_ctx());
+    if (!c) return fail(PT_ENOMEM, "out of host memory");
+    c->device = device;
+    c->ncu = prop.multiProcessorCount;
+    HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    *out = c.release();
+    return PT_OK;
+}
+
+void pt_ctx_destroy(pt_ctx* ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    ctx->drop_graphs();
+    for (auto e : ctx->ev_free) (void)hipEventDestroy(e);
+    for (auto& pr : ctx->ev_pending) {
+        (void)hipEventDestroy(pr.first);
+        (void)hipEventDestroy(pr.second);
+    }
+    DevBuf* bufs[] = {&ctx->desc,  &ctx->pop,  &ctx->trial, &ctx->fpop,    &ctx->partials, &ctx->hist,
+                      &ctx->state, &ctx->rec,  &ctx->staging, &ctx->eval_pop, &ctx->scratch};
+    for (DevBuf* b : bufs) b->release();
+    ctx->hdesc.release();
+    ctx->hrec.release();
+    ctx->hstate.release();
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    delete ctx;
+}
+
+int pt_fit_block(pt_ctx* ctx, const pt_block* block, const pt_de_settings* de, void* hip_stream, pt_fit* out) {
+    if (!ctx) return fail(PT_EINVAL, "ctx is null");
+    if (!block) return fail(PT_EINVAL, "block is null");
+    return run_fit(ctx, block, 1, de, hip_stream, out);
+}
+
+int pt_fit_batch(pt_ctx* ctx, const pt_block* blocks, int nblk, const pt_de_settings* de, void* hip_stream,
+                 pt_fit* out) {
+    if (!ctx) return fail(PT_EINVAL, "ctx is null");
+    if (!blocks) return fail(PT_EINVAL, "blocks is null");
+    return run_fit(ctx, blocks, nblk, de, hip_stream, out);
+}
+
+// Shared set-up of the bare objective entry points: descriptor of one block
+// without DE state, the caller's P x 6 rows copied into the stride-8 trial
+// rows, and the objective kernel of the chosen geometry.
+static int eval_setup(pt_ctx* ctx, const pt_block* block, const double* pop, int P, int precision, hipStream_t s,
+                      Plan* pl, ObjKernel* obj) {
+    int rc = check_block(block, 0);
+    if (rc) return rc;
+    if (!pop) return fail(PT_EINVAL, "pop is null");
+    if (P < 1 || P > PT_MAX_POP) return fail(PT_EINVAL, "P = %d outside [1, %d]", P, PT_MAX_POP);
+    if (precision != PT_PREC_FP64 && precision != PT_PREC_MIXED) return fail(PT_EINVAL, "precision %d", precision);
+    HIPCHK(hipSetDevice(ctx->device));
+    pt_de_settings de;
+    std::memset(&de, 0, sizeof de);
+    de.pop = P;
+    de.max_gens = 0;
+    de.F = 0.5;
+    de.CR = 0.5;
+    de.precision = precision;
+    void* old_desc = ctx->desc.p;
+    if ((rc = prepare(ctx, block, 1, &de, s, pl, false))) return rc;
+    if (ctx->desc.p != old_desc) ctx->drop_graphs();
+    const BlockDesc* hd = static_cast<const BlockDesc*>(ctx->hdesc.p);
+    HIPCHK(hipMemcpy2DAsync(hd[0].trial, kStride * sizeof(double), pop, PT_NSLOT * sizeof(double),
+                            PT_NSLOT * sizeof(double), P, hipMemcpyDeviceToDevice, s));
+    *obj = objective_kernel(pl->dtype, pl->geo, pl->mixed, pl->slope);
+    return PT_OK;
+}
+
+int pt_objective(pt_ctx* ctx, const pt_block* block, const double* pop, int P, int precision, void* hip_stream,
+                 double* out) {
+    if (!ctx) return fail(PT_EINVAL, "ctx is null");
+    if (!out) return fail(PT_EINVAL, "out is null");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    Plan pl;
+    ObjKernel obj = nullptr;
+    int rc = eval_setup(ctx, block, pop, P, precision, s, &pl, &obj);
+    if (rc) return rc;
+    const BlockDesc* d = static_cast<const BlockDesc*>(ctx->desc.p);
+    hipLaunchKernelGGL(obj, dim3(pl.grid), dim3(kThreads), 0, s, d, 1, pl.total_units);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(k_reduce_out, dim3(1), dim3(pl.de_threads), pl.de_threads * sizeof(double), s, d, out);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
+    return PT_OK;
+}
+
+int pt_time_objective(pt_ctx* ctx, const pt_block* block, const double* pop, int P, int precision, int reps,
+                      void* hip_stream, double* avg_ms) {
+    if (!ctx) return fail(PT_EINVAL, "ctx is null");
+    if (!avg_ms) return fail(PT_EINVAL, "avg_ms is null");
+    if (reps < 1 || reps > 100000) return fail(PT_EINVAL, "reps = %d outside [1, 100000]", reps);
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    Plan pl;
+    ObjKernel obj = nullptr;
+    int rc = eval_setup(ctx, block, pop, P, precision, s, &pl, &obj);
+    if (rc) return rc;
+    const BlockDesc* d = static_cast<const BlockDesc*>(ctx->desc.p);
+    hipLaunchKernelGGL(obj, dim3(pl.grid), dim3(kThreads), 0, s, d, 1, pl.total_units);  // warm
+    HIPCHK(hipGetLastError());
+    hipEvent_t e0 = take_event(ctx), e1 = take_event(ctx);
+    if (!e0 || !e1) return fail(PT_EDEVICE, "hipEventCreate failed");
+    HIPCHK(hipEventRecord(e0, s));
+    for (int r = 0; r < reps; ++r) hipLaunchKernelGGL(obj, dim3(pl.grid), dim3(kThreads), 0, s, d, 1, pl.total_units);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipEventRecord(e1, s));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    ctx->ev_free.push_back(e0);
+    ctx->ev_free.push_back(e1);
+    *avg_ms = (double)ms / reps;
+    return PT_OK;
+}
+
+int pt_last_population(pt_ctx* ctx, int index, double* pop_host, double* fpop_host, int P) {
+    if (!ctx) return fail(PT_EINVAL, "ctx is null");
+    if (index < 0 || index >= ctx->last_nblk) return fail(PT_EINVAL, "index %d outside the last fit", index);
+    if (P != ctx->last_P) return fail(PT_EINVAL, "P = %d, last fit used %d", P, ctx->last_P);
+    HIPCHK(hipSetDevice(ctx->device));
+    HIPCHK(hipDeviceSynchronize());
+    if (pop_host) {
+        const double* src = static_cast<const double*>(ctx->pop.p) + (size_t)index * P * kStride;
+        HIPCHK(hipMemcpy2D(pop_host, PT_NSLOT * sizeof(double), src, kStride * sizeof(double),
+                           PT_NSLOT * sizeof(double), P, hipMemcpyDeviceToHost));
+    }
+    if (fpop_host) {
+        const double* src = static_cast<const double*>(ctx->fpop.p) + (size_t)index * P;
+        HIPCHK(hipMemcpy(fpop_host, src, sizeof(double) * P, hipMemcpyDeviceToHost));
+    }
+    return PT_OK;
+}
+
+int pt_last_history(pt_ctx* ctx, int index, double* hist_host, int n, int* count) {
+    if (!ctx) return fail(PT_EINVAL, "ctx is null");
+    if (index < 0 || index >= ctx->last_nblk) return fail(PT_EINVAL, "index %d outside the last fit", index);
+    if (!hist_host || n < 0) return fail(PT_EINVAL, "hist_host is null or n < 0");
+    const int avail = ctx->last_gens[index] + 1;
+    const int k = std::min(n, avail);
+    HIPCHK(hipSetDevice(ctx->device));
+    HIPCHK(hipDeviceSynchronize());
+    const double* src = static_cast<const double*>(ctx->hist.p) + (size_t)index * (ctx->last_maxg + 1);
+    if (k) HIPCHK(hipMemcpy(hist_host, src, sizeof(double) * k, hipMemcpyDeviceToHost));
+    if (count) *count = k;
+    return PT_OK;
+}
+
+// ------------------------------------------------------ derived observables
+static double fit_phase(const pt_fit* f, double t) {
+    return f->coef[1] + 2.0 * M_PI * (f->coef[2] * t + f->coef[3] * t * t / 2.0 + f->coef[4] * t * t * t / 6.0);
+}
+
+int pt_phase(const pt_fit* fit, const double* t, int64_t n, double* phase, double* phase_mod2pi, double* freq_hz,
+             double* fdot_hz_s) {
+    if (!fit) return fail(PT_EINVAL, "fit is null");
+    if (n < 0 || (n > 0 && !t)) return fail(PT_EINVAL, "t is null or n < 0");
+    const double two_pi = 2.0 * M_PI;
+    for (int64_t k = 0; k < n; ++k) {
+        const double tk = t[k];
+        const double p = fit_phase(fit, tk);
+        if (phase) phase[k] = p;
+        if (phase_mod2pi) {
+            double r = std::fmod(p, two_pi);
+            phase_mod2pi[k] = r < 0 ? r + two_pi : r;
+        }
+        if (freq_hz) freq_hz[k] = fit->coef[2] + fit->coef[3] * tk + fit->coef[4] * tk * tk / 2.0;
+        if (fdot_hz_s) fdot_hz_s[k] = fit->coef[3] + fit->coef[4] * tk;
+    }
+    return PT_OK;
+}
+
+int pt_total_phase(const pt_fit* fit, double t_start, double t_end, double* dphi_rad, double* f_int_rad_s) {
+    if (!fit) return fail(PT_EINVAL, "fit is null");
+    if (!(t_end != t_start)) return fail(PT_EINVAL, "t_end must differ from t_start");
+    const double d = fit_phase(fit, t_end) - fit_phase(fit, t_start);
+    if (dphi_rad) *dphi_rad = d;
+    if (f_int_rad_s) *f_int_rad_s = d / (t_end - t_start);
+    return PT_OK;
+}
+
+int pt_connect_phase(const pt_fit* fits, int nblk, double* phi_total_rad, double* f_int_rad_s) {
+    if (!fits || nblk < 1) return fail(PT_EINVAL, "fits is null or nblk < 1");
+    double tot = 0.0, Tc = 0.0;
+    for (int b = 0; b < nblk; ++b) {
+        const pt_fit* f = &fits[b];
+        if (!(f->t_right > f->t_left)) return fail(PT_EINVAL, "fit %d: t_right <= t_left", b);
+        tot += fit_phase(f, f->t_right) - fit_phase(f, f->t_left);
+        Tc += f->t_right - f->t_left;
+    }
+    if (phi_total_rad) *phi_total_rad = tot;
+    if (f_int_rad_s) *f_int_rad_s = tot / Tc;
+    return PT_OK;
+}
+
+int pt_los_accel(const pt_fit* fit, double t, double f_carrier_hz, double M2, int three_way, double* a_m_s2) {
+    if (!fit || !a_m_s2) return fail(PT_EINVAL, "fit / a_m_s2 is null");
+    if (!(f_carrier_hz > 0)) return fail(PT_EINVAL, "f_carrier must be > 0");
+    if (three_way && !(M2 > 0)) return fail(PT_EINVAL, "M2 must be > 0 for three-way");
+    const double c = 299792458.0;
+    const double phi2 = 2.0 * M_PI * (fit->coef[3] + fit->coef[4] * t);  // rad/s^2
+    const double k = three_way ? 4.0 * M_PI * M2 * f_carrier_hz : 2.0 * M_PI * f_carrier_hz;
+    *a_m_s2 = phi2 * c / k;
+    return PT_OK;
+}
+
+// ------------------------------------------------------------ instrumentation
+int pt_ctx_set_timing(pt_ctx* ctx, int on) {
+    if (!ctx) return fail(PT_EINVAL, "ctx is null");
+    ctx->timing = on != 0;
+    ctx->launches = 0;
+    ctx->total_ms = 0.0;
+    return PT_OK;
+}
+
+int pt_ctx_kernel_stats(pt_ctx* ctx, int64_t* launches, double* total_ms) {
+    if (!ctx) return fail(PT_EINVAL, "ctx is null");
+    if (launches) *launches = ctx->launches;
+    if (total_ms) *total_ms = ctx->total_ms;
+    return PT_OK;
+}
+
+int pt_ctx_get_tile(pt_ctx* ctx, int64_t n, int P, int precision, int* spl, int* cpg) {
+    if (!ctx) return fail(PT_EINVAL, "ctx is null");
+    if (n < 1 || P < 1) return fail(PT_EINVAL, "n and P must be positive");
+    Geometry g = choose_geometry(ctx, n, P, precision == PT_PREC_MIXED);
+    if (spl) *spl = g.spl;
+    if (cpg) *cpg = g.cpg;
+    return PT_OK;
+}
+
+int pt_ctx_set_tile(pt_ctx* ctx, int spl, int cpg) {
+    if (!ctx) return fail(PT_EINVAL, "ctx is null");
+    if (spl == 0 && cpg == 0) {
+        ctx->forced = {0, 0};
+        return PT_OK;
+    }
+    if (!spl_ok(spl) || !cpg_ok(cpg)) return fail(PT_EINVAL, "unsupported geometry (%d, %d)", spl, cpg);
+    ctx->forced = {spl, cpg};
+    return PT_OK;
+}
+
+int pt_ctx_autotune(pt_ctx* ctx, int64_t n, int P, int precision, void* hip_stream, int* best_spl, int* best_cpg) {
+    if (!ctx) return fail(PT_EINVAL, "ctx is null");
+    if (n < 8 || n > ((int64_t)1 << 31) || P < 4 || P > PT_MAX_POP) return fail(PT_EINVAL, "n or P out of range");
+    if (precision != PT_PREC_FP64 && precision != PT_PREC_MIXED) return fail(PT_EINVAL, "precision %d", precision);
+    HIPCHK(hipSetDevice(ctx->device));
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    // synthetic FP32 block and population (values only matter for timing)
+    int rc;
+    if ((rc = ctx->scratch.ensure((size_t)n * 4))) return rc;
+    if ((rc = ctx->eval_pop.ensure((size_t)P * PT_NSLOT * 8 + (size_t)P * 8))) return rc;
+    std::vector<float> hs((size_t)std::min<int64_t>(n, 1 << 20));
+    for (size_t k = 0; k < hs.size(); ++k) hs[k] = (float)std::cos(0.37 * (double)k);
+    for (int64_t off = 0; off < n; off += (int64_t)hs.size()) {
+        const size_t cnt = (size_t)std::min<int64_t>((int64_t)hs.size(), n - off);
+        HIPCHK(hipMemcpy(static_cast<float*>(ctx->scratch.p) + off, hs.data(), cnt * 4, hipMemcpyHostToDevice));
+    }
+    std::vector<double> hp((size_t)P * PT_NSLOT);
+    for (int p = 0; p < P; ++p) {
+        double* x = &hp[(size_t)p * PT_NSLOT];
+        x[0] = 1.0; x[1] = 0.1 * p; x[2] = 1000.0 + p; x[3] = 0.5; x[4] = 0.01; x[5] = 0.0;
+    }
+    HIPCHK(hipMemcpy(ctx->eval_pop.p, hp.data(), hp.size() * 8, hipMemcpyHostToDevice));
+    pt_block b;
+    std::memset(&b, 0, sizeof b);
+    b.samples = ctx->scratch.p;
+    b.n = n;
+    b.dtype = PT_F32;
+    b.on_device = 1;
+    b.fs = 50000.0;
+    b.ref = NAN;
+    for (int j = 0; j < PT_NSLOT; ++j) { b.box.lo[j] = 0; b.box.hi[j] = 1; }
+    b.box.hi[5] = 0;
+    const Geometry saved = ctx->forced;
+    Geometry best{0, 0};
+    double best_ms = 1e30;
+    for (int spl : kSpl) {
+        for (int cpg : kCpg) {
+            ctx->forced = {spl, cpg};
+            double ms = 0.0;
+            rc = pt_time_objective(ctx, &b, static_cast<const double*>(ctx->eval_pop.p), P, precision, 20, s, &ms);
+            if (rc) break;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = {spl, cpg};
+            }
+        }
+        if (rc) break;
+    }
+    ctx->forced = saved;
+    if (rc) return rc;
+    ctx->tuned[std::make_tuple(size_class(n), P, precision == PT_PREC_MIXED ? 1 : 0)] = best;
+    if (best_spl) *best_spl = best.spl;
+    if (best_cpg) *best_cpg = best.cpg;
+    return PT_OK;
+}
+
+}  // extern "C"

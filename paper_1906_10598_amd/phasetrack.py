@@ -1,0 +1,353 @@
+"""ctypes binding of libphasetrack.so (the C ABI declared in include/phasetrack.h).
+
+Argument marshalling only: every step of the fit runs in the library's HIP
+kernels.  The entry points keep the C names (``pt_fit_block`` ...);
+:class:`Context` adds a little convenience for torch tensors (device memory
+and the current HIP stream come from torch, nothing else does).
+
+Loading fails loudly when the library has not been built: there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from typing import Optional, Sequence
+
+NSLOT = 6
+MAX_POP = 1024
+PT_OK, PT_EINVAL, PT_ENOMEM, PT_EDEVICE, PT_EBUSY, PT_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+PT_F32, PT_F64 = 0, 1
+PT_PREC_FP64, PT_PREC_MIXED = 0, 1
+PT_FLAG_CONVERGED, PT_FLAG_MAXGEN, PT_FLAG_VTR, PT_FLAG_AT_BOUND = 1, 2, 4, 8
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libphasetrack.so")
+
+
+class PtError(RuntimeError):
+    def __init__(self, code: int, where: str, msg: str):
+        super().__init__(f"{where} failed ({code}): {msg}")
+        self.code = code
+
+
+class pt_box(ctypes.Structure):
+    _fields_ = [("lo", ctypes.c_double * NSLOT), ("hi", ctypes.c_double * NSLOT)]
+
+
+class pt_de_settings(ctypes.Structure):
+    _fields_ = [
+        ("pop", ctypes.c_int32),
+        ("max_gens", ctypes.c_int32),
+        ("F", ctypes.c_double),
+        ("CR", ctypes.c_double),
+        ("seed", ctypes.c_uint64),
+        ("vtr", ctypes.c_double),
+        ("rel_tol", ctypes.c_double),
+        ("window", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+    ]
+
+
+class pt_block(ctypes.Structure):
+    _fields_ = [
+        ("samples", ctypes.c_void_p),
+        ("n", ctypes.c_int64),
+        ("dtype", ctypes.c_int32),
+        ("on_device", ctypes.c_int32),
+        ("fs", ctypes.c_double),
+        ("ref", ctypes.c_double),
+        ("stream", ctypes.c_uint64),
+        ("box", pt_box),
+    ]
+
+
+class pt_fit(ctypes.Structure):
+    _fields_ = [
+        ("coef", ctypes.c_double * NSLOT),
+        ("objective", ctypes.c_double),
+        ("generations", ctypes.c_int32),
+        ("flags", ctypes.c_int32),
+        ("ref", ctypes.c_double),
+        ("t_left", ctypes.c_double),
+        ("t_right", ctypes.c_double),
+        ("phase_centre", ctypes.c_double),
+        ("phase_left", ctypes.c_double),
+        ("phase_right", ctypes.c_double),
+        ("freq_left", ctypes.c_double),
+        ("freq_right", ctypes.c_double),
+        ("total_phase", ctypes.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        return {k: (list(getattr(self, k)) if k == "coef" else getattr(self, k)) for k, _ in self._fields_}
+
+
+_lib = None
+_DP = ctypes.POINTER(ctypes.c_double)
+_VP = ctypes.c_void_p
+_CTX = ctypes.c_void_p
+
+
+def _signatures(L):
+    i32, i64 = ctypes.c_int, ctypes.c_int64
+    spec = {
+        "pt_version": ([], i32),
+        "pt_last_error": ([], ctypes.c_char_p),
+        "pt_ctx_create": ([i32, ctypes.POINTER(_CTX)], i32),
+        "pt_ctx_destroy": ([_CTX], None),
+        "pt_fit_block": ([_CTX, ctypes.POINTER(pt_block), ctypes.POINTER(pt_de_settings), _VP,
+                          ctypes.POINTER(pt_fit)], i32),
+        "pt_fit_batch": ([_CTX, ctypes.POINTER(pt_block), i32, ctypes.POINTER(pt_de_settings), _VP,
+                          ctypes.POINTER(pt_fit)], i32),
+        "pt_objective": ([_CTX, ctypes.POINTER(pt_block), _VP, i32, i32, _VP, _VP], i32),
+        "pt_last_population": ([_CTX, i32, _DP, _DP, i32], i32),
+        "pt_last_history": ([_CTX, i32, _DP, i32, ctypes.POINTER(i32)], i32),
+        "pt_phase": ([ctypes.POINTER(pt_fit), _DP, i64, _DP, _DP, _DP, _DP], i32),
+        "pt_total_phase": ([ctypes.POINTER(pt_fit), ctypes.c_double, ctypes.c_double, _DP, _DP], i32),
+        "pt_connect_phase": ([ctypes.POINTER(pt_fit), i32, _DP, _DP], i32),
+        "pt_los_accel": ([ctypes.POINTER(pt_fit), ctypes.c_double, ctypes.c_double, ctypes.c_double, i32,
+                          _DP], i32),
+        "pt_time_objective": ([_CTX, ctypes.POINTER(pt_block), _VP, i32, i32, i32, _VP, _DP], i32),
+        "pt_ctx_set_timing": ([_CTX, i32], i32),
+        "pt_ctx_kernel_stats": ([_CTX, ctypes.POINTER(i64), _DP], i32),
+        "pt_ctx_get_tile": ([_CTX, i64, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)], i32),
+        "pt_ctx_set_tile": ([_CTX, i32, i32], i32),
+        "pt_ctx_autotune": ([_CTX, i64, i32, i32, _VP, ctypes.POINTER(i32), ctypes.POINTER(i32)], i32),
+    }
+    for name, (args, res) in spec.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+
+
+def lib():
+    """The loaded library.  Raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"libphasetrack.so is not built ({LIB_PATH}); run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        _signatures(L)
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, where: str):
+    if rc != PT_OK:
+        raise PtError(rc, where, lib().pt_last_error().decode(errors="replace"))
+
+
+# ----------------------------------------------------------------- C names
+def pt_version() -> int:
+    return lib().pt_version()
+
+
+def pt_last_error() -> str:
+    return lib().pt_last_error().decode(errors="replace")
+
+
+def pt_ctx_create(device: int = 0):
+    h = _CTX()
+    _check(lib().pt_ctx_create(device, ctypes.byref(h)), "pt_ctx_create")
+    return h
+
+
+def pt_ctx_destroy(ctx) -> None:
+    lib().pt_ctx_destroy(ctx)
+
+
+def pt_fit_block(ctx, block: pt_block, de: pt_de_settings, stream=None) -> pt_fit:
+    out = pt_fit()
+    _check(lib().pt_fit_block(ctx, ctypes.byref(block), ctypes.byref(de), stream, ctypes.byref(out)),
+           "pt_fit_block")
+    return out
+
+
+def pt_fit_batch(ctx, blocks: Sequence[pt_block], de: pt_de_settings, stream=None):
+    arr = (pt_block * len(blocks))(*blocks)
+    out = (pt_fit * len(blocks))()
+    _check(lib().pt_fit_batch(ctx, arr, len(blocks), ctypes.byref(de), stream, out), "pt_fit_batch")
+    return list(out)
+
+
+def pt_objective(ctx, block: pt_block, pop_ptr: int, P: int, precision: int, out_ptr: int, stream=None):
+    _check(lib().pt_objective(ctx, ctypes.byref(block), pop_ptr, P, precision, stream, out_ptr), "pt_objective")
+
+
+def pt_last_population(ctx, index: int, P: int):
+    import numpy as np
+
+    pop = np.empty((P, NSLOT))
+    f = np.empty(P)
+    _check(lib().pt_last_population(ctx, index, pop.ctypes.data_as(_DP), f.ctypes.data_as(_DP), P),
+           "pt_last_population")
+    return pop, f
+
+
+def pt_last_history(ctx, index: int, n: int):
+    import numpy as np
+
+    h = np.empty(max(n, 1))
+    cnt = ctypes.c_int()
+    _check(lib().pt_last_history(ctx, index, h.ctypes.data_as(_DP), n, ctypes.byref(cnt)), "pt_last_history")
+    return h[: cnt.value]
+
+
+def pt_phase(fit: pt_fit, t):
+    import numpy as np
+
+    t = np.ascontiguousarray(t, dtype=np.float64)
+    outs = [np.empty_like(t) for _ in range(4)]
+    _check(lib().pt_phase(ctypes.byref(fit), t.ctypes.data_as(_DP), t.size,
+                          *[o.ctypes.data_as(_DP) for o in outs]), "pt_phase")
+    return tuple(outs)
+
+
+def pt_total_phase(fit: pt_fit, t_start: float, t_end: float):
+    d, f = ctypes.c_double(), ctypes.c_double()
+    _check(lib().pt_total_phase(ctypes.byref(fit), t_start, t_end, ctypes.byref(d), ctypes.byref(f)),
+           "pt_total_phase")
+    return d.value, f.value
+
+
+def pt_connect_phase(fits: Sequence[pt_fit]):
+    arr = (pt_fit * len(fits))(*fits)
+    d, f = ctypes.c_double(), ctypes.c_double()
+    _check(lib().pt_connect_phase(arr, len(fits), ctypes.byref(d), ctypes.byref(f)), "pt_connect_phase")
+    return d.value, f.value
+
+
+def pt_los_accel(fit: pt_fit, t: float, f_carrier_hz: float, M2: float = 1.0, three_way: bool = False):
+    a = ctypes.c_double()
+    _check(lib().pt_los_accel(ctypes.byref(fit), t, f_carrier_hz, M2, int(three_way), ctypes.byref(a)),
+           "pt_los_accel")
+    return a.value
+
+
+def pt_time_objective(ctx, block: pt_block, pop_ptr: int, P: int, precision: int, reps: int, stream=None):
+    ms = ctypes.c_double()
+    _check(lib().pt_time_objective(ctx, ctypes.byref(block), pop_ptr, P, precision, reps, stream,
+                                   ctypes.byref(ms)), "pt_time_objective")
+    return ms.value
+
+
+def pt_ctx_set_timing(ctx, on: bool):
+    _check(lib().pt_ctx_set_timing(ctx, int(on)), "pt_ctx_set_timing")
+
+
+def pt_ctx_kernel_stats(ctx):
+    n, ms = ctypes.c_int64(), ctypes.c_double()
+    _check(lib().pt_ctx_kernel_stats(ctx, ctypes.byref(n), ctypes.byref(ms)), "pt_ctx_kernel_stats")
+    return n.value, ms.value
+
+
+def pt_ctx_get_tile(ctx, n: int, P: int, precision: int):
+    a, b = ctypes.c_int(), ctypes.c_int()
+    _check(lib().pt_ctx_get_tile(ctx, n, P, precision, ctypes.byref(a), ctypes.byref(b)), "pt_ctx_get_tile")
+    return a.value, b.value
+
+
+def pt_ctx_set_tile(ctx, spl: int, cpg: int):
+    _check(lib().pt_ctx_set_tile(ctx, spl, cpg), "pt_ctx_set_tile")
+
+
+def pt_ctx_autotune(ctx, n: int, P: int, precision: int, stream=None):
+    a, b = ctypes.c_int(), ctypes.c_int()
+    _check(lib().pt_ctx_autotune(ctx, n, P, precision, stream, ctypes.byref(a), ctypes.byref(b)),
+           "pt_ctx_autotune")
+    return a.value, b.value
+
+
+# ------------------------------------------------------------ conveniences
+def make_box(lo, hi) -> pt_box:
+    b = pt_box()
+    for j in range(NSLOT):
+        b.lo[j] = float(lo[j])
+        b.hi[j] = float(hi[j])
+    return b
+
+
+def make_settings(pop: int, max_gens: int, F: float = 0.5, CR: float = 0.9, seed: int = 0,
+                  vtr: float = -math.inf, rel_tol: float = 0.0, window: int = 0,
+                  precision: int = PT_PREC_FP64) -> pt_de_settings:
+    s = pt_de_settings()
+    s.pop, s.max_gens, s.F, s.CR, s.seed = pop, max_gens, F, CR, seed
+    s.vtr, s.rel_tol, s.window, s.precision = vtr, rel_tol, window, precision
+    return s
+
+
+def make_block(samples, fs: float, lo, hi, ref: Optional[float] = None, stream: int = 0) -> pt_block:
+    """pt_block over a torch tensor on the GPU (FP32 or FP64, contiguous)."""
+    import torch
+
+    if not isinstance(samples, torch.Tensor):
+        raise TypeError("samples must be a torch tensor")
+    if not samples.is_contiguous():
+        raise ValueError("samples must be contiguous")
+    if samples.dtype == torch.float32:
+        dt = PT_F32
+    elif samples.dtype == torch.float64:
+        dt = PT_F64
+    else:
+        raise TypeError("samples must be float32 or float64")
+    b = pt_block()
+    b.samples = samples.data_ptr()
+    b.n = samples.numel()
+    b.dtype = dt
+    b.on_device = 1 if samples.is_cuda else 0
+    b.fs = float(fs)
+    b.ref = float("nan") if ref is None else float(ref)
+    b.stream = int(stream)
+    b.box = make_box(lo, hi)
+    b._samples = samples  # the block only holds a raw pointer: keep the tensor alive with it
+    return b
+
+
+def current_stream():
+    import torch
+
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Context:
+    """Owning wrapper of a pt_ctx handle."""
+
+    def __init__(self, device: int = 0):
+        self.handle = pt_ctx_create(device)
+        self.device = device
+
+    def close(self):
+        if self.handle is not None:
+            pt_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def fit_block(self, block: pt_block, de: pt_de_settings) -> pt_fit:
+        return pt_fit_block(self.handle, block, de, current_stream())
+
+    def fit_batch(self, blocks, de: pt_de_settings):
+        return pt_fit_batch(self.handle, blocks, de, current_stream())
+
+    def objective(self, block: pt_block, pop, precision: int = PT_PREC_FP64):
+        """chi^2 of each row of ``pop`` (torch FP64 tensor P x 6 on the GPU)."""
+        import torch
+
+        pop = pop.contiguous()
+        if pop.dtype != torch.float64 or pop.dim() != 2 or pop.shape[1] != NSLOT or not pop.is_cuda:
+            raise ValueError("pop must be a CUDA float64 tensor of shape (P, 6)")
+        out = torch.empty(pop.shape[0], dtype=torch.float64, device=pop.device)
+        pt_objective(self.handle, block, pop.data_ptr(), pop.shape[0], precision, out.data_ptr(),
+                     current_stream())
+        return out

@@ -1,0 +1,87 @@
+"""Shared helpers of the GPU tests (device context, tensors, tolerances)."""
+import math
+
+import numpy as np
+
+import synth
+from paper_1906_10598_amd import phasetrack as ptk
+
+_CTX = None
+
+
+def ctx():
+    global _CTX
+    if _CTX is None:
+        _CTX = ptk.Context(0)
+    return _CTX
+
+
+def to_dev(a):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def block_of(b: synth.Block, samples_dev, ref=None, stream=None, lo=None, hi=None):
+    return ptk.make_block(samples_dev, b.fs, b.lo if lo is None else lo, b.hi if hi is None else hi,
+                          ref=b.ref if ref is None else ref, stream=b.stream if stream is None else stream)
+
+
+def settings_of(b: synth.Block, gens=None, precision=ptk.PT_PREC_FP64, **kw):
+    de = b.de
+    args = dict(pop=de.pop, max_gens=de.max_gens if gens is None else gens, F=de.F, CR=de.CR, seed=de.seed,
+                vtr=de.vtr, rel_tol=de.rel_tol, window=de.window, precision=precision)
+    args.update(kw)
+    return ptk.make_settings(**args)
+
+
+def phase_rounding_bound(s, pop, fs, ref):
+    """Largest change of chi^2 that FP64 rounding of the phase can cause:
+    each side forms phi with an error of a few ulp of |phi| <= phi_max, which
+    moves every residual by at most A * eps_phi, so chi^2 moves by at most
+    2 sum|rho| A eps_phi <= 2 sqrt(n chi^2) A eps_phi."""
+    n = np.asarray(s).size
+    tmax = max(abs(ref), abs(n - 1 - ref)) / fs
+    pop = np.atleast_2d(pop)
+    phi_max = (np.abs(pop[:, 1]) + 2 * math.pi * (np.abs(pop[:, 2]) * tmax + np.abs(pop[:, 3]) * tmax ** 2 / 2
+                                                  + np.abs(pop[:, 4]) * tmax ** 3 / 6))
+    return 8 * phi_max * 2.0 ** -53, np.abs(pop[:, 0])
+
+
+def assert_chi2_close(got, ref, n, amp=1.0, rel=1e-10, eps_phi=None):
+    """Objectives agree within `rel` relative.  For noise-free data, where
+    chi^2 -> 0 and a relative error is undefined, pass eps_phi (per-candidate
+    phase rounding, see phase_rounding_bound): the bound becomes
+    2 sqrt(n chi^2) A eps_phi + n (1e-13 A)^2."""
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    amp = np.broadcast_to(np.asarray(amp, dtype=np.float64), ref.shape)
+    err = np.abs(got - ref)
+    tol = np.maximum(rel * np.abs(ref), n * (1e-13 * amp) ** 2)
+    if eps_phi is not None:
+        tol = np.maximum(tol, 2 * np.sqrt(n * np.abs(ref)) * amp * eps_phi + n * (1e-13 * amp) ** 2)
+    bad = np.nonzero(err > tol)[0]
+    assert bad.size == 0, (
+        f"{bad.size} objectives outside tolerance; worst rel err "
+        f"{float(np.max(err / np.maximum(np.abs(ref), 1e-300))):.3e} at {int(bad[0])}: "
+        f"gpu {got[bad[0]]!r} oracle {ref[bad[0]]!r} tol {tol[bad[0]]!r}")
+
+
+def random_population(rng, lo, hi, P, far=0):
+    """P members uniform in the box, plus `far` members well outside it."""
+    lo = np.asarray(lo, dtype=np.float64)
+    hi = np.asarray(hi, dtype=np.float64)
+    pop = lo + rng.random((P, 6)) * (hi - lo)
+    for k in range(min(far, P)):
+        w = hi - lo
+        pop[k] = lo + (rng.random(6) * 5 - 2) * np.where(w > 0, w, 1.0)
+        pop[k, 5] = 0.0 if hi[5] == lo[5] else pop[k, 5]
+    return pop
+
+
+def crlb_f0(n, fs, amp, sigma):
+    """Cramer-Rao bound on f0 [Hz] of a real sinusoid in white noise with the
+    time origin at the block centre and f0 the only unknown besides the
+    amplitude and phase: var = 2 sigma^2 / (A^2 (2 pi)^2 sum t^2), sum t^2 ~ n T^2 / 12."""
+    T = n / fs
+    return math.sqrt(6.0) * sigma / (math.pi * amp * T * math.sqrt(n))
