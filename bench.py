@@ -29,7 +29,7 @@ PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector (published, packed)
 # (3 FMA) + turn reduction (1) + r^2 (1) + cosine polynomial (degree 10 FP64
 # / degree 6 FP32, one FMA per degree) + residual FMA + square-accumulate FMA.
 FLOP_PER_PAIR = {"fp64": 6 + 1 + 1 + 20 + 2 + 2, "mixed": 6 + 1 + 1 + 12 + 2 + 2}
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "objective_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_objective_fp64_paper400k.md")
 KERNEL_SRC = [os.path.join(ROOT, "paper_1906_10598_amd", "csrc", f) for f in ("kernels.h", "device.h")]
 
 
@@ -39,6 +39,21 @@ def kernel_hash():
         with open(p, "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
+
+
+def read_traffic():
+    """HBM bytes per objective launch from the committed rocprofv3 summary,
+    or None when the kernel sources changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            for line in f:
+                if line.startswith("traffic:"):
+                    kv = dict(item.split("=", 1) for item in line.split()[1:])
+                    if kv.get("kernel_hash") == kernel_hash() and kv.get("workload") == "paper-400000-fp32":
+                        return float(kv["bytes_per_launch"])
+    except (OSError, ValueError, KeyError):
+        return None
+    return None
 
 
 def pct(xs, q):
@@ -86,9 +101,14 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--latency-fits", type=int, default=100, help="fits per path for p50/p99")
-    ap.add_argument("--cpu-gens", type=int, default=120, help="oracle generations in the CPU sample")
+    ap.add_argument("--cpu-gens", type=int, default=800, help="oracle generations in the CPU sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--tile", default="", help="force the objective geometry, e.g. 16,4")
+    ap.add_argument("--kernel-only", default="", choices=["", "fp64", "mixed"],
+                    help="profiling mode: one fit, then --reps back-to-back objective launches; "
+                         "also one 256 MiB device copy as the traffic-counter calibration")
+    ap.add_argument("--reps", type=int, default=200)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -110,11 +130,31 @@ def main():
     stream = ptk.current_stream()
 
     tiles = {}
+    if args.tile:
+        spl, cpg = (int(v) for v in args.tile.split(","))
+        ptk.pt_ctx_set_tile(ctx.handle, spl, cpg)
     for name, prec in (("fp64", ptk.PT_PREC_FP64), ("mixed", ptk.PT_PREC_MIXED)):
-        if not args.no_tune:
+        if not args.no_tune and not args.tile and not args.kernel_only:
             ptk.pt_ctx_autotune(ctx.handle, N, P, prec, stream)
         tiles[name] = ptk.pt_ctx_get_tile(ctx.handle, N, P, prec)
     print(f"# geometry (samples/lane, candidates/workgroup): {tiles}", file=sys.stderr, flush=True)
+
+    if args.kernel_only:
+        prec = ptk.PT_PREC_FP64 if args.kernel_only == "fp64" else ptk.PT_PREC_MIXED
+        ctx.fit_block(blk, ptk.make_settings(pop=P, max_gens=G, F=b.de.F, CR=b.de.CR, seed=b.de.seed,
+                                             precision=prec))
+        pop, _ = ptk.pt_last_population(ctx.handle, 0, P)
+        popd = torch.from_numpy(pop).cuda()
+        avg_ms = ptk.pt_time_objective(ctx.handle, blk, popd.data_ptr(), P, prec, args.reps, stream)
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.mul(src, 2.0, out=dst)  # calibration: reads 256 MiB, writes 256 MiB
+        torch.cuda.synchronize()
+        print(json.dumps({"kernel_only": args.kernel_only, "avg_launch_ms": avg_ms, "reps": args.reps,
+                          "geometry": tiles[args.kernel_only], "kernel_hash": kernel_hash(),
+                          "calibration_copy_bytes": 2 * src.numel() * 4}), flush=True)
+        ctx.close()
+        return
 
     def de(prec):
         return lambda k: ptk.make_settings(pop=P, max_gens=G, F=b.de.F, CR=b.de.CR, seed=b.de.seed + k,
@@ -169,15 +209,7 @@ def main():
         roof[name] = {"avg_launch_ms": avg_ms, "in_fit_event_ms": ms / max(nl, 1), "launches": nl,
                       "achieved": ach, "peak": peak}
 
-    traffic = None
-    if os.path.exists(TRAFFIC_FILE):
-        try:
-            with open(TRAFFIC_FILE) as f:
-                tr = json.load(f)
-            if tr.get("kernel_hash") == kernel_hash() and tr.get("workload") == "paper-400000-fp32":
-                traffic = tr.get("bytes_per_launch")
-        except (OSError, ValueError):
-            traffic = None
+    traffic = read_traffic()
 
     # ---- CPU oracle baseline (bounded sample of the same fit)
     cpu = None

@@ -231,6 +231,26 @@ int pt_connect_phase(const pt_fit* fits, int nblk, double* phi_total_rad, double
 int pt_los_accel(const pt_fit* fit, double t, double f_carrier_hz, double M2, int three_way,
                  double* a_m_s2);
 
+/* ---- launch strategy ---- */
+
+/* How a fit's generations are launched.
+ *   PT_LAUNCH_PERSISTENT: one cooperative grid runs every generation of
+ *     every block; workgroups keep their sample chunks in registers, and the
+ *     workgroup that completes a block's generation runs its DE step (no
+ *     grid-wide barrier, no per-generation launches).  Needs P <= 256 and a
+ *     grid that fits on the device at once.
+ *   PT_LAUNCH_GRAPH: per generation one objective launch and one DE-step
+ *     launch, replayed from captured HIP graphs of 50 generations.
+ *   PT_LAUNCH_AUTO (default): persistent when possible, else graph.
+ * Both give bit-identical results for the same geometry. */
+enum { PT_LAUNCH_AUTO = 0, PT_LAUNCH_GRAPH = 1, PT_LAUNCH_PERSISTENT = 2 };
+
+int pt_ctx_set_launch_mode(pt_ctx* ctx, int mode);
+
+/* Launch strategy the context's most recent fit used (PT_LAUNCH_GRAPH or
+ * PT_LAUNCH_PERSISTENT). */
+int pt_ctx_last_launch(pt_ctx* ctx, int* mode);
+
 /* ---- instrumentation ---- */
 
 /* Turn per-kernel timing of the objective kernel on (1) or off (0).  While

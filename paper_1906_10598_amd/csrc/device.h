@@ -29,8 +29,8 @@ struct DeState {
     int flags;     // PT_FLAG_* bits
     int best;      // index of the best member
     double best_f;
-    int err;       // nonzero: device-side inconsistency detected
-    int pad;
+    int arrive;    // persistent kernel: work units finished, all generations
+    int ready;     // persistent kernel: DE steps completed (trial of `ready` is set)
 };
 
 // Everything a kernel needs to know about one block of a launch.

@@ -89,28 +89,61 @@ __device__ __forceinline__ Anchor make_anchor(const Cand& c, double m0) {
 }
 
 // ---------------------------------------------------------------------------
-// FP64 lane accumulation over S samples for one candidate.
+// FP64 lane accumulation over S samples for one candidate.  The phase is
+// stepped with forward differences of the local cubic, Phi(j + 1) =
+// Phi(j) + d1(j), d1(j + 1) = d1(j) + d2(j), d2(j + 1) = d2(j) + 6 b3, with
+// d1(0) = b1 + b2 + b3 and d2(0) = 2 b2 + 6 b3; each step continues from the
+// exactly reduced phase r(j) = Phi(j) - rint(Phi(j)), so the running value
+// stays within one turn (rounding ~1e-16 turns per step, S <= 32 steps).
 // ---------------------------------------------------------------------------
 template <int S, bool TAIL, bool SLOPE>
 __device__ __forceinline__ double lane_chi2_f64(const double (&sv)[S], const Anchor& an, double amp0,
                                                 double ad, int valid) {
-    double acc = 0.0;
+    // Samples are processed in groups of IL: the phase recurrence runs
+    // through the group, then the IL cosine polynomials are evaluated in
+    // lockstep (IL independent FMA chains hide the FP64 FMA latency) and
+    // summed into IL accumulators that are combined at the end.
+    constexpr int IL = 4;
+    static_assert(S % IL == 0, "samples per lane must be a multiple of 4");
+    double acc[IL];
 #pragma unroll
-    for (int j = 0; j < S; ++j) {
-        const double jj = (double)j;
-        const double ph = (j == 0) ? an.b0
-                                   : __fma_rn(__fma_rn(__fma_rn(an.b3, jj, an.b2), jj, an.b1), jj, an.b0);
-        const double r = ph - rint(ph);
-        const double cv = cos_turns64(r * r);
-        const double amp = SLOPE ? __fma_rn(ad, jj, amp0) : amp0;
-        const double rho = __fma_rn(-amp, cv, sv[j]);
-        if (TAIL) {
-            if (j < valid) acc = __fma_rn(rho, rho, acc);
-        } else {
-            acc = __fma_rn(rho, rho, acc);
+    for (int q = 0; q < IL; ++q) acc[q] = 0.0;
+    double ph = an.b0;
+    double d1 = (an.b1 + an.b2) + an.b3;
+    double d2 = __fma_rn(6.0, an.b3, 2.0 * an.b2);
+    const double d3 = 6.0 * an.b3;
+#pragma unroll
+    for (int g = 0; g < S; g += IL) {
+        double u[IL], p[IL];
+#pragma unroll
+        for (int q = 0; q < IL; ++q) {
+            const double r = ph - rint(ph);
+            if (g + q + 1 < S) {
+                ph = r + d1;
+                d1 += d2;
+                d2 += d3;
+            }
+            u[q] = r * r;
+            p[q] = kCos64[0];
+        }
+#pragma unroll
+        for (int k = 1; k <= kCosDeg64; ++k) {
+#pragma unroll
+            for (int q = 0; q < IL; ++q) p[q] = __fma_rn(p[q], u[q], kCos64[k]);
+        }
+#pragma unroll
+        for (int q = 0; q < IL; ++q) {
+            const int j = g + q;
+            const double amp = SLOPE ? __fma_rn(ad, (double)j, amp0) : amp0;
+            const double rho = __fma_rn(-amp, p[q], sv[j]);
+            if (TAIL) {
+                if (j < valid) acc[q] = __fma_rn(rho, rho, acc[q]);
+            } else {
+                acc[q] = (g == 0) ? rho * rho : __fma_rn(rho, rho, acc[q]);
+            }
         }
     }
-    return acc;
+    return (acc[0] + acc[1]) + (acc[2] + acc[3]);
 }
 
 // ---------------------------------------------------------------------------
@@ -123,6 +156,8 @@ __device__ __forceinline__ double lane_chi2_f64(const double (&sv)[S], const Anc
 template <int S, bool TAIL, bool SLOPE>
 __device__ __forceinline__ float lane_chi2_mixed(const float (&sv)[S], const Anchor& an, double amp0,
                                                  double ad, int valid) {
+    constexpr int IL = 4;  // samples whose cosine chains run in lockstep
+    static_assert(S % IL == 0, "samples per lane must be a multiple of 4");
     const float b1h = __int_as_float(__float_as_int((float)an.b1) & ~63);
     const float b1l = (float)(an.b1 - (double)b1h);
     const float b0 = (float)an.b0;
@@ -130,67 +165,65 @@ __device__ __forceinline__ float lane_chi2_mixed(const float (&sv)[S], const Anc
     const float b3 = (float)an.b3;
     const float A = (float)amp0;
     const float Ad = (float)ad;
-    float acc = 0.0f;
+    float acc[IL];
 #pragma unroll
-    for (int j = 0; j < S; ++j) {
-        const float jj = (float)j;
-        float ph;
-        if (j == 0) {
-            ph = b0;
-        } else {
-            float lin = jj * b1h;
-            lin -= rintf(lin);
-            const float sm = __fmaf_rn(__fmaf_rn(__fmaf_rn(b3, jj, b2), jj, b1l), jj, b0);
-            ph = lin + sm;
+    for (int q = 0; q < IL; ++q) acc[q] = 0.0f;
+#pragma unroll
+    for (int g = 0; g < S; g += IL) {
+        float u[IL], p[IL];
+#pragma unroll
+        for (int q = 0; q < IL; ++q) {
+            const int j = g + q;
+            const float jj = (float)j;
+            float ph;
+            if (j == 0) {
+                ph = b0;
+            } else {
+                float lin = jj * b1h;  // exact: b1h has 18 significant bits, j < 64
+                lin -= rintf(lin);
+                const float sm = __fmaf_rn(__fmaf_rn(__fmaf_rn(b3, jj, b2), jj, b1l), jj, b0);
+                ph = lin + sm;
+            }
+            const float r = ph - rintf(ph);
+            u[q] = r * r;
+            p[q] = kCos32[0];
         }
-        const float r = ph - rintf(ph);
-        const float cv = cos_turns32(r * r);
-        const float amp = SLOPE ? __fmaf_rn(Ad, jj, A) : A;
-        const float rho = __fmaf_rn(-amp, cv, sv[j]);
-        if (TAIL) {
-            if (j < valid) acc = __fmaf_rn(rho, rho, acc);
-        } else {
-            acc = __fmaf_rn(rho, rho, acc);
+#pragma unroll
+        for (int k = 1; k <= kCosDeg32; ++k) {
+#pragma unroll
+            for (int q = 0; q < IL; ++q) p[q] = __fmaf_rn(p[q], u[q], kCos32[k]);
+        }
+#pragma unroll
+        for (int q = 0; q < IL; ++q) {
+            const int j = g + q;
+            const float amp = SLOPE ? __fmaf_rn(Ad, (float)j, A) : A;
+            const float rho = __fmaf_rn(-amp, p[q], sv[j]);
+            if (TAIL) {
+                if (j < valid) acc[q] = __fmaf_rn(rho, rho, acc[q]);
+            } else {
+                acc[q] = (g == 0) ? rho * rho : __fmaf_rn(rho, rho, acc[q]);
+            }
         }
     }
-    return acc;
+    return (acc[0] + acc[1]) + (acc[2] + acc[3]);
 }
 
 // ---------------------------------------------------------------------------
-// Objective kernel.  T: sample type; S: samples per lane; CPG: candidates
-// per workgroup; MIXED: precision mode; SLOPE: amplitude slope active.
-// Writes partials[cand * ntiles + tile] for every (tile, cand).
+// One work unit of the objective: the 256 * S samples of `tile` against the
+// CPG candidates of `group`.  Writes partials[cand * ntiles + tile].
+// T: sample type; S: samples per lane; CPG: candidates per workgroup;
+// MIXED: precision mode; SLOPE: amplitude slope active.  sv holds the
+// lane's samples (loaded by load_lane); cs / red are LDS scratch.
 // ---------------------------------------------------------------------------
-template <typename T, int S, int CPG, bool MIXED, bool SLOPE>
-__global__ __launch_bounds__(kThreads) void k_objective(const BlockDesc* __restrict__ descs, int nblk,
-                                                        int total_units) {
-    const int nwg = gridDim.x;  // multiple of 8
-    const int bid = blockIdx.x;
-    const int unit = (bid & 7) * (nwg >> 3) + (bid >> 3);
-    if (unit >= total_units) return;
-    const BlockDesc* __restrict__ d = descs + find_block(descs, nblk, unit);
-    if (d->st != nullptr && d->st->done) return;
-
-    const int local = unit - d->unit_begin;
-    const int tile = local / d->ngroups;
-    const int group = local - tile * d->ngroups;
-    const int cbase = group * CPG;
-    const int ncand = min(CPG, d->P - cbase);
-    const int tid = threadIdx.x;
-
-    __shared__ Cand cs[CPG];
-    __shared__ double red[CPG][kThreads];
-
-    if (tid < ncand) cs[tid] = make_cand(d->trial + (size_t)(cbase + tid) * kStride, d->fs);
-
+template <typename V, typename T, int S>
+__device__ __forceinline__ void load_lane(const BlockDesc* __restrict__ d, int tile, V (&sv)[S], bool& full,
+                                          int& valid) {
     const int64_t n = d->n;
     const int64_t tile0 = (int64_t)tile * (kThreads * S);
-    const int64_t n0 = tile0 + (int64_t)tid * S;
-    const bool full = tile0 + kThreads * S <= n;
+    const int64_t n0 = tile0 + (int64_t)threadIdx.x * S;
+    full = tile0 + kThreads * S <= n;
     const T* __restrict__ sp = static_cast<const T*>(d->samples);
-    using V = typename std::conditional<MIXED, float, double>::type;
-    V sv[S];
-    int valid = S;
+    valid = S;
     if (full) {
 #pragma unroll
         for (int j = 0; j < S; ++j) sv[j] = (V)sp[n0 + j];
@@ -200,7 +233,17 @@ __global__ __launch_bounds__(kThreads) void k_objective(const BlockDesc* __restr
 #pragma unroll
         for (int j = 0; j < S; ++j) sv[j] = j < valid ? (V)sp[n0 + j] : (V)0;
     }
-    const double m0 = (double)n0 - d->ref;
+}
+
+template <int S, int CPG, bool MIXED, bool SLOPE, typename V>
+__device__ __forceinline__ void objective_unit(const BlockDesc* __restrict__ d, int tile, int group,
+                                               const V (&sv)[S], bool full, int valid, Cand* cs,
+                                               double (*red)[kThreads]) {
+    const int cbase = group * CPG;
+    const int ncand = min(CPG, d->P - cbase);
+    const int tid = threadIdx.x;
+    if (tid < ncand) cs[tid] = make_cand(d->trial + (size_t)(cbase + tid) * kStride, d->fs);
+    const double m0 = (double)((int64_t)tile * (kThreads * S) + (int64_t)tid * S) - d->ref;
     __syncthreads();
 
     for (int c = 0; c < ncand; ++c) {
@@ -225,6 +268,31 @@ __global__ __launch_bounds__(kThreads) void k_objective(const BlockDesc* __restr
         v = wave_sum(v);
         if (lane == 0) d->partials[(size_t)(cbase + c) * d->ntiles + tile] = v;
     }
+}
+
+// Objective kernel: one work unit per workgroup.  Units are remapped so
+// that the candidate groups of a tile run on one XCD.
+template <typename T, int S, int CPG, bool MIXED, bool SLOPE>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_objective(
+    const BlockDesc* __restrict__ descs, int nblk, int total_units) {
+    const int nwg = gridDim.x;  // multiple of 8
+    const int bid = blockIdx.x;
+    const int unit = (bid & 7) * (nwg >> 3) + (bid >> 3);
+    if (unit >= total_units) return;
+    const BlockDesc* __restrict__ d = descs + find_block(descs, nblk, unit);
+    if (d->st != nullptr && d->st->done) return;
+    const int local = unit - d->unit_begin;
+    const int tile = local / d->ngroups;
+    const int group = local - tile * d->ngroups;
+
+    __shared__ Cand cs[CPG];
+    __shared__ double red[CPG][kThreads];
+    using V = typename std::conditional<MIXED, float, double>::type;
+    V sv[S];
+    bool full;
+    int valid;
+    load_lane<V, T, S>(d, tile, sv, full, valid);
+    objective_unit<S, CPG, MIXED, SLOPE>(d, tile, group, sv, full, valid, cs, red);
 }
 
 // ---------------------------------------------------------------------------
@@ -273,9 +341,10 @@ __global__ void k_reduce_out(const BlockDesc* __restrict__ descs, double* __rest
 // DE: initial population (generation 0), one workgroup per block.
 // x_j = lo_j + u (hi_j - lo_j), u = (w + 1/2) / 2^32 from the INIT stream.
 // ---------------------------------------------------------------------------
-__global__ void k_de_init(const BlockDesc* __restrict__ descs) {
+__global__ void k_de_init(const BlockDesc* __restrict__ descs, int* __restrict__ err) {
     const BlockDesc* d = descs + blockIdx.x;
     const int i = threadIdx.x;
+    if (err != nullptr && blockIdx.x == 0 && i == 0) *err = 0;
     if (i < d->P) {
         double x[kStride];
 #pragma unroll
@@ -304,8 +373,8 @@ __global__ void k_de_init(const BlockDesc* __restrict__ descs) {
         s.flags = 0;
         s.best = 0;
         s.best_f = __builtin_inf();
-        s.err = 0;
-        s.pad = 0;
+        s.arrive = 0;
+        s.ready = 0;
         *d->st = s;
     }
 }
@@ -327,10 +396,8 @@ __device__ __forceinline__ bool better(double fa, int ia, double fb, int ib) {
 // Member rows and the state are fetched before the reduction so their
 // latency overlaps it.  Dynamic LDS: P * kSlots + 2 NT doubles + NT ints.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_de_step(const BlockDesc* __restrict__ descs) {
-    const BlockDesc* __restrict__ d = descs + blockIdx.x;
+__device__ __forceinline__ void de_step_body(const BlockDesc* __restrict__ d, double* lds) {
     DeState* st = d->st;
-    extern __shared__ double lds[];
     const int P = d->P, NT = blockDim.x, i = threadIdx.x;
     double* xs = lds;                              // P x kSlots
     double* red = xs + (size_t)P * kSlots;         // NT
@@ -351,10 +418,15 @@ __global__ __launch_bounds__(1024) void k_de_step(const BlockDesc* __restrict__ 
         fo = d->fpop[i];
     }
     if (i == 0) {
-        const int g0 = st->gen;
-        s_done = st->done;
+        // Atomic (vector, agent-scope) loads: inside the persistent kernel these
+        // words are rewritten by other workgroups, so they must not come from
+        // the scalar cache.
+        const int g0 = __hip_atomic_load(&st->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_done = __hip_atomic_load(&st->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         s_gen = g0;
-        s_old = (d->rel_tol > 0.0 && d->window > 0 && g0 >= d->window) ? d->hist[g0 - d->window] : 0.0;
+        s_old = (d->rel_tol > 0.0 && d->window > 0 && g0 >= d->window)
+                    ? __hip_atomic_load(d->hist + (g0 - d->window), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                    : 0.0;
     }
     const double ft = reduce_partials(d, red);  // contains a barrier
     if (s_done) return;
@@ -470,6 +542,117 @@ __global__ __launch_bounds__(1024) void k_de_step(const BlockDesc* __restrict__ 
     double* trow = d->trial + (size_t)i * kStride;
 #pragma unroll
     for (int j = 0; j < kStride; ++j) trow[j] = y[j];
+}
+
+__global__ __launch_bounds__(1024) void k_de_step(const BlockDesc* __restrict__ descs) {
+    extern __shared__ double lds[];
+    de_step_body(descs + blockIdx.x, lds);
+}
+
+// ---------------------------------------------------------------------------
+// Persistent fit kernel: every generation of every block of a launch in one
+// cooperative grid.  Workgroup w owns a fixed list of work units (those of
+// its XCD's contiguous range of units, round-robin over the XCD's
+// workgroups); with at most one unit per workgroup its samples stay in
+// registers for the whole fit.  Per block there is no grid-wide barrier:
+// each finished unit bumps the block's arrival counter, the workgroup that
+// completes a generation runs that block's DE step and publishes the next
+// trial population by raising the block's ready counter, and a workgroup
+// about to evaluate generation g of a block waits until ready >= g.
+//
+// Progress: every workgroup processes generation g of all its units before
+// any unit of generation g + 1, so the workgroups at the lowest generation
+// only ever wait for DE steps whose units are all finished; with all
+// workgroups resident (cooperative launch) the grid always drains.  Waits
+// are bounded by spin_ticks of the constant-rate clock as a safety net: on
+// expiry the kernel sets *err and every workgroup leaves.
+// ---------------------------------------------------------------------------
+constexpr int kPersistLds = 256 * kSlots + 2 * 256 + 128;  // doubles: DE step (P <= 256) or one unit
+
+// Poll with relaxed agent-scope loads (no cache maintenance per poll), then
+// one acquire fence once the value is reached.  Called by one thread.
+__device__ __forceinline__ bool spin_until_ge(int* p, int want, int* err, uint64_t spin_ticks) {
+    const uint64_t t0 = wall_clock64();
+    for (;;) {
+        if (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= want) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            return true;
+        }
+        if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
+        if (wall_clock64() - t0 > spin_ticks) {
+            __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(2);
+    }
+}
+
+template <typename T, int S, int CPG, bool MIXED, bool SLOPE>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_fit_persistent(
+    const BlockDesc* __restrict__ descs, int nblk, int total_units, int max_gens, int resident,
+    int* __restrict__ err, uint64_t spin_ticks) {
+    __shared__ double lds[kPersistLds];
+    __shared__ int s_ok, s_done, s_last;
+    Cand* cs = reinterpret_cast<Cand*>(lds);
+    double(*red)[kThreads] = reinterpret_cast<double(*)[kThreads]>(lds + 64);
+
+    const int G = gridDim.x, w = blockIdx.x;
+    const int xcd = w & 7, k = w >> 3, Gx = G >> 3;
+    const int Ux = (total_units + 7) >> 3;
+    const int u_begin = xcd * Ux, u_end = min(total_units, u_begin + Ux);
+
+    using V = typename std::conditional<MIXED, float, double>::type;
+    V sv[S];
+    bool full = true;
+    int valid = S;
+    if (resident && u_begin + k < u_end) {
+        const int u = u_begin + k;
+        const BlockDesc* d = descs + find_block(descs, nblk, u);
+        load_lane<V, T, S>(d, (u - d->unit_begin) / d->ngroups, sv, full, valid);
+    }
+
+    for (int g = 0; g <= max_gens; ++g) {
+        bool any = false;
+        for (int u = u_begin + k; u < u_end; u += Gx) {
+            const BlockDesc* __restrict__ d = descs + find_block(descs, nblk, u);
+            const int local = u - d->unit_begin;
+            const int tile = local / d->ngroups;
+            const int group = local - tile * d->ngroups;
+            __syncthreads();  // everyone is done with the shared flags of the last unit
+            if (threadIdx.x == 0) {
+                const bool ok = spin_until_ge(&d->st->ready, g, err, spin_ticks);
+                s_ok = ok;
+                s_done = ok ? __hip_atomic_load(&d->st->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 1;
+            }
+            __syncthreads();
+            if (!s_ok) return;
+            if (s_done) continue;
+            any = true;
+            if (!resident) load_lane<V, T, S>(d, tile, sv, full, valid);
+            objective_unit<S, CPG, MIXED, SLOPE>(d, tile, group, sv, full, valid, cs, red);
+            // The workgroup barrier makes every wave's partial stores visible
+            // at the XCD's L2; one release fence then publishes them device-wide
+            // before the arrival is counted.
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                const int units_b = d->ntiles * d->ngroups;
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                const int old = __hip_atomic_fetch_add(&d->st->arrive, 1, __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT);
+                const bool last = old == units_b * (g + 1) - 1;
+                if (last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                s_last = last;
+            }
+            __syncthreads();
+            if (s_last) {
+                de_step_body(d, lds);
+                __syncthreads();
+                if (threadIdx.x == 0)
+                    __hip_atomic_store(&d->st->ready, g + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+        if (!any) return;  // every block of this workgroup has stopped
+    }
 }
 
 // ---------------------------------------------------------------------------

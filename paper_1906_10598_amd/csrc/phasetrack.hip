@@ -143,6 +143,38 @@ ObjKernel objective_kernel(int dtype, Geometry g, bool mixed, bool slope) {
     return dtype == PT_F64 ? pick_spl<double>(g, mixed, slope) : pick_spl<float>(g, mixed, slope);
 }
 
+using PersistKernel = void (*)(const BlockDesc*, int, int, int, int, int*, uint64_t);
+
+template <typename T, int S, int C>
+PersistKernel ppick_mode(bool mixed, bool slope) {
+    if (mixed) return slope ? k_fit_persistent<T, S, C, true, true> : k_fit_persistent<T, S, C, true, false>;
+    return slope ? k_fit_persistent<T, S, C, false, true> : k_fit_persistent<T, S, C, false, false>;
+}
+
+template <typename T, int S>
+PersistKernel ppick_cpg(int cpg, bool mixed, bool slope) {
+    switch (cpg) {
+        case 1: return ppick_mode<T, S, 1>(mixed, slope);
+        case 2: return ppick_mode<T, S, 2>(mixed, slope);
+        case 4: return ppick_mode<T, S, 4>(mixed, slope);
+        default: return ppick_mode<T, S, 8>(mixed, slope);
+    }
+}
+
+template <typename T>
+PersistKernel ppick_spl(Geometry g, bool mixed, bool slope) {
+    switch (g.spl) {
+        case 4: return ppick_cpg<T, 4>(g.cpg, mixed, slope);
+        case 8: return ppick_cpg<T, 8>(g.cpg, mixed, slope);
+        case 16: return ppick_cpg<T, 16>(g.cpg, mixed, slope);
+        default: return ppick_cpg<T, 32>(g.cpg, mixed, slope);
+    }
+}
+
+PersistKernel persistent_kernel(int dtype, Geometry g, bool mixed, bool slope) {
+    return dtype == PT_F64 ? ppick_spl<double>(g, mixed, slope) : ppick_spl<float>(g, mixed, slope);
+}
+
 unsigned pow2_at_least(int v) {
     unsigned p = 256;
     while ((int)p < v) p <<= 1;
@@ -183,6 +215,11 @@ struct pt_ctx {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;
     int64_t launches = 0;
     double total_ms = 0.0;
+    // launch mode and the persistent kernel's error flag
+    int launch_mode = PT_LAUNCH_AUTO;
+    int last_launch = PT_LAUNCH_GRAPH;
+    uint64_t spin_ticks = 0;
+    DevBuf errflag;
     // geometry
     Geometry forced{0, 0};
     std::map<std::tuple<int, int, int>, Geometry> tuned;  // (size class, P, mixed)
@@ -496,11 +533,48 @@ int run_fit(pt_ctx* ctx, const pt_block* blocks, int nblk, const pt_de_settings*
     ObjKernel obj = objective_kernel(pl.dtype, pl.geo, pl.mixed, pl.slope);
     const BlockDesc* d = static_cast<const BlockDesc*>(ctx->desc.p);
 
-    hipLaunchKernelGGL(k_de_init, dim3(nblk), dim3(pl.de_threads), 0, s, d);
+    // persistent launch: one cooperative grid runs every generation
+    bool persistent = false;
+    int pgrid = 0, resident = 0;
+    PersistKernel pk = nullptr;
+    if (ctx->launch_mode != PT_LAUNCH_GRAPH && !ctx->timing && pl.P <= 256) {
+        pk = persistent_kernel(pl.dtype, pl.geo, pl.mixed, pl.slope);
+        int per_cu = 0;
+        HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(pk), kThreads,
+                                                            0));
+        const int cap = per_cu * ctx->ncu / 8 * 8;
+        if (cap >= 8) {
+            pgrid = std::min(cap, (pl.total_units + 7) / 8 * 8);
+            resident = (pl.total_units + 7) / 8 <= pgrid / 8;
+            persistent = true;
+        }
+    }
+    if (ctx->launch_mode == PT_LAUNCH_PERSISTENT && !persistent)
+        return fail(PT_EUNSUPPORTED, "persistent launch not possible (P = %d, timing %d)", pl.P, (int)ctx->timing);
+    if ((rc = ctx->errflag.ensure(sizeof(int)))) return rc;
+    int* err = static_cast<int*>(ctx->errflag.p);
+
+    hipLaunchKernelGGL(k_de_init, dim3(nblk), dim3(pl.de_threads), 0, s, d, err);
     HIPCHK(hipGetLastError());
 
     const int iters = de->max_gens + 1;  // evaluation of gen 0 plus max_gens generations
-    if (ctx->timing) {
+    if (persistent) {
+        int nb = nblk, tu = pl.total_units, mg = de->max_gens;
+        uint64_t ticks = ctx->spin_ticks;
+        void* args[] = {&d, &nb, &tu, &mg, &resident, &err, &ticks};
+        hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(pk), dim3(pgrid), dim3(kThreads),
+                                                  args, 0, s);
+        if (e != hipSuccess) {
+            if (ctx->launch_mode == PT_LAUNCH_PERSISTENT)
+                return fail(PT_EDEVICE, "hipLaunchCooperativeKernel: %s", hipGetErrorString(e));
+            (void)hipGetLastError();
+            persistent = false;  // fall back to the graph path below
+        }
+    }
+    ctx->last_launch = persistent ? PT_LAUNCH_PERSISTENT : PT_LAUNCH_GRAPH;
+    if (persistent) {
+        // nothing else to enqueue
+    } else if (ctx->timing) {
         for (int k = 0; k < iters; ++k)
             if ((rc = enqueue_generation(ctx, pl, obj, s, true))) return rc;
     } else {
@@ -525,8 +599,11 @@ int run_fit(pt_ctx* ctx, const pt_block* blocks, int nblk, const pt_de_settings*
     hipLaunchKernelGGL(k_finalize, dim3(nblk), dim3(64), 0, s, d, static_cast<FitRecord*>(ctx->rec.p));
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(ctx->hrec.p, ctx->rec.p, sizeof(FitRecord) * nblk, hipMemcpyDeviceToHost, s));
+    int* herr = reinterpret_cast<int*>(static_cast<char*>(ctx->hstate.p));
+    HIPCHK(hipMemcpyAsync(herr, err, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (ctx->timing && (rc = collect_timing(ctx))) return rc;
+    if (*herr) return fail(PT_EDEVICE, "persistent fit: a block's generation did not complete in time");
 
     const FitRecord* r = static_cast<const FitRecord*>(ctx->hrec.p);
     ctx->last_nblk = nblk;
@@ -574,6 +651,10 @@ int pt_ctx_create(int device, pt_ctx** out) {
     if (!c) return fail(PT_ENOMEM, "out of host memory");
     c->device = device;
     c->ncu = prop.multiProcessorCount;
+    int clk_khz = 0;
+    if (hipDeviceGetAttribute(&clk_khz, hipDeviceAttributeWallClockRate, device) != hipSuccess || clk_khz <= 0)
+        clk_khz = 100000;
+    c->spin_ticks = (uint64_t)clk_khz * 1000ull * 5ull;  // 5 s
     HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
     *out = c.release();
     return PT_OK;
@@ -589,8 +670,8 @@ void pt_ctx_destroy(pt_ctx* ctx) {
         (void)hipEventDestroy(pr.first);
         (void)hipEventDestroy(pr.second);
     }
-    DevBuf* bufs[] = {&ctx->desc,  &ctx->pop,  &ctx->trial, &ctx->fpop,    &ctx->partials, &ctx->hist,
-                      &ctx->state, &ctx->rec,  &ctx->staging, &ctx->eval_pop, &ctx->scratch};
+    DevBuf* bufs[] = {&ctx->desc,    &ctx->pop,      &ctx->trial,   &ctx->fpop,  &ctx->partials, &ctx->hist,
+                      &ctx->state,   &ctx->rec,      &ctx->staging, &ctx->eval_pop, &ctx->scratch, &ctx->errflag};
     for (DevBuf* b : bufs) b->release();
     ctx->hdesc.release();
     ctx->hrec.release();
@@ -777,6 +858,20 @@ int pt_los_accel(const pt_fit* fit, double t, double f_carrier_hz, double M2, in
 }
 
 // ------------------------------------------------------------ instrumentation
+int pt_ctx_set_launch_mode(pt_ctx* ctx, int mode) {
+    if (!ctx) return fail(PT_EINVAL, "ctx is null");
+    if (mode != PT_LAUNCH_AUTO && mode != PT_LAUNCH_GRAPH && mode != PT_LAUNCH_PERSISTENT)
+        return fail(PT_EINVAL, "launch mode %d", mode);
+    ctx->launch_mode = mode;
+    return PT_OK;
+}
+
+int pt_ctx_last_launch(pt_ctx* ctx, int* mode) {
+    if (!ctx || !mode) return fail(PT_EINVAL, "ctx / mode is null");
+    *mode = ctx->last_launch;
+    return PT_OK;
+}
+
 int pt_ctx_set_timing(pt_ctx* ctx, int on) {
     if (!ctx) return fail(PT_EINVAL, "ctx is null");
     ctx->timing = on != 0;

@@ -21,6 +21,7 @@ PT_OK, PT_EINVAL, PT_ENOMEM, PT_EDEVICE, PT_EBUSY, PT_EUNSUPPORTED = 0, -1, -2, 
 PT_F32, PT_F64 = 0, 1
 PT_PREC_FP64, PT_PREC_MIXED = 0, 1
 PT_FLAG_CONVERGED, PT_FLAG_MAXGEN, PT_FLAG_VTR, PT_FLAG_AT_BOUND = 1, 2, 4, 8
+PT_LAUNCH_AUTO, PT_LAUNCH_GRAPH, PT_LAUNCH_PERSISTENT = 0, 1, 2
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libphasetrack.so")
 
@@ -109,6 +110,8 @@ def _signatures(L):
         "pt_los_accel": ([ctypes.POINTER(pt_fit), ctypes.c_double, ctypes.c_double, ctypes.c_double, i32,
                           _DP], i32),
         "pt_time_objective": ([_CTX, ctypes.POINTER(pt_block), _VP, i32, i32, i32, _VP, _DP], i32),
+        "pt_ctx_set_launch_mode": ([_CTX, i32], i32),
+        "pt_ctx_last_launch": ([_CTX, ctypes.POINTER(i32)], i32),
         "pt_ctx_set_timing": ([_CTX, i32], i32),
         "pt_ctx_kernel_stats": ([_CTX, ctypes.POINTER(i64), _DP], i32),
         "pt_ctx_get_tile": ([_CTX, i64, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)], i32),
@@ -230,6 +233,16 @@ def pt_time_objective(ctx, block: pt_block, pop_ptr: int, P: int, precision: int
     _check(lib().pt_time_objective(ctx, ctypes.byref(block), pop_ptr, P, precision, reps, stream,
                                    ctypes.byref(ms)), "pt_time_objective")
     return ms.value
+
+
+def pt_ctx_set_launch_mode(ctx, mode: int):
+    _check(lib().pt_ctx_set_launch_mode(ctx, mode), "pt_ctx_set_launch_mode")
+
+
+def pt_ctx_last_launch(ctx) -> int:
+    m = ctypes.c_int()
+    _check(lib().pt_ctx_last_launch(ctx, ctypes.byref(m)), "pt_ctx_last_launch")
+    return m.value
 
 
 def pt_ctx_set_timing(ctx, on: bool):
