@@ -80,6 +80,57 @@ def run_fits(ctx, blk, de_fn, n, label):
     return time.perf_counter() - t0, lat, fits
 
 
+def run_serving(ctx, ptk, synth, np, torch, nblocks):
+    """16 tracks, Poisson arrivals at 20 blocks/s, N in {1e5, 2e5, 4e5, 1e6}.
+
+    Blocks are submitted when their arrival time has passed on the server
+    clock; latency = completion - arrival.  Window stop rule (1e-9 over 50
+    generations, cap 3000), warm starts with a 30 % narrower box."""
+    items = synth.config4_stream(seed=0, ntracks=16, nblocks=nblocks, rate=20.0)
+    de = ptk.make_settings(pop=40, max_gens=3000, F=0.5, CR=0.9, seed=0x19061059 ^ 0xDE, rel_tol=1e-9, window=50)
+    srv = ptk.pt_server_create(ctx.handle, ptk.make_server_config(de, max_slots=64, gens_per_step=32,
+                                                                  hbm_budget_bytes=64 << 30))
+    stream = ptk.current_stream()
+    host = [torch.from_numpy(it["block"].samples) for it in items]
+    blks = [ptk.make_block(h, it["block"].fs, it["block"].lo, it["block"].hi, ref=it["block"].ref,
+                           stream=it["block"].stream) for h, it in zip(host, items)]
+    t0 = ptk.pt_server_clock(srv)
+    nxt, res, tick = 0, {}, {}
+    active = pending = 0
+    while len(res) < len(items):
+        now = ptk.pt_server_clock(srv) - t0
+        while nxt < len(items) and items[nxt]["arrival"] <= now:
+            t = ptk.pt_server_submit(srv, items[nxt]["track"], blks[nxt])
+            if t is None:
+                break
+            tick[t] = nxt
+            nxt += 1
+        if active or pending or nxt > len(res):
+            active, pending = ptk.pt_server_step(srv, stream)
+        elif nxt < len(items):
+            time.sleep(max(0.0, min(0.002, items[nxt]["arrival"] - now)))
+        for r in ptk.pt_server_poll(srv):
+            res[tick[r.ticket]] = r
+    elapsed = ptk.pt_server_clock(srv) - t0
+    ptk.pt_server_destroy(srv)
+    lat, errs, gens, warm = [], [], [], 0
+    for k, it in enumerate(items):
+        r = res[k]
+        lat.append((r.t_done - t0 - it["arrival"]) * 1e3)
+        b = it["block"]
+        sig = math.sqrt(6.0) * b.sigma / (math.pi * b.truth[0] * (b.n / b.fs) * math.sqrt(b.n))
+        errs.append(abs(r.fit.coef[2] - b.truth[2]) / sig)
+        gens.append(r.fit.generations)
+        warm += r.warm
+    return {"workload": f"{len(items)} blocks from 16 tracks, Poisson arrivals at 20 blocks/s, N in "
+                        "{1e5, 2e5, 4e5, 1e6} at 50 kHz, window stop 1e-9/50 (cap 3000), warm starts 0.7x box",
+            "latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99), "max": max(lat)},
+            "blocks_per_s": len(items) / elapsed, "offered_blocks_per_s": 20.0,
+            "f0_err_over_crlb": {"median": pct(errs, 50), "p99": pct(errs, 99)},
+            "generations": {"mean": float(sum(gens) / len(gens)), "max": max(gens)},
+            "warm_fraction": warm / len(items)}
+
+
 def cpu_baseline(b, gens, nthreads):
     import numpy as np
 
@@ -109,6 +160,9 @@ def main():
                     help="profiling mode: one fit, then --reps back-to-back objective launches; "
                          "also one 256 MiB device copy as the traffic-counter calibration")
     ap.add_argument("--reps", type=int, default=200)
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-block batched fits")
+    ap.add_argument("--no-serve", action="store_true", help="skip the real-time serving run")
+    ap.add_argument("--serve-blocks", type=int, default=160)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -211,6 +265,40 @@ def main():
 
     traffic = read_traffic()
 
+    # ---- batched fits: 64 uneven blocks, own populations, shared launches
+    batch = None
+    if not args.no_batch:
+        batch = {}
+        blocks = synth.config3(0)
+        bdev = [torch.from_numpy(x.samples).cuda() for x in blocks]
+        pbs = [ptk.make_block(d, x.fs, x.lo, x.hi, ref=x.ref, stream=x.stream) for x, d in zip(blocks, bdev)]
+        gens_b = blocks[0].de.max_gens
+        pairs_b = sum(P * (gens_b + 1) * x.n for x in blocks)
+        for name, prec in (("fp64", ptk.PT_PREC_FP64), ("mixed", ptk.PT_PREC_MIXED)):
+            deb = ptk.make_settings(pop=P, max_gens=gens_b, F=0.5, CR=0.9, seed=b.de.seed, precision=prec)
+            ctx.fit_batch(pbs, deb)  # warm (graph capture for this shape)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fits_b = ctx.fit_batch(pbs, deb)
+            dt = time.perf_counter() - t0
+            errs = [abs(f.coef[2] - x.truth[2]) for f, x in zip(fits_b, blocks)]
+            batch[name] = {"value": pairs_b / dt, "unit": "candidate*sample/s", "seconds": dt,
+                           "block_fits_per_s": len(blocks) / dt, "median_abs_f0_err_hz": float(np.median(errs)),
+                           "geometry": list(ptk.pt_ctx_get_tile(ctx.handle, 400_000, P, prec))}
+        batch["workload"] = ("64 blocks, N log-uniform in [5e4, 4e5] at 50 kHz (total %d samples), own "
+                             "populations P=40, 1500 generations, one launch per generation" %
+                             sum(x.n for x in blocks))
+        print(f"# batch: {batch['fp64']['seconds']:.3f} s fp64, {batch['mixed']['seconds']:.3f} s mixed",
+              file=sys.stderr, flush=True)
+        del bdev
+
+    # ---- real-time serving: Poisson arrivals, warm starts, continuous batching
+    serving = None
+    if not args.no_serve:
+        serving = run_serving(ctx, ptk, synth, np, torch, args.serve_blocks)
+        print(f"# serving: p50 {serving['latency_ms']['p50']:.1f} ms p99 {serving['latency_ms']['p99']:.1f} ms",
+              file=sys.stderr, flush=True)
+
     # ---- CPU oracle baseline (bounded sample of the same fit)
     cpu = None
     if not args.no_cpu:
@@ -254,6 +342,8 @@ def main():
                      "in_fit_event_ms": r64["in_fit_event_ms"], "launches_per_fit": r64["launches"],
                      "flop_per_candidate_sample": FLOP_PER_PAIR["fp64"],
                      "kernel_hash": kernel_hash()},
+        "batch": batch,
+        "serving": serving,
         "cpu_baseline": cpu,
         "paper_context": {"gtx580_fit_s": 6.5, "evaluations": 80000, "block": "~400K samples"},
     }

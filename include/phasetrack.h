@@ -231,6 +231,67 @@ int pt_connect_phase(const pt_fit* fits, int nblk, double* phi_total_rad, double
 int pt_los_accel(const pt_fit* fit, double t, double f_carrier_hz, double M2, int three_way,
                  double* a_m_s2);
 
+/* ---- serving: continuous batching of arriving blocks ----
+ * A server keeps up to max_slots blocks resident on the device (samples,
+ * population, partial sums and DE state of each).  pt_server_step runs
+ * gens_per_step generations of every resident block in shared launches (one
+ * objective grid over all resident blocks, then each block's DE step), then
+ * retires the blocks whose stop rule fired into the result queue; blocks
+ * submitted meanwhile are admitted at the start of the next step as slots
+ * and the HBM budget free up.  A track's blocks are fitted in submission
+ * order: the next one is admitted once the previous fit is done and starts
+ * warm -- the previous fitted phase re-expanded about the new block's
+ * reference time (the running range of Sec. 3.1.1), with the block's own box
+ * half-widths scaled by warm_narrow around that prediction.  The first block
+ * of a track uses its box as given.  Every block of a server uses the same
+ * DE settings and one objective geometry, so a block's result does not
+ * depend on which other blocks share its steps. */
+typedef struct pt_server pt_server;
+
+typedef struct {
+    int32_t max_slots;          /* resident blocks, 1..1024 */
+    int32_t gens_per_step;      /* generations per scheduler step, >= 1 */
+    int32_t max_pending;        /* queued (not yet admitted) blocks, >= 1 */
+    int32_t spl, cpg;           /* objective geometry; 0, 0 = default for 400K samples */
+    int32_t reserved;
+    double warm_narrow;         /* box scale of warm starts, 0 (off) .. 1 */
+    uint64_t hbm_budget_bytes;  /* device bytes resident blocks may hold */
+    pt_de_settings de;          /* settings of every block (pop <= 256) */
+} pt_server_config;
+
+typedef struct {
+    uint64_t ticket;            /* from pt_server_submit */
+    int32_t track;
+    int32_t warm;               /* 1: warm-started from the track's previous fit */
+    double t_submit, t_done;    /* seconds on the server clock */
+    pt_box box;                 /* search box the fit used */
+    pt_fit fit;
+} pt_server_result;
+
+int pt_server_create(pt_ctx* ctx, const pt_server_config* cfg, pt_server** out);
+
+/* Destroy a server (its queued and running blocks are dropped). */
+void pt_server_destroy(pt_server* srv);
+
+/* Queue a block of `track` (samples copied by the call, host or device).
+ * PT_EBUSY when max_pending blocks are already queued; PT_EINVAL when the
+ * block alone exceeds the HBM budget. */
+int pt_server_submit(pt_server* srv, int32_t track, const pt_block* block, uint64_t* ticket);
+
+/* One scheduler step on hip_stream (admit, run gens_per_step generations,
+ * retire); returns after the step's results are queued.  n_active: blocks
+ * still running afterwards; n_pending: blocks still queued. */
+int pt_server_step(pt_server* srv, void* hip_stream, int32_t* n_active, int32_t* n_pending);
+
+/* Move up to max finished results to out (oldest first). */
+int pt_server_poll(pt_server* srv, pt_server_result* out, int32_t max, int32_t* n_out);
+
+/* Resident blocks, queued blocks and budgeted device bytes in use. */
+int pt_server_stats(pt_server* srv, int32_t* active, int32_t* pending, uint64_t* used_bytes);
+
+/* Seconds since the server was created (monotonic host clock). */
+double pt_server_clock(pt_server* srv);
+
 /* ---- launch strategy ---- */
 
 /* How a fit's generations are launched.
@@ -241,7 +302,9 @@ int pt_los_accel(const pt_fit* fit, double t, double f_carrier_hz, double M2, in
  *     grid that fits on the device at once.
  *   PT_LAUNCH_GRAPH: per generation one objective launch and one DE-step
  *     launch, replayed from captured HIP graphs of 50 generations.
- *   PT_LAUNCH_AUTO (default): persistent when possible, else graph.
+ *   PT_LAUNCH_AUTO (default): graph.  On MI355X the per-block barrier of
+ *     the persistent grid costs about as much as graph-replayed launches,
+ *     which run back to back, so the graph path is the faster default.
  * Both give bit-identical results for the same geometry. */
 enum { PT_LAUNCH_AUTO = 0, PT_LAUNCH_GRAPH = 1, PT_LAUNCH_PERSISTENT = 2 };
 
@@ -250,6 +313,19 @@ int pt_ctx_set_launch_mode(pt_ctx* ctx, int mode);
 /* Launch strategy the context's most recent fit used (PT_LAUNCH_GRAPH or
  * PT_LAUNCH_PERSISTENT). */
 int pt_ctx_last_launch(pt_ctx* ctx, int* mode);
+
+/* ---- FP64 objective arithmetic ----
+ * PT_FP64_AUTO (default): inside each lane's chunk of S samples the phasor
+ *   exp(2 pi i Phi) advances by two complex multiplies per sample from an
+ *   exact FP64 anchor (cubic term inside the chunk dropped), whenever that
+ *   is exact to 1e-12 turns for the block and box: (S - 1)^3 |f2|max /
+ *   (6 fs^3) <= 1e-12 and the chunk's second phase difference is below
+ *   1e-2 / (2 pi) turns; otherwise the per-sample path.
+ * PT_FP64_POLY: always the per-sample path (exact reduction of the phase in
+ *   turns, degree-10 cosine polynomial). */
+enum { PT_FP64_AUTO = 0, PT_FP64_POLY = 1 };
+
+int pt_ctx_set_fp64_method(pt_ctx* ctx, int method);
 
 /* ---- instrumentation ---- */
 

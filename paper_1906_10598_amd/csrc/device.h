@@ -60,8 +60,17 @@ struct BlockDesc {
     double* partials;  // P x ntiles objective partial sums
     double* hist;      // max_gens + 1 best-so-far values
     DeState* st;       // may be null (bare objective evaluation)
-    double* result;    // 8 doubles: best slots 0..5, objective, unused
+    int* sync;         // persistent kernel: kSyncInts counters (see k_fit_persistent), or null
+    int gen_begin;     // persistent kernel: generation whose trial is ready at launch
+    int pad1;
 };
+
+// Persistent-kernel synchronisation words of one block, one 128-byte line each:
+// line x < 8: arrivals of the block's units in XCD range x; line 8 + x: copy of
+// the block's ready generation polled by XCD range x; line 16: arrivals of
+// XCD ranges.
+constexpr int kSyncLine = 32;  // ints per 128-byte line
+constexpr int kSyncInts = 17 * kSyncLine;
 
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two

@@ -29,6 +29,52 @@
 namespace pt {
 
 // ---------------------------------------------------------------------------
+// Accesses to data one workgroup writes and another reads inside one launch
+// of the persistent kernel (population rows, partial sums, DE state).
+// Variant 0: plain accesses, agent-scope acquire / release fences (L2
+// invalidate / write-back).  Variant 1: coherent (agent-scope atomic) loads,
+// so readers need no L2 invalidate.  Variant 2 (built): coherent loads and
+// stores, so neither side needs cache maintenance; fences only order the
+// wave.  All three give bit-identical fits; on the paper-scale block the fit
+// takes 70, 52 and 48 ms with them.
+// ---------------------------------------------------------------------------
+#ifndef PT_SYNC_VARIANT
+#define PT_SYNC_VARIANT 2
+#endif
+#if PT_SYNC_VARIANT >= 1
+#define PT_ACQ_SCOPE "workgroup"
+#else
+#define PT_ACQ_SCOPE "agent"
+#endif
+#if PT_SYNC_VARIANT >= 2
+#define PT_REL_SCOPE "workgroup"
+#else
+#define PT_REL_SCOPE "agent"
+#endif
+
+__device__ __forceinline__ double xld(const double* p) {
+#if PT_SYNC_VARIANT >= 1
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#else
+    return *p;
+#endif
+}
+__device__ __forceinline__ void xst(double* p, double v) {
+#if PT_SYNC_VARIANT >= 2
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#else
+    *p = v;
+#endif
+}
+__device__ __forceinline__ void xsti(int* p, int v) {
+#if PT_SYNC_VARIANT >= 2
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#else
+    *p = v;
+#endif
+}
+
+// ---------------------------------------------------------------------------
 // helpers
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double wave_sum(double v) {
@@ -51,15 +97,15 @@ struct Cand {
     double a0, a1, a2, a3, A, Ad;  // Ad = Adot / fs: amplitude slope per sample
 };
 
-__device__ __forceinline__ Cand make_cand(const double* __restrict__ x, double fs) {
+__device__ __forceinline__ Cand make_cand(const double* x, double fs) {
     Cand c;
-    const double t = x[1] * 0.15915494309189533577;  // phi0 / (2 pi)
+    const double t = xld(x + 1) * 0.15915494309189533577;  // phi0 / (2 pi)
     c.a0 = t - rint(t);
-    c.a1 = x[2] / fs;
-    c.a2 = x[3] / (2.0 * fs * fs);
-    c.a3 = x[4] / (6.0 * fs * fs * fs);
-    c.A = x[0];
-    c.Ad = x[5] / fs;
+    c.a1 = xld(x + 2) / fs;
+    c.a2 = xld(x + 3) / (2.0 * fs * fs);
+    c.a3 = xld(x + 4) / (6.0 * fs * fs * fs);
+    c.A = xld(x + 0);
+    c.Ad = xld(x + 5) / fs;
     return c;
 }
 
@@ -103,8 +149,15 @@ __device__ __forceinline__ double lane_chi2_f64(const double (&sv)[S], const Anc
     // through the group, then the IL cosine polynomials are evaluated in
     // lockstep (IL independent FMA chains hide the FP64 FMA latency) and
     // summed into IL accumulators that are combined at the end.
-    constexpr int IL = 4;
-    static_assert(S % IL == 0, "samples per lane must be a multiple of 4");
+#ifndef PT_IL64
+#define PT_IL64 4
+#endif
+#ifndef PT_COS64
+#define PT_COS64 kCos64
+#define PT_COS64_DEG kCosDeg64
+#endif
+    constexpr int IL = (S >= PT_IL64) ? PT_IL64 : S;
+    static_assert(S % IL == 0, "samples per lane must be a multiple of the interleave");
     double acc[IL];
 #pragma unroll
     for (int q = 0; q < IL; ++q) acc[q] = 0.0;
@@ -124,12 +177,12 @@ __device__ __forceinline__ double lane_chi2_f64(const double (&sv)[S], const Anc
                 d2 += d3;
             }
             u[q] = r * r;
-            p[q] = kCos64[0];
+            p[q] = PT_COS64[0];
         }
 #pragma unroll
-        for (int k = 1; k <= kCosDeg64; ++k) {
+        for (int k = 1; k <= PT_COS64_DEG; ++k) {
 #pragma unroll
-            for (int q = 0; q < IL; ++q) p[q] = __fma_rn(p[q], u[q], kCos64[k]);
+            for (int q = 0; q < IL; ++q) p[q] = __fma_rn(p[q], u[q], PT_COS64[k]);
         }
 #pragma unroll
         for (int q = 0; q < IL; ++q) {
@@ -143,7 +196,74 @@ __device__ __forceinline__ double lane_chi2_f64(const double (&sv)[S], const Anc
             }
         }
     }
-    return (acc[0] + acc[1]) + (acc[2] + acc[3]);
+    double tot = 0.0;
+#pragma unroll
+    for (int q = 0; q < IL; ++q) tot += acc[q];
+    return tot;
+}
+
+// ---------------------------------------------------------------------------
+// FP64 phasor lane accumulation.  Within one lane chunk the phase is the
+// quadratic b0 + b1 j + b2 j^2 (turns); the host selects this path only when
+// the dropped cubic term, (S - 1)^3 |b3|, is below 1e-12 turns and the
+// second difference 2 b2 is below 1e-2 / (2 pi) turns for every candidate.
+// z_j = exp(2 pi i Phi(j)) then follows the recurrence z_{j+1} = z_j w_j,
+// w_{j+1} = w_j v with w_0 = exp(2 pi i (b1 + b2)) and v = exp(2 pi i 2 b2):
+// two complex multiplies (8 FMA/MUL) per sample instead of a reduction and
+// a degree-10 cosine.  z_0 and w_0 come from the sine / cosine polynomials
+// of the reduced turns; v from its Taylor series (|angle| <= 1e-2, error
+// below 1e-20).  The recurrence's rounding grows as ~2 S ulp (S <= 32).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void sincos_turns64(double r, double& c, double& sn) {
+    const double u = r * r;
+    double pc = kCos64[0], ps = kSin64[0];
+#pragma unroll
+    for (int k = 1; k <= kCosDeg64; ++k) {
+        pc = __fma_rn(pc, u, kCos64[k]);
+        ps = __fma_rn(ps, u, kSin64[k]);
+    }
+    c = pc;
+    sn = r * ps;
+}
+
+template <int S, bool TAIL, bool SLOPE>
+__device__ __forceinline__ double lane_chi2_f64_rot(const double (&sv)[S], const Anchor& an, double amp0,
+                                                    double ad, int valid) {
+    static_assert(kSinDeg64 == kCosDeg64, "sine and cosine tables have one degree");
+    double zr, zi, wr, wi;
+    sincos_turns64(an.b0, zr, zi);  // b0 is already reduced to [-1/2, 1/2]
+    double d = an.b1 + an.b2;
+    d -= rint(d);
+    sincos_turns64(d, wr, wi);
+    const double x = 12.566370614359172954 * an.b2;  // 2 pi (2 b2) radians
+    const double x2 = x * x;
+    const double vr = __fma_rn(x2, __fma_rn(x2, __fma_rn(x2, -1.0 / 720.0, 1.0 / 24.0), -0.5), 1.0);
+    const double vi = x * __fma_rn(x2, __fma_rn(x2, __fma_rn(x2, -1.0 / 5040.0, 1.0 / 120.0), -1.0 / 6.0), 1.0);
+    double acc0 = 0.0, acc1 = 0.0;
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+        const double amp = SLOPE ? __fma_rn(ad, (double)j, amp0) : amp0;
+        const double rho = __fma_rn(-amp, zr, sv[j]);
+        double& acc = (j & 1) ? acc1 : acc0;
+        if (TAIL) {
+            if (j < valid) acc = __fma_rn(rho, rho, acc);
+        } else {
+            acc = (j < 2) ? rho * rho : __fma_rn(rho, rho, acc);
+        }
+        if (j + 1 < S) {
+            const double nzr = __fma_rn(zr, wr, -(zi * wi));
+            const double nzi = __fma_rn(zr, wi, zi * wr);
+            zr = nzr;
+            zi = nzi;
+            if (j + 2 < S) {
+                const double nwr = __fma_rn(wr, vr, -(wi * vi));
+                const double nwi = __fma_rn(wr, vi, wi * vr);
+                wr = nwr;
+                wi = nwi;
+            }
+        }
+    }
+    return acc0 + acc1;
 }
 
 // ---------------------------------------------------------------------------
@@ -212,7 +332,7 @@ __device__ __forceinline__ float lane_chi2_mixed(const float (&sv)[S], const Anc
 // One work unit of the objective: the 256 * S samples of `tile` against the
 // CPG candidates of `group`.  Writes partials[cand * ntiles + tile].
 // T: sample type; S: samples per lane; CPG: candidates per workgroup;
-// MIXED: precision mode; SLOPE: amplitude slope active.  sv holds the
+// MODE: arithmetic (see objective_unit); SLOPE: amplitude slope active.  sv holds the
 // lane's samples (loaded by load_lane); cs / red are LDS scratch.
 // ---------------------------------------------------------------------------
 template <typename V, typename T, int S>
@@ -235,7 +355,9 @@ __device__ __forceinline__ void load_lane(const BlockDesc* __restrict__ d, int t
     }
 }
 
-template <int S, int CPG, bool MIXED, bool SLOPE, typename V>
+// MODE: 0 = FP64 with per-sample cosine polynomial, 1 = mixed precision,
+// 2 = FP64 phasor recurrence.
+template <int S, int CPG, int MODE, bool SLOPE, typename V>
 __device__ __forceinline__ void objective_unit(const BlockDesc* __restrict__ d, int tile, int group,
                                                const V (&sv)[S], bool full, int valid, Cand* cs,
                                                double (*red)[kThreads]) {
@@ -251,9 +373,12 @@ __device__ __forceinline__ void objective_unit(const BlockDesc* __restrict__ d, 
         const Anchor an = make_anchor(cc, m0);
         const double amp0 = SLOPE ? __fma_rn(cc.Ad, m0, cc.A) : cc.A;
         double acc;
-        if constexpr (MIXED) {
+        if constexpr (MODE == 1) {
             acc = full ? (double)lane_chi2_mixed<S, false, SLOPE>(sv, an, amp0, cc.Ad, valid)
                        : (double)lane_chi2_mixed<S, true, SLOPE>(sv, an, amp0, cc.Ad, valid);
+        } else if constexpr (MODE == 2) {
+            acc = full ? lane_chi2_f64_rot<S, false, SLOPE>(sv, an, amp0, cc.Ad, valid)
+                       : lane_chi2_f64_rot<S, true, SLOPE>(sv, an, amp0, cc.Ad, valid);
         } else {
             acc = full ? lane_chi2_f64<S, false, SLOPE>(sv, an, amp0, cc.Ad, valid)
                        : lane_chi2_f64<S, true, SLOPE>(sv, an, amp0, cc.Ad, valid);
@@ -266,13 +391,13 @@ __device__ __forceinline__ void objective_unit(const BlockDesc* __restrict__ d, 
     for (int c = wave; c < ncand; c += kThreads / 64) {
         double v = ((red[c][lane] + red[c][lane + 64]) + red[c][lane + 128]) + red[c][lane + 192];
         v = wave_sum(v);
-        if (lane == 0) d->partials[(size_t)(cbase + c) * d->ntiles + tile] = v;
+        if (lane == 0) xst(d->partials + (size_t)(cbase + c) * d->ntiles + tile, v);
     }
 }
 
 // Objective kernel: one work unit per workgroup.  Units are remapped so
 // that the candidate groups of a tile run on one XCD.
-template <typename T, int S, int CPG, bool MIXED, bool SLOPE>
+template <typename T, int S, int CPG, int MODE, bool SLOPE>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_objective(
     const BlockDesc* __restrict__ descs, int nblk, int total_units) {
     const int nwg = gridDim.x;  // multiple of 8
@@ -287,12 +412,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 4))
 
     __shared__ Cand cs[CPG];
     __shared__ double red[CPG][kThreads];
-    using V = typename std::conditional<MIXED, float, double>::type;
+    using V = typename std::conditional<MODE == 1, float, double>::type;
     V sv[S];
     bool full;
     int valid;
     load_lane<V, T, S>(d, tile, sv, full, valid);
-    objective_unit<S, CPG, MIXED, SLOPE>(d, tile, group, sv, full, valid, cs, red);
+    objective_unit<S, CPG, MODE, SLOPE>(d, tile, group, sv, full, valid, cs, red);
 }
 
 // ---------------------------------------------------------------------------
@@ -309,15 +434,16 @@ __device__ __forceinline__ double reduce_partials(const BlockDesc* __restrict__ 
     const int k = NT >= P ? NT / P : 1;
     if (t < P * k) {
         const int c = t / k, part = t - c * k;
-        const double* __restrict__ pr = d->partials + (size_t)c * T;
+        const double* pr = d->partials + (size_t)c * T;
         double s = 0.0;
         int tt = part;
         // issue four independent loads per step; add them in tile order
         for (; tt + 3 * k < T; tt += 4 * k) {
-            const double v0 = pr[tt], v1 = pr[tt + k], v2 = pr[tt + 2 * k], v3 = pr[tt + 3 * k];
+            const double v0 = xld(pr + tt), v1 = xld(pr + tt + k), v2 = xld(pr + tt + 2 * k),
+                         v3 = xld(pr + tt + 3 * k);
             s = (((s + v0) + v1) + v2) + v3;
         }
-        for (; tt < T; tt += k) s += pr[tt];
+        for (; tt < T; tt += k) s += xld(pr + tt);
         red[t] = s;
     }
     __syncthreads();
@@ -341,10 +467,9 @@ __global__ void k_reduce_out(const BlockDesc* __restrict__ descs, double* __rest
 // DE: initial population (generation 0), one workgroup per block.
 // x_j = lo_j + u (hi_j - lo_j), u = (w + 1/2) / 2^32 from the INIT stream.
 // ---------------------------------------------------------------------------
-__global__ void k_de_init(const BlockDesc* __restrict__ descs, int* __restrict__ err) {
-    const BlockDesc* d = descs + blockIdx.x;
+// Initial population of one block (generation 0) and its DE state.
+__device__ __forceinline__ void init_block(const BlockDesc* __restrict__ d) {
     const int i = threadIdx.x;
-    if (err != nullptr && blockIdx.x == 0 && i == 0) *err = 0;
     if (i < d->P) {
         double x[kStride];
 #pragma unroll
@@ -377,6 +502,13 @@ __global__ void k_de_init(const BlockDesc* __restrict__ descs, int* __restrict__
         s.ready = 0;
         *d->st = s;
     }
+    if (d->sync != nullptr)
+        for (int k = i; k < kSyncInts; k += blockDim.x) d->sync[k] = 0;  // gen_begin is 0 here
+}
+
+__global__ void k_de_init(const BlockDesc* __restrict__ descs, int* __restrict__ err) {
+    if (err != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *err = 0;
+    init_block(descs + blockIdx.x);
 }
 
 // (f, index) pair order of the argmin: smaller objective, then smaller index.
@@ -412,10 +544,10 @@ __device__ __forceinline__ void de_step_body(const BlockDesc* __restrict__ d, do
         const double* b = d->pop + (size_t)i * kStride;
 #pragma unroll
         for (int j = 0; j < kSlots; ++j) {
-            tr[j] = a[j];
-            po[j] = b[j];
+            tr[j] = xld(a + j);
+            po[j] = xld(b + j);
         }
-        fo = d->fpop[i];
+        fo = xld(d->fpop + i);
     }
     if (i == 0) {
         // Atomic (vector, agent-scope) loads: inside the persistent kernel these
@@ -441,10 +573,10 @@ __device__ __forceinline__ void de_step_body(const BlockDesc* __restrict__ d, do
         for (int j = 0; j < kSlots; ++j) {
             const double v = take ? tr[j] : po[j];
             xs[i * kSlots + j] = v;
-            if (take) prow[j] = v;
+            if (take) xst(prow + j, v);
         }
         fsel = take ? ft : fo;
-        if (take) d->fpop[i] = ft;
+        if (take) xst(d->fpop + i, ft);
     }
 
     // argmin, lowest index on ties
@@ -485,19 +617,19 @@ __device__ __forceinline__ void de_step_body(const BlockDesc* __restrict__ d, do
     bf = fr[0];
 
     if (i == 0) {
-        d->hist[g] = bf;
+        xst(d->hist + g, bf);
         int flags = 0;
         if (bf <= d->vtr) flags |= 4;  // PT_FLAG_VTR
         if (d->rel_tol > 0.0 && d->window > 0 && g >= d->window && s_old - bf <= d->rel_tol * bf)
             flags |= 1;  // PT_FLAG_CONVERGED
         if (!flags && g >= d->max_gens) flags |= 2;  // PT_FLAG_MAXGEN
-        st->best = best;
-        st->best_f = bf;
+        xsti(&st->best, best);
+        xst(&st->best_f, bf);
         if (flags) {
-            st->flags = flags;
-            st->done = 1;
+            xsti(&st->flags, flags);
+            xsti(&st->done, 1);
         } else {
-            st->gen = g + 1;
+            xsti(&st->gen, g + 1);
         }
         s_stop = flags != 0;
     }
@@ -541,7 +673,7 @@ __device__ __forceinline__ void de_step_body(const BlockDesc* __restrict__ d, do
     }
     double* trow = d->trial + (size_t)i * kStride;
 #pragma unroll
-    for (int j = 0; j < kStride; ++j) trow[j] = y[j];
+    for (int j = 0; j < kStride; ++j) xst(trow + j, y[j]);
 }
 
 __global__ __launch_bounds__(1024) void k_de_step(const BlockDesc* __restrict__ descs) {
@@ -560,6 +692,14 @@ __global__ __launch_bounds__(1024) void k_de_step(const BlockDesc* __restrict__ 
 // trial population by raising the block's ready counter, and a workgroup
 // about to evaluate generation g of a block waits until ready >= g.
 //
+// Synchronisation words live in BlockDesc::sync (kSyncInts ints per block,
+// one 128-byte line per counter): a unit's arrival is counted in its XCD
+// range's counter, the last arrival of a range counts the range in the
+// block counter, and the DE step publishes the ready generation to one copy
+// per XCD range, so no counter or polled word serves more than one XCD's
+// workgroups.  Launches may start at any generation (gen_begin) and run
+// `steps` generations; counters restart at every launch.
+//
 // Progress: every workgroup processes generation g of all its units before
 // any unit of generation g + 1, so the workgroups at the lowest generation
 // only ever wait for DE steps whose units are all finished; with all
@@ -575,7 +715,7 @@ __device__ __forceinline__ bool spin_until_ge(int* p, int want, int* err, uint64
     const uint64_t t0 = wall_clock64();
     for (;;) {
         if (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= want) {
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, PT_ACQ_SCOPE);
             return true;
         }
         if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
@@ -583,13 +723,20 @@ __device__ __forceinline__ bool spin_until_ge(int* p, int want, int* err, uint64
             __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             return false;
         }
-        __builtin_amdgcn_s_sleep(2);
+        __builtin_amdgcn_s_sleep(4);
     }
 }
 
-template <typename T, int S, int CPG, bool MIXED, bool SLOPE>
+// Number of units of block d that fall in XCD range x ([x Ux, (x + 1) Ux)).
+__device__ __forceinline__ int units_in_range(const BlockDesc* d, int x, int Ux, int total_units) {
+    const int ub = d->unit_begin, ue = ub + d->ntiles * d->ngroups;
+    const int rb = x * Ux, re = min(total_units, rb + Ux);
+    return max(0, min(ue, re) - max(ub, rb));
+}
+
+template <typename T, int S, int CPG, int MODE, bool SLOPE>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_fit_persistent(
-    const BlockDesc* __restrict__ descs, int nblk, int total_units, int max_gens, int resident,
+    const BlockDesc* __restrict__ descs, int nblk, int total_units, int steps, int resident,
     int* __restrict__ err, uint64_t spin_ticks) {
     __shared__ double lds[kPersistLds];
     __shared__ int s_ok, s_done, s_last;
@@ -601,7 +748,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 4))
     const int Ux = (total_units + 7) >> 3;
     const int u_begin = xcd * Ux, u_end = min(total_units, u_begin + Ux);
 
-    using V = typename std::conditional<MIXED, float, double>::type;
+    using V = typename std::conditional<MODE == 1, float, double>::type;
     V sv[S];
     bool full = true;
     int valid = S;
@@ -611,16 +758,21 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 4))
         load_lane<V, T, S>(d, (u - d->unit_begin) / d->ngroups, sv, full, valid);
     }
 
-    for (int g = 0; g <= max_gens; ++g) {
+    // step s evaluates generation gen_begin + s of every block (the initial
+    // population when that is 0)
+    for (int step = 0; step < steps; ++step) {
         bool any = false;
         for (int u = u_begin + k; u < u_end; u += Gx) {
             const BlockDesc* __restrict__ d = descs + find_block(descs, nblk, u);
+            const int g = d->gen_begin + step;
+            if (g > d->max_gens) continue;
             const int local = u - d->unit_begin;
             const int tile = local / d->ngroups;
             const int group = local - tile * d->ngroups;
+            int* sync = d->sync;
             __syncthreads();  // everyone is done with the shared flags of the last unit
             if (threadIdx.x == 0) {
-                const bool ok = spin_until_ge(&d->st->ready, g, err, spin_ticks);
+                const bool ok = spin_until_ge(sync + (8 + xcd) * kSyncLine, g, err, spin_ticks);
                 s_ok = ok;
                 s_done = ok ? __hip_atomic_load(&d->st->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 1;
             }
@@ -629,30 +781,63 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 4))
             if (s_done) continue;
             any = true;
             if (!resident) load_lane<V, T, S>(d, tile, sv, full, valid);
-            objective_unit<S, CPG, MIXED, SLOPE>(d, tile, group, sv, full, valid, cs, red);
+            objective_unit<S, CPG, MODE, SLOPE>(d, tile, group, sv, full, valid, cs, red);
             // The workgroup barrier makes every wave's partial stores visible
             // at the XCD's L2; one release fence then publishes them device-wide
-            // before the arrival is counted.
+            // before the arrival is counted.  Arrivals are counted per XCD
+            // range first, so no counter sees more than one XCD's workgroups.
             __syncthreads();
             if (threadIdx.x == 0) {
-                const int units_b = d->ntiles * d->ngroups;
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-                const int old = __hip_atomic_fetch_add(&d->st->arrive, 1, __ATOMIC_RELAXED,
+                // counters restart at every launch (k_de_init / k_sync_reset)
+                const int done_steps = step + 1;
+                const int nx = units_in_range(d, xcd, Ux, total_units);
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, PT_REL_SCOPE);
+                const int old = __hip_atomic_fetch_add(sync + xcd * kSyncLine, 1, __ATOMIC_RELAXED,
                                                        __HIP_MEMORY_SCOPE_AGENT);
-                const bool last = old == units_b * (g + 1) - 1;
-                if (last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                bool last = false;
+                if (old == nx * done_steps - 1) {
+                    int nranges = 0;
+                    for (int x = 0; x < 8; ++x) nranges += units_in_range(d, x, Ux, total_units) > 0;
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, PT_ACQ_SCOPE);
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, PT_REL_SCOPE);
+                    const int old2 = __hip_atomic_fetch_add(sync + 16 * kSyncLine, 1, __ATOMIC_RELAXED,
+                                                            __HIP_MEMORY_SCOPE_AGENT);
+                    last = old2 == nranges * done_steps - 1;
+                    if (last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, PT_ACQ_SCOPE);
+                }
                 s_last = last;
             }
             __syncthreads();
             if (s_last) {
                 de_step_body(d, lds);
                 __syncthreads();
-                if (threadIdx.x == 0)
-                    __hip_atomic_store(&d->st->ready, g + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                if (threadIdx.x == 0) {
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, PT_REL_SCOPE);
+                    for (int x = 0; x < 8; ++x)
+                        if (units_in_range(d, x, Ux, total_units) > 0)
+                            __hip_atomic_store(sync + (8 + x) * kSyncLine, g + 1, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+                }
             }
         }
-        if (!any) return;  // every block of this workgroup has stopped
+        if (!any) return;  // every block of this workgroup is done or past its cap
     }
+}
+
+// Restart the persistent kernel's per-launch counters of every block and
+// set its ready copies to the generation the launch starts from.
+__global__ void k_sync_reset(const BlockDesc* __restrict__ descs) {
+    const BlockDesc* d = descs + blockIdx.x;
+    if (d->sync == nullptr) return;
+    for (int k = threadIdx.x; k < kSyncInts; k += blockDim.x)
+        d->sync[k] = (k >= 8 * kSyncLine && k < 16 * kSyncLine) ? d->gen_begin : 0;
+}
+
+// Initial population of the blocks flagged fresh (BlockDesc::pad0 != 0);
+// the others keep their running state.  Used by the serving loop.
+__global__ void k_de_init_fresh(const BlockDesc* __restrict__ descs) {
+    const BlockDesc* d = descs + blockIdx.x;
+    if (d->pad0) init_block(d);
 }
 
 // ---------------------------------------------------------------------------

@@ -7,7 +7,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <deque>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -113,66 +115,93 @@ int size_class(int64_t n) {
 // ----------------------------------------------------------------- launchers
 using ObjKernel = void (*)(const BlockDesc*, int, int);
 
+// Kernel arithmetic modes (template argument MODE of the kernels).
+enum { kModePoly = 0, kModeMixed = 1, kModePhasor = 2 };
+
+template <typename T, int S, int C, int M>
+ObjKernel pick_slope(bool slope) {
+    return slope ? k_objective<T, S, C, M, true> : k_objective<T, S, C, M, false>;
+}
+
 template <typename T, int S, int C>
-ObjKernel pick_mode(bool mixed, bool slope) {
-    if (mixed) return slope ? k_objective<T, S, C, true, true> : k_objective<T, S, C, true, false>;
-    return slope ? k_objective<T, S, C, false, true> : k_objective<T, S, C, false, false>;
+ObjKernel pick_mode(int mode, bool slope) {
+    if (mode == kModeMixed) return pick_slope<T, S, C, kModeMixed>(slope);
+    if (mode == kModePhasor) return pick_slope<T, S, C, kModePhasor>(slope);
+    return pick_slope<T, S, C, kModePoly>(slope);
 }
 
 template <typename T, int S>
-ObjKernel pick_cpg(int cpg, bool mixed, bool slope) {
+ObjKernel pick_cpg(int cpg, int mode, bool slope) {
     switch (cpg) {
-        case 1: return pick_mode<T, S, 1>(mixed, slope);
-        case 2: return pick_mode<T, S, 2>(mixed, slope);
-        case 4: return pick_mode<T, S, 4>(mixed, slope);
-        default: return pick_mode<T, S, 8>(mixed, slope);
+        case 1: return pick_mode<T, S, 1>(mode, slope);
+        case 2: return pick_mode<T, S, 2>(mode, slope);
+        case 4: return pick_mode<T, S, 4>(mode, slope);
+        default: return pick_mode<T, S, 8>(mode, slope);
     }
 }
 
 template <typename T>
-ObjKernel pick_spl(Geometry g, bool mixed, bool slope) {
+ObjKernel pick_spl(Geometry g, int mode, bool slope) {
     switch (g.spl) {
-        case 4: return pick_cpg<T, 4>(g.cpg, mixed, slope);
-        case 8: return pick_cpg<T, 8>(g.cpg, mixed, slope);
-        case 16: return pick_cpg<T, 16>(g.cpg, mixed, slope);
-        default: return pick_cpg<T, 32>(g.cpg, mixed, slope);
+        case 4: return pick_cpg<T, 4>(g.cpg, mode, slope);
+        case 8: return pick_cpg<T, 8>(g.cpg, mode, slope);
+        case 16: return pick_cpg<T, 16>(g.cpg, mode, slope);
+        default: return pick_cpg<T, 32>(g.cpg, mode, slope);
     }
 }
 
-ObjKernel objective_kernel(int dtype, Geometry g, bool mixed, bool slope) {
-    return dtype == PT_F64 ? pick_spl<double>(g, mixed, slope) : pick_spl<float>(g, mixed, slope);
+ObjKernel objective_kernel(int dtype, Geometry g, int mode, bool slope) {
+    return dtype == PT_F64 ? pick_spl<double>(g, mode, slope) : pick_spl<float>(g, mode, slope);
 }
 
 using PersistKernel = void (*)(const BlockDesc*, int, int, int, int, int*, uint64_t);
 
+template <typename T, int S, int C, int M>
+PersistKernel ppick_slope(bool slope) {
+    return slope ? k_fit_persistent<T, S, C, M, true> : k_fit_persistent<T, S, C, M, false>;
+}
+
 template <typename T, int S, int C>
-PersistKernel ppick_mode(bool mixed, bool slope) {
-    if (mixed) return slope ? k_fit_persistent<T, S, C, true, true> : k_fit_persistent<T, S, C, true, false>;
-    return slope ? k_fit_persistent<T, S, C, false, true> : k_fit_persistent<T, S, C, false, false>;
+PersistKernel ppick_mode(int mode, bool slope) {
+    if (mode == kModeMixed) return ppick_slope<T, S, C, kModeMixed>(slope);
+    if (mode == kModePhasor) return ppick_slope<T, S, C, kModePhasor>(slope);
+    return ppick_slope<T, S, C, kModePoly>(slope);
 }
 
 template <typename T, int S>
-PersistKernel ppick_cpg(int cpg, bool mixed, bool slope) {
+PersistKernel ppick_cpg(int cpg, int mode, bool slope) {
     switch (cpg) {
-        case 1: return ppick_mode<T, S, 1>(mixed, slope);
-        case 2: return ppick_mode<T, S, 2>(mixed, slope);
-        case 4: return ppick_mode<T, S, 4>(mixed, slope);
-        default: return ppick_mode<T, S, 8>(mixed, slope);
+        case 1: return ppick_mode<T, S, 1>(mode, slope);
+        case 2: return ppick_mode<T, S, 2>(mode, slope);
+        case 4: return ppick_mode<T, S, 4>(mode, slope);
+        default: return ppick_mode<T, S, 8>(mode, slope);
     }
 }
 
 template <typename T>
-PersistKernel ppick_spl(Geometry g, bool mixed, bool slope) {
+PersistKernel ppick_spl(Geometry g, int mode, bool slope) {
     switch (g.spl) {
-        case 4: return ppick_cpg<T, 4>(g.cpg, mixed, slope);
-        case 8: return ppick_cpg<T, 8>(g.cpg, mixed, slope);
-        case 16: return ppick_cpg<T, 16>(g.cpg, mixed, slope);
-        default: return ppick_cpg<T, 32>(g.cpg, mixed, slope);
+        case 4: return ppick_cpg<T, 4>(g.cpg, mode, slope);
+        case 8: return ppick_cpg<T, 8>(g.cpg, mode, slope);
+        case 16: return ppick_cpg<T, 16>(g.cpg, mode, slope);
+        default: return ppick_cpg<T, 32>(g.cpg, mode, slope);
     }
 }
 
-PersistKernel persistent_kernel(int dtype, Geometry g, bool mixed, bool slope) {
-    return dtype == PT_F64 ? ppick_spl<double>(g, mixed, slope) : ppick_spl<float>(g, mixed, slope);
+PersistKernel persistent_kernel(int dtype, Geometry g, int mode, bool slope) {
+    return dtype == PT_F64 ? ppick_spl<double>(g, mode, slope) : ppick_spl<float>(g, mode, slope);
+}
+
+// The phasor recurrence drops the cubic term inside a lane chunk and uses a
+// Taylor series for the second-difference rotation; it is exact to 1e-12
+// turns when (S - 1)^3 |f2| / (6 fs^3) <= 1e-12 and the chunk's second
+// difference 2 |b2| <= 1e-2 / (2 pi), with b2 = f1 / (2 fs^2) + f2 m / (2 fs^3)
+// over the block's sample offsets |m| <= n + |ref|.
+bool phasor_ok(int spl, double fs, double span, double f1max, double f2max) {
+    const double a3 = f2max / (6.0 * fs * fs * fs);
+    const double b2 = f1max / (2.0 * fs * fs) + 3.0 * a3 * span;
+    const double s1 = spl - 1;
+    return s1 * s1 * s1 * a3 <= 1e-12 && 2.0 * b2 <= 1e-2 / (2.0 * M_PI);
 }
 
 unsigned pow2_at_least(int v) {
@@ -188,6 +217,7 @@ struct Plan {
     int dtype = PT_F32;
     bool mixed = false;
     bool slope = false;
+    int mode = 0;          // kernel arithmetic: kModePoly / kModeMixed / kModePhasor
     Geometry geo{16, 4};
     int total_units = 0;
     int grid = 0;          // objective workgroups (multiple of 8)
@@ -204,7 +234,7 @@ struct pt_ctx {
     int device = 0;
     int ncu = 0;
     hipStream_t cap_stream = nullptr;
-    DevBuf desc, pop, trial, fpop, partials, hist, state, rec, staging, eval_pop, scratch;
+    DevBuf desc, pop, trial, fpop, partials, hist, state, rec, staging, eval_pop, scratch, sync;
     PinBuf hdesc, hrec, hstate;
     // last fit (for pt_last_population / pt_last_history)
     int last_nblk = 0, last_P = 0, last_maxg = 0;
@@ -217,6 +247,7 @@ struct pt_ctx {
     double total_ms = 0.0;
     // launch mode and the persistent kernel's error flag
     int launch_mode = PT_LAUNCH_AUTO;
+    int fp64_method = PT_FP64_AUTO;
     int last_launch = PT_LAUNCH_GRAPH;
     uint64_t spin_ticks = 0;
     DevBuf errflag;
@@ -358,7 +389,7 @@ int enqueue_generation(pt_ctx* ctx, const Plan& pl, ObjKernel obj, hipStream_t s
 
 int get_graph(pt_ctx* ctx, const Plan& pl, ObjKernel obj, int iters, hipGraphExec_t* out) {
     pt_ctx::GraphKey key{ctx->desc.p, pl.nblk, pl.grid, pl.total_units, pl.geo.spl, pl.geo.cpg, pl.dtype,
-                         (int)pl.mixed, (int)pl.slope, pl.de_threads, pl.de_lds, iters};
+                         pl.mode, (int)pl.slope, pl.de_threads, pl.de_lds, iters};
     auto it = ctx->graphs.find(key);
     if (it != ctx->graphs.end()) {
         *out = it->second;
@@ -404,6 +435,18 @@ int prepare(pt_ctx* ctx, const pt_block* blocks, int nblk, const pt_de_settings*
     pl->slope = slope;
     // geometry from the largest block (one kernel instance per launch)
     pl->geo = choose_geometry(ctx, nmax, P, pl->mixed);
+    pl->mode = pl->mixed ? kModeMixed : kModePoly;
+    if (!pl->mixed && ctx->fp64_method != PT_FP64_POLY) {
+        bool ok = true;
+        for (int b = 0; b < nblk && ok; ++b) {
+            const pt_box& bx = blocks[b].box;
+            const double f1 = std::max(std::fabs(bx.lo[3]), std::fabs(bx.hi[3]));
+            const double f2 = std::max(std::fabs(bx.lo[4]), std::fabs(bx.hi[4]));
+            const double span = (double)blocks[b].n + std::fabs(block_ref(&blocks[b]));
+            ok = phasor_ok(pl->geo.spl, blocks[b].fs, span, f1, f2);
+        }
+        if (ok) pl->mode = kModePhasor;
+    }
     const int tile = kThreads * pl->geo.spl;
     const int groups = (P + pl->geo.cpg - 1) / pl->geo.cpg;
 
@@ -431,6 +474,7 @@ int prepare(pt_ctx* ctx, const pt_block* blocks, int nblk, const pt_de_settings*
         (rc = ctx->partials.ensure(part_elems * sizeof(double))) ||
         (rc = ctx->hist.ensure((size_t)nblk * (de->max_gens + 1) * sizeof(double))) ||
         (rc = ctx->state.ensure((size_t)nblk * sizeof(DeState))) ||
+        (rc = ctx->sync.ensure((size_t)nblk * kSyncInts * sizeof(int))) ||
         (rc = ctx->rec.ensure((size_t)nblk * sizeof(FitRecord))) ||
         (rc = ctx->hdesc.ensure(sizeof(BlockDesc) * nblk)) ||
         (rc = ctx->hrec.ensure((size_t)nblk * sizeof(FitRecord))) ||
@@ -492,7 +536,8 @@ int prepare(pt_ctx* ctx, const pt_block* blocks, int nblk, const pt_de_settings*
         part_off += (size_t)P * ntiles[b];
         d.hist = hist + (size_t)b * (de->max_gens + 1);
         d.st = with_state ? st + b : nullptr;
-        d.result = nullptr;
+        d.sync = with_state ? static_cast<int*>(ctx->sync.p) + (size_t)b * kSyncInts : nullptr;
+        d.gen_begin = 0;
         hd[b] = d;
     }
     HIPCHK(hipMemcpyAsync(ctx->desc.p, hd, sizeof(BlockDesc) * nblk, hipMemcpyHostToDevice, s));
@@ -530,15 +575,15 @@ int run_fit(pt_ctx* ctx, const pt_block* blocks, int nblk, const pt_de_settings*
     void* old_desc = ctx->desc.p;
     if ((rc = prepare(ctx, blocks, nblk, de, s, &pl, true))) return rc;
     if (ctx->desc.p != old_desc) ctx->drop_graphs();
-    ObjKernel obj = objective_kernel(pl.dtype, pl.geo, pl.mixed, pl.slope);
+    ObjKernel obj = objective_kernel(pl.dtype, pl.geo, pl.mode, pl.slope);
     const BlockDesc* d = static_cast<const BlockDesc*>(ctx->desc.p);
 
     // persistent launch: one cooperative grid runs every generation
     bool persistent = false;
     int pgrid = 0, resident = 0;
     PersistKernel pk = nullptr;
-    if (ctx->launch_mode != PT_LAUNCH_GRAPH && !ctx->timing && pl.P <= 256) {
-        pk = persistent_kernel(pl.dtype, pl.geo, pl.mixed, pl.slope);
+    if (ctx->launch_mode == PT_LAUNCH_PERSISTENT && !ctx->timing && pl.P <= 256) {
+        pk = persistent_kernel(pl.dtype, pl.geo, pl.mode, pl.slope);
         int per_cu = 0;
         HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(pk), kThreads,
                                                             0));
@@ -559,9 +604,9 @@ int run_fit(pt_ctx* ctx, const pt_block* blocks, int nblk, const pt_de_settings*
 
     const int iters = de->max_gens + 1;  // evaluation of gen 0 plus max_gens generations
     if (persistent) {
-        int nb = nblk, tu = pl.total_units, mg = de->max_gens;
+        int nb = nblk, tu = pl.total_units, steps = de->max_gens + 1;
         uint64_t ticks = ctx->spin_ticks;
-        void* args[] = {&d, &nb, &tu, &mg, &resident, &err, &ticks};
+        void* args[] = {&d, &nb, &tu, &steps, &resident, &err, &ticks};
         hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(pk), dim3(pgrid), dim3(kThreads),
                                                   args, 0, s);
         if (e != hipSuccess) {
@@ -671,7 +716,8 @@ void pt_ctx_destroy(pt_ctx* ctx) {
         (void)hipEventDestroy(pr.second);
     }
     DevBuf* bufs[] = {&ctx->desc,    &ctx->pop,      &ctx->trial,   &ctx->fpop,  &ctx->partials, &ctx->hist,
-                      &ctx->state,   &ctx->rec,      &ctx->staging, &ctx->eval_pop, &ctx->scratch, &ctx->errflag};
+                      &ctx->state,   &ctx->rec,      &ctx->staging, &ctx->eval_pop, &ctx->scratch, &ctx->errflag,
+                      &ctx->sync};
     for (DevBuf* b : bufs) b->release();
     ctx->hdesc.release();
     ctx->hrec.release();
@@ -717,7 +763,21 @@ static int eval_setup(pt_ctx* ctx, const pt_block* block, const double* pop, int
     const BlockDesc* hd = static_cast<const BlockDesc*>(ctx->hdesc.p);
     HIPCHK(hipMemcpy2DAsync(hd[0].trial, kStride * sizeof(double), pop, PT_NSLOT * sizeof(double),
                             PT_NSLOT * sizeof(double), P, hipMemcpyDeviceToDevice, s));
-    *obj = objective_kernel(pl->dtype, pl->geo, pl->mixed, pl->slope);
+    if (pl->mode == kModePhasor) {
+        // an arbitrary population may leave the box: decide on its own f1, f2
+        std::vector<double> hp((size_t)P * PT_NSLOT);
+        HIPCHK(hipMemcpyAsync(hp.data(), pop, hp.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        double f1 = 0.0, f2 = 0.0;
+        for (int p = 0; p < P; ++p) {
+            f1 = std::max(f1, std::fabs(hp[(size_t)p * PT_NSLOT + 3]));
+            f2 = std::max(f2, std::fabs(hp[(size_t)p * PT_NSLOT + 4]));
+        }
+        const double span = (double)block->n + std::fabs(block_ref(block));
+        if (!(std::isfinite(f1) && std::isfinite(f2) && phasor_ok(pl->geo.spl, block->fs, span, f1, f2)))
+            pl->mode = kModePoly;
+    }
+    *obj = objective_kernel(pl->dtype, pl->geo, pl->mode, pl->slope);
     return PT_OK;
 }
 
@@ -866,6 +926,13 @@ int pt_ctx_set_launch_mode(pt_ctx* ctx, int mode) {
     return PT_OK;
 }
 
+int pt_ctx_set_fp64_method(pt_ctx* ctx, int method) {
+    if (!ctx) return fail(PT_EINVAL, "ctx is null");
+    if (method != PT_FP64_AUTO && method != PT_FP64_POLY) return fail(PT_EINVAL, "fp64 method %d", method);
+    ctx->fp64_method = method;
+    return PT_OK;
+}
+
 int pt_ctx_last_launch(pt_ctx* ctx, int* mode) {
     if (!ctx || !mode) return fail(PT_EINVAL, "ctx / mode is null");
     *mode = ctx->last_launch;
@@ -960,6 +1027,393 @@ int pt_ctx_autotune(pt_ctx* ctx, int64_t n, int P, int precision, void* hip_stre
     ctx->tuned[std::make_tuple(size_class(n), P, precision == PT_PREC_MIXED ? 1 : 0)] = best;
     if (best_spl) *best_spl = best.spl;
     if (best_cpg) *best_cpg = best.cpg;
+    return PT_OK;
+}
+
+}  // extern "C"
+
+// ==================================================================== server
+// Continuous batching of arriving blocks.  Each admitted block owns a device
+// slot (samples, population, partials, DE state).  A scheduler step runs
+// `gens_per_step` generations of every active slot in shared launches (one
+// objective grid over all slots' work units, then every slot's DE step);
+// blocks admitted while others are running join at the next step, and a
+// block that meets its stop rule is retired at the end of the step in which
+// it stopped.  A track's next block waits for its previous fit and starts
+// from it (warm start): the previous phase is re-expanded about the new
+// block's reference time (Sec. 3.1.1 running range) and the search box is
+// the block's own box narrowed by `warm_narrow` around that prediction.
+struct pt_server {
+    struct Slot {
+        bool active = false, fresh = false;
+        int track = -1;
+        uint64_t ticket = 0;
+        int gen = 0;
+        int warm = 0;
+        double t_submit = 0.0;
+        size_t bytes = 0;
+        pt_block blk{};
+        DevBuf samples, pop, trial, fpop, partials, hist, state;
+    };
+    struct Pending {
+        uint64_t ticket;
+        int track;
+        double t_submit;
+        pt_block blk;
+        std::vector<char> host;
+    };
+    struct Track {
+        bool busy = false, has_fit = false;
+        pt_fit last{};
+        int64_t n = 0;
+        double fs = 0.0, ref = 0.0;
+    };
+    pt_ctx* ctx = nullptr;
+    pt_server_config cfg{};
+    Geometry geo{16, 4};
+    int mode = 0;  // kernel arithmetic, fixed for the server's lifetime
+    std::vector<Slot> slots;
+    std::deque<Pending> pending;
+    std::map<int, Track> tracks;
+    std::deque<pt_server_result> done;
+    size_t used_bytes = 0;
+    uint64_t next_ticket = 1;
+    DevBuf desc, rec;
+    PinBuf hdesc, hrec, hstate;
+    std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+    double clock() const {
+        return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+};
+
+namespace {
+
+// Phase of the previous fit re-expanded about the new block's reference
+// time, dt seconds later: phi0 + 2 pi (f0 dt + f1 dt^2/2 + f2 dt^3/6),
+// f0 + f1 dt + f2 dt^2/2, f1 + f2 dt, f2; amplitude A + Adot dt.
+void predict(const double* c, double dt, double* out) {
+    const double two_pi = 2.0 * M_PI;
+    double turns = c[2] * dt + c[3] * dt * dt / 2.0 + c[4] * dt * dt * dt / 6.0;
+    turns -= std::floor(turns);
+    double ph = std::fmod(c[1] + two_pi * turns, two_pi);
+    if (ph < 0) ph += two_pi;
+    out[0] = c[0] + c[5] * dt;
+    out[1] = ph;
+    out[2] = c[2] + c[3] * dt + c[4] * dt * dt / 2.0;
+    out[3] = c[3] + c[4] * dt;
+    out[4] = c[4];
+    out[5] = c[5];
+}
+
+size_t slot_bytes(const pt_block& b, int P, int max_gens, int tile) {
+    const size_t ntiles = (size_t)((b.n + tile - 1) / tile);
+    return (size_t)b.n * (b.dtype == PT_F64 ? 8 : 4) + (size_t)P * (2 * kStride + 1) * 8 + (size_t)P * ntiles * 8 +
+           (size_t)(max_gens + 1) * 8 + sizeof(DeState);
+}
+
+int server_admit(pt_server* sv, hipStream_t s) {
+    const int P = sv->cfg.de.pop;
+    const int tile = kThreads * sv->geo.spl;
+    for (auto it = sv->pending.begin(); it != sv->pending.end();) {
+        pt_server::Track& tr = sv->tracks[it->track];
+        if (tr.busy) {
+            ++it;
+            continue;
+        }
+        int free = -1;
+        for (int k = 0; k < (int)sv->slots.size(); ++k)
+            if (!sv->slots[k].active) {
+                free = k;
+                break;
+            }
+        const size_t need = slot_bytes(it->blk, P, sv->cfg.de.max_gens, tile);
+        if (free < 0 || sv->used_bytes + need > sv->cfg.hbm_budget_bytes) break;  // no room now
+        pt_server::Slot& sl = sv->slots[free];
+        const size_t sbytes = (size_t)it->blk.n * (it->blk.dtype == PT_F64 ? 8 : 4);
+        const size_t ntiles = (size_t)((it->blk.n + tile - 1) / tile);
+        int rc;
+        if ((rc = sl.samples.ensure(sbytes)) || (rc = sl.pop.ensure((size_t)P * kStride * 8)) ||
+            (rc = sl.trial.ensure((size_t)P * kStride * 8)) || (rc = sl.fpop.ensure((size_t)P * 8)) ||
+            (rc = sl.partials.ensure((size_t)P * ntiles * 8)) ||
+            (rc = sl.hist.ensure((size_t)(sv->cfg.de.max_gens + 1) * 8)) ||
+            (rc = sl.state.ensure(sizeof(DeState))))
+            return rc;
+        HIPCHK(hipMemcpyAsync(sl.samples.p, it->host.data(), sbytes, hipMemcpyHostToDevice, s));
+        sl.blk = it->blk;
+        sl.blk.samples = sl.samples.p;
+        sl.blk.on_device = 1;
+        sl.blk.ref = block_ref(&it->blk);
+        sl.warm = 0;
+        if (tr.has_fit && sv->cfg.warm_narrow > 0.0 && tr.fs == it->blk.fs) {
+            const double dt = ((double)tr.n - tr.ref) / tr.fs + sl.blk.ref / sl.blk.fs;
+            double pred[PT_NSLOT];
+            predict(tr.last.coef, dt, pred);
+            for (int j = 0; j < PT_NSLOT; ++j) {
+                const double half = 0.5 * (it->blk.box.hi[j] - it->blk.box.lo[j]);
+                if (half > 0) {
+                    sl.blk.box.lo[j] = pred[j] - sv->cfg.warm_narrow * half;
+                    sl.blk.box.hi[j] = pred[j] + sv->cfg.warm_narrow * half;
+                }
+            }
+            sl.warm = 1;
+        }
+        sl.active = true;
+        sl.fresh = true;
+        sl.track = it->track;
+        sl.ticket = it->ticket;
+        sl.t_submit = it->t_submit;
+        sl.gen = 0;
+        sl.bytes = need;
+        sv->used_bytes += need;
+        tr.busy = true;
+        tr.n = it->blk.n;
+        tr.fs = it->blk.fs;
+        tr.ref = sl.blk.ref;
+        // the host copy can go once the stream has consumed it
+        HIPCHK(hipStreamSynchronize(s));
+        it = sv->pending.erase(it);
+    }
+    return PT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pt_server_create(pt_ctx* ctx, const pt_server_config* cfg, pt_server** out) {
+    if (!ctx || !cfg || !out) return fail(PT_EINVAL, "ctx / cfg / out is null");
+    *out = nullptr;
+    int rc = check_de(&cfg->de);
+    if (rc) return rc;
+    if (cfg->de.pop > 256) return fail(PT_EINVAL, "server population %d > 256", cfg->de.pop);
+    if (cfg->max_slots < 1 || cfg->max_slots > 1024) return fail(PT_EINVAL, "max_slots %d", cfg->max_slots);
+    if (cfg->gens_per_step < 1 || cfg->gens_per_step > 100000)
+        return fail(PT_EINVAL, "gens_per_step %d", cfg->gens_per_step);
+    if (cfg->max_pending < 1) return fail(PT_EINVAL, "max_pending %d", cfg->max_pending);
+    if (!(cfg->warm_narrow >= 0.0 && cfg->warm_narrow <= 1.0)) return fail(PT_EINVAL, "warm_narrow outside [0, 1]");
+    if ((cfg->spl || cfg->cpg) && !(spl_ok(cfg->spl) && cpg_ok(cfg->cpg)))
+        return fail(PT_EINVAL, "unsupported geometry (%d, %d)", cfg->spl, cfg->cpg);
+    std::unique_ptr<pt_server> sv(new (std::nothrow) pt_server());
+    if (!sv) return fail(PT_ENOMEM, "out of host memory");
+    sv->ctx = ctx;
+    sv->cfg = *cfg;
+    sv->geo = cfg->spl ? Geometry{cfg->spl, cfg->cpg} : default_geometry(400000, cfg->de.pop);
+    // one arithmetic for every block of the server, so that a block's result
+    // never depends on which blocks share its steps
+    sv->mode = cfg->de.precision == PT_PREC_MIXED ? kModeMixed
+                                                  : (ctx->fp64_method == PT_FP64_POLY ? kModePoly : kModePhasor);
+    sv->slots.resize(cfg->max_slots);
+    *out = sv.release();
+    return PT_OK;
+}
+
+void pt_server_destroy(pt_server* sv) {
+    if (!sv) return;
+    (void)hipSetDevice(sv->ctx->device);
+    (void)hipDeviceSynchronize();
+    for (auto& sl : sv->slots) {
+        DevBuf* b[] = {&sl.samples, &sl.pop, &sl.trial, &sl.fpop, &sl.partials, &sl.hist, &sl.state};
+        for (DevBuf* x : b) x->release();
+    }
+    sv->desc.release();
+    sv->rec.release();
+    sv->hdesc.release();
+    sv->hrec.release();
+    sv->hstate.release();
+    delete sv;
+}
+
+double pt_server_clock(pt_server* sv) { return sv ? sv->clock() : 0.0; }
+
+int pt_server_submit(pt_server* sv, int32_t track, const pt_block* block, uint64_t* ticket) {
+    if (!sv) return fail(PT_EINVAL, "server is null");
+    int rc = check_block(block, 0);
+    if (rc) return rc;
+    if (sv->pending.size() >= (size_t)sv->cfg.max_pending) return fail(PT_EBUSY, "pending queue full");
+    const int tile = kThreads * sv->geo.spl;
+    if (slot_bytes(*block, sv->cfg.de.pop, sv->cfg.de.max_gens, tile) > sv->cfg.hbm_budget_bytes)
+        return fail(PT_EINVAL, "block needs more than the whole HBM budget");
+    if (sv->mode == kModePhasor) {
+        // warm boxes move the f1 centre by f2 dt; check with generous margins
+        const pt_box& bx = block->box;
+        const double f1 = 2.0 * std::max(std::fabs(bx.lo[3]), std::fabs(bx.hi[3])) + 1.0;
+        const double f2 = 2.0 * std::max(std::fabs(bx.lo[4]), std::fabs(bx.hi[4]));
+        const double span = 2.0 * ((double)block->n + std::fabs(block_ref(block)));
+        if (!phasor_ok(sv->geo.spl, block->fs, span, f1, f2))
+            return fail(PT_EINVAL, "block needs the per-sample FP64 path: create the server with PT_FP64_POLY");
+    }
+    pt_server::Pending pd;
+    pd.ticket = sv->next_ticket++;
+    pd.track = track;
+    pd.t_submit = sv->clock();
+    pd.blk = *block;
+    const size_t bytes = (size_t)block->n * (block->dtype == PT_F64 ? 8 : 4);
+    pd.host.resize(bytes);
+    if (block->on_device) {
+        HIPCHK(hipSetDevice(sv->ctx->device));
+        HIPCHK(hipMemcpy(pd.host.data(), block->samples, bytes, hipMemcpyDeviceToHost));
+    } else {
+        std::memcpy(pd.host.data(), block->samples, bytes);
+    }
+    pd.blk.samples = nullptr;
+    sv->pending.push_back(std::move(pd));
+    if (ticket) *ticket = sv->pending.back().ticket;
+    return PT_OK;
+}
+
+int pt_server_step(pt_server* sv, void* hip_stream, int32_t* n_active, int32_t* n_pending) {
+    if (!sv) return fail(PT_EINVAL, "server is null");
+    pt_ctx* ctx = sv->ctx;
+    HIPCHK(hipSetDevice(ctx->device));
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    int rc = server_admit(sv, s);
+    if (rc) return rc;
+    std::vector<int> act;
+    for (int k = 0; k < (int)sv->slots.size(); ++k)
+        if (sv->slots[k].active) act.push_back(k);
+    const int nb = (int)act.size();
+    if (n_pending) *n_pending = (int)sv->pending.size();
+    if (nb == 0) {
+        if (n_active) *n_active = 0;
+        return PT_OK;
+    }
+    const int P = sv->cfg.de.pop;
+    const pt_de_settings& de = sv->cfg.de;
+    const int tile = kThreads * sv->geo.spl;
+    const int groups = (P + sv->geo.cpg - 1) / sv->geo.cpg;
+    if ((rc = sv->desc.ensure(sizeof(BlockDesc) * nb)) || (rc = sv->hdesc.ensure(sizeof(BlockDesc) * nb)) ||
+        (rc = sv->rec.ensure(sizeof(FitRecord) * nb)) || (rc = sv->hrec.ensure(sizeof(FitRecord) * nb)) ||
+        (rc = sv->hstate.ensure(sizeof(DeState) * nb)))
+        return rc;
+    BlockDesc* hd = static_cast<BlockDesc*>(sv->hdesc.p);
+    int units = 0, dtype = -1;
+    bool slope = false, any_fresh = false;
+    for (int q = 0; q < nb; ++q) {
+        pt_server::Slot& sl = sv->slots[act[q]];
+        const pt_block& B = sl.blk;
+        if (dtype < 0) dtype = B.dtype;
+        if (B.dtype != dtype) return fail(PT_EINVAL, "server blocks must share one sample dtype");
+        BlockDesc d;
+        std::memset(&d, 0, sizeof d);
+        d.samples = B.samples;
+        d.n = B.n;
+        d.fs = B.fs;
+        d.ref = B.ref;
+        d.dtype = B.dtype;
+        d.P = P;
+        int D = 0;
+        for (int j = 0; j < kSlots; ++j) {
+            d.lo[j] = B.box.lo[j];
+            d.hi[j] = B.box.hi[j];
+            if (B.box.lo[j] < B.box.hi[j]) d.act[D++] = j;
+        }
+        if (B.box.lo[5] != 0.0 || B.box.hi[5] != 0.0) slope = true;
+        d.D = D;
+        d.ntiles = (int)((B.n + tile - 1) / tile);
+        d.ngroups = groups;
+        d.unit_begin = units;
+        units += d.ntiles * groups;
+        d.window = de.window;
+        d.max_gens = de.max_gens;
+        d.F = de.F;
+        d.CR = de.CR;
+        d.vtr = de.vtr;
+        d.rel_tol = de.rel_tol;
+        d.seed = de.seed;
+        d.stream = B.stream;
+        d.pop = static_cast<double*>(sl.pop.p);
+        d.trial = static_cast<double*>(sl.trial.p);
+        d.fpop = static_cast<double*>(sl.fpop.p);
+        d.partials = static_cast<double*>(sl.partials.p);
+        d.hist = static_cast<double*>(sl.hist.p);
+        d.st = static_cast<DeState*>(sl.state.p);
+        d.sync = nullptr;
+        d.gen_begin = sl.gen;
+        d.pad0 = sl.fresh ? 1 : 0;  // k_de_init initialises only fresh slots
+        any_fresh = any_fresh || sl.fresh;
+        hd[q] = d;
+    }
+    const int mode = sv->mode;
+    HIPCHK(hipMemcpyAsync(sv->desc.p, hd, sizeof(BlockDesc) * nb, hipMemcpyHostToDevice, s));
+    const BlockDesc* dd = static_cast<const BlockDesc*>(sv->desc.p);
+    const unsigned de_threads = pow2_at_least(P);
+    const size_t de_lds = (size_t)P * kSlots * 8 + (size_t)de_threads * (8 + 8 + 4);
+    if (any_fresh) {
+        hipLaunchKernelGGL(k_de_init_fresh, dim3(nb), dim3(de_threads), 0, s, dd);
+        HIPCHK(hipGetLastError());
+    }
+    ObjKernel obj = objective_kernel(dtype, sv->geo, mode, slope);
+    const int grid = (units + 7) / 8 * 8;
+    for (int k = 0; k < sv->cfg.gens_per_step; ++k) {
+        hipLaunchKernelGGL(obj, dim3(grid), dim3(kThreads), 0, s, dd, nb, units);
+        hipLaunchKernelGGL(k_de_step, dim3(nb), dim3(de_threads), de_lds, s, dd);
+    }
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(k_finalize, dim3(nb), dim3(64), 0, s, dd, static_cast<FitRecord*>(sv->rec.p));
+    HIPCHK(hipGetLastError());
+    DeState* hst = static_cast<DeState*>(sv->hstate.p);
+    for (int q = 0; q < nb; ++q)
+        HIPCHK(hipMemcpyAsync(hst + q, sv->slots[act[q]].state.p, sizeof(DeState), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(sv->hrec.p, sv->rec.p, sizeof(FitRecord) * nb, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const double now = sv->clock();
+    const FitRecord* r = static_cast<const FitRecord*>(sv->hrec.p);
+    int still = 0;
+    for (int q = 0; q < nb; ++q) {
+        pt_server::Slot& sl = sv->slots[act[q]];
+        sl.fresh = false;
+        sl.gen = hst[q].gen;
+        if (!hst[q].done) {
+            ++still;
+            continue;
+        }
+        pt_server_result res;
+        std::memset(&res, 0, sizeof res);
+        res.ticket = sl.ticket;
+        res.track = sl.track;
+        res.warm = sl.warm;
+        res.t_submit = sl.t_submit;
+        res.t_done = now;
+        res.box = sl.blk.box;
+        pt_fit& f = res.fit;
+        for (int j = 0; j < PT_NSLOT; ++j) f.coef[j] = r[q].x[j];
+        f.objective = r[q].f;
+        f.generations = r[q].gens;
+        f.flags = r[q].flags;
+        f.ref = sl.blk.ref;
+        f.t_left = (0.0 - f.ref) / sl.blk.fs;
+        f.t_right = ((double)sl.blk.n - f.ref) / sl.blk.fs;
+        derive(&f);
+        sv->done.push_back(res);
+        pt_server::Track& tr = sv->tracks[sl.track];
+        tr.busy = false;
+        tr.has_fit = true;
+        tr.last = f;
+        sv->used_bytes -= sl.bytes;
+        sl.active = false;
+    }
+    if (n_active) *n_active = still;
+    return PT_OK;
+}
+
+int pt_server_poll(pt_server* sv, pt_server_result* out, int32_t max, int32_t* n_out) {
+    if (!sv || (!out && max > 0) || max < 0) return fail(PT_EINVAL, "server / out is null or max < 0");
+    int k = 0;
+    while (k < max && !sv->done.empty()) {
+        out[k++] = sv->done.front();
+        sv->done.pop_front();
+    }
+    if (n_out) *n_out = k;
+    return PT_OK;
+}
+
+int pt_server_stats(pt_server* sv, int32_t* active, int32_t* pending, uint64_t* used_bytes) {
+    if (!sv) return fail(PT_EINVAL, "server is null");
+    int a = 0;
+    for (auto& sl : sv->slots) a += sl.active;
+    if (active) *active = a;
+    if (pending) *pending = (int)sv->pending.size();
+    if (used_bytes) *used_bytes = sv->used_bytes;
     return PT_OK;
 }
 

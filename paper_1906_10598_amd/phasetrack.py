@@ -22,6 +22,7 @@ PT_F32, PT_F64 = 0, 1
 PT_PREC_FP64, PT_PREC_MIXED = 0, 1
 PT_FLAG_CONVERGED, PT_FLAG_MAXGEN, PT_FLAG_VTR, PT_FLAG_AT_BOUND = 1, 2, 4, 8
 PT_LAUNCH_AUTO, PT_LAUNCH_GRAPH, PT_LAUNCH_PERSISTENT = 0, 1, 2
+PT_FP64_AUTO, PT_FP64_POLY = 0, 1
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libphasetrack.so")
 
@@ -84,6 +85,32 @@ class pt_fit(ctypes.Structure):
         return {k: (list(getattr(self, k)) if k == "coef" else getattr(self, k)) for k, _ in self._fields_}
 
 
+class pt_server_config(ctypes.Structure):
+    _fields_ = [
+        ("max_slots", ctypes.c_int32),
+        ("gens_per_step", ctypes.c_int32),
+        ("max_pending", ctypes.c_int32),
+        ("spl", ctypes.c_int32),
+        ("cpg", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("warm_narrow", ctypes.c_double),
+        ("hbm_budget_bytes", ctypes.c_uint64),
+        ("de", pt_de_settings),
+    ]
+
+
+class pt_server_result(ctypes.Structure):
+    _fields_ = [
+        ("ticket", ctypes.c_uint64),
+        ("track", ctypes.c_int32),
+        ("warm", ctypes.c_int32),
+        ("t_submit", ctypes.c_double),
+        ("t_done", ctypes.c_double),
+        ("box", pt_box),
+        ("fit", pt_fit),
+    ]
+
+
 _lib = None
 _DP = ctypes.POINTER(ctypes.c_double)
 _VP = ctypes.c_void_p
@@ -110,7 +137,16 @@ def _signatures(L):
         "pt_los_accel": ([ctypes.POINTER(pt_fit), ctypes.c_double, ctypes.c_double, ctypes.c_double, i32,
                           _DP], i32),
         "pt_time_objective": ([_CTX, ctypes.POINTER(pt_block), _VP, i32, i32, i32, _VP, _DP], i32),
+        "pt_server_create": ([_CTX, ctypes.POINTER(pt_server_config), ctypes.POINTER(_CTX)], i32),
+        "pt_server_destroy": ([_CTX], None),
+        "pt_server_submit": ([_CTX, i32, ctypes.POINTER(pt_block), ctypes.POINTER(ctypes.c_uint64)], i32),
+        "pt_server_step": ([_CTX, _VP, ctypes.POINTER(i32), ctypes.POINTER(i32)], i32),
+        "pt_server_poll": ([_CTX, ctypes.POINTER(pt_server_result), i32, ctypes.POINTER(i32)], i32),
+        "pt_server_stats": ([_CTX, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_uint64)],
+                            i32),
+        "pt_server_clock": ([_CTX], ctypes.c_double),
         "pt_ctx_set_launch_mode": ([_CTX, i32], i32),
+        "pt_ctx_set_fp64_method": ([_CTX, i32], i32),
         "pt_ctx_last_launch": ([_CTX, ctypes.POINTER(i32)], i32),
         "pt_ctx_set_timing": ([_CTX, i32], i32),
         "pt_ctx_kernel_stats": ([_CTX, ctypes.POINTER(i64), _DP], i32),
@@ -235,8 +271,65 @@ def pt_time_objective(ctx, block: pt_block, pop_ptr: int, P: int, precision: int
     return ms.value
 
 
+def pt_server_create(ctx, cfg: pt_server_config):
+    h = _CTX()
+    _check(lib().pt_server_create(ctx, ctypes.byref(cfg), ctypes.byref(h)), "pt_server_create")
+    return h
+
+
+def pt_server_destroy(srv) -> None:
+    lib().pt_server_destroy(srv)
+
+
+def pt_server_submit(srv, track: int, block: pt_block):
+    """Returns the ticket, or None when the queue is full (PT_EBUSY)."""
+    t = ctypes.c_uint64()
+    rc = lib().pt_server_submit(srv, track, ctypes.byref(block), ctypes.byref(t))
+    if rc == PT_EBUSY:
+        return None
+    _check(rc, "pt_server_submit")
+    return t.value
+
+
+def pt_server_step(srv, stream=None):
+    a, p = ctypes.c_int(), ctypes.c_int()
+    _check(lib().pt_server_step(srv, stream, ctypes.byref(a), ctypes.byref(p)), "pt_server_step")
+    return a.value, p.value
+
+
+def pt_server_poll(srv, max_results: int = 256):
+    out = (pt_server_result * max_results)()
+    n = ctypes.c_int()
+    _check(lib().pt_server_poll(srv, out, max_results, ctypes.byref(n)), "pt_server_poll")
+    return [out[k] for k in range(n.value)]
+
+
+def pt_server_stats(srv):
+    a, p, u = ctypes.c_int(), ctypes.c_int(), ctypes.c_uint64()
+    _check(lib().pt_server_stats(srv, ctypes.byref(a), ctypes.byref(p), ctypes.byref(u)), "pt_server_stats")
+    return a.value, p.value, u.value
+
+
+def pt_server_clock(srv) -> float:
+    return lib().pt_server_clock(srv)
+
+
+def make_server_config(de: pt_de_settings, max_slots: int = 64, gens_per_step: int = 32,
+                       max_pending: int = 4096, spl: int = 16, cpg: int = 4, warm_narrow: float = 0.7,
+                       hbm_budget_bytes: int = 64 << 30) -> pt_server_config:
+    c = pt_server_config()
+    c.max_slots, c.gens_per_step, c.max_pending = max_slots, gens_per_step, max_pending
+    c.spl, c.cpg, c.warm_narrow, c.hbm_budget_bytes = spl, cpg, warm_narrow, hbm_budget_bytes
+    c.de = de
+    return c
+
+
 def pt_ctx_set_launch_mode(ctx, mode: int):
     _check(lib().pt_ctx_set_launch_mode(ctx, mode), "pt_ctx_set_launch_mode")
+
+
+def pt_ctx_set_fp64_method(ctx, method: int):
+    _check(lib().pt_ctx_set_fp64_method(ctx, method), "pt_ctx_set_fp64_method")
 
 
 def pt_ctx_last_launch(ctx) -> int:

@@ -119,6 +119,43 @@ def test_noise_free_signal_vanishes_at_truth():
     assert got[0] < 1e-18 and want[0] < 1e-18
 
 
+@pytest.mark.parametrize("case", ["tiny", "paper", "ragged"])
+def test_fp64_per_sample_path(case):
+    # the same checks with the per-sample cosine path forced (the default
+    # FP64 path uses the phasor recurrence when it is exact to 1e-12 turns)
+    c = ctx()
+    ptk.pt_ctx_set_fp64_method(c.handle, ptk.PT_FP64_POLY)
+    try:
+        if case == "tiny":
+            b = synth.config0(3)
+            pop = random_population(np.random.default_rng(21), b.lo, b.hi, 32, far=4)
+        elif case == "paper":
+            b = synth.config1(4)
+            pop = random_population(np.random.default_rng(22), b.lo, b.hi, 40, far=3)
+        else:
+            b = synth.config1(5, n=65536 + 33)
+            pop = random_population(np.random.default_rng(23), b.lo, b.hi, 13, far=2)
+        _check(b, pop)
+    finally:
+        ptk.pt_ctx_set_fp64_method(c.handle, ptk.PT_FP64_AUTO)
+
+
+def test_large_frequency_acceleration_falls_back_to_per_sample_path():
+    # at fs = 200 Hz with |f2| up to 40 Hz/s^2 the dropped cubic term would
+    # exceed 1e-12 turns, so the phasor path must not be used; values still
+    # match the oracle
+    rng = np.random.default_rng(31)
+    n, fs = 5000, 200.0
+    t = (np.arange(n) - n / 2) / fs
+    s = np.cos(0.3 + 2 * np.pi * (17.0 * t + 3.0 * t * t / 2 + 30.0 * t ** 3 / 6)) + rng.normal(0, 0.3, n)
+    x = np.array([1.0, 0.3, 17.0, 3.0, 30.0, 0.0])
+    lo, hi = x - [0.2, 3, 1, 1, 10, 0], x + [0.2, 3, 1, 1, 10, 0]
+    b = synth.Block(s, fs, n / 2, x, lo, hi, synth.DESettings(16, 1), 0.3, name="big-f2")
+    pop = random_population(rng, lo, hi, 16)
+    pop[0] = x
+    _check(b, pop)
+
+
 def test_mixed_precision_error_stated():
     b = synth.config1(0)
     rng = np.random.default_rng(12)

@@ -1,0 +1,144 @@
+"""The serving loop (continuous batching with warm starts) on the GPU.
+
+  * a block's result is the same alone and in the mix: every track's blocks
+    fitted by a server that sees only that track equal, bit for bit, the
+    results of a server that interleaves all tracks;
+  * a served fit equals pt_fit_block on the same block with the box the
+    server used (same kernels, same geometry), and its reported objective
+    matches the FP64 oracle;
+  * warm starts: the next block of a track starts from the previous fit
+    re-expanded to its centre, recovers f0 and needs fewer generations;
+  * admission under a tiny HBM budget still completes every block with the
+    same results; a full queue answers PT_EBUSY.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import assert_chi2_close, ctx
+from paper_1906_10598_amd import phasetrack as ptk
+
+pytestmark = pytest.mark.gpu
+
+GENS = 800
+
+
+def _stream(ntracks=3, nblocks=8, seed=0):
+    return synth.config4_stream(seed=seed, ntracks=ntracks, nblocks=nblocks, lengths=(100_000, 200_000))
+
+
+def _settings():
+    return ptk.make_settings(pop=40, max_gens=GENS, F=0.5, CR=0.9, seed=0x19061059 ^ 0xDE,
+                             rel_tol=1e-9, window=50)
+
+
+def _blk(item):
+    b = item["block"]
+    return ptk.make_block(__import__("torch").from_numpy(b.samples), b.fs, b.lo, b.hi, ref=b.ref,
+                          stream=b.stream)
+
+
+def _serve(items, budget=64 << 30, slots=16, gens_per_step=32, max_pending=4096):
+    c = ctx()
+    srv = ptk.pt_server_create(c.handle, ptk.make_server_config(
+        _settings(), max_slots=slots, gens_per_step=gens_per_step, max_pending=max_pending,
+        hbm_budget_bytes=budget))
+    try:
+        tickets = {}
+        for it in items:
+            t = ptk.pt_server_submit(srv, it["track"], _blk(it))
+            assert t is not None
+            tickets[t] = (it["track"], it["seq"])
+        out = {}
+        max_active = 0
+        for _ in range(10000):
+            a, p = ptk.pt_server_step(srv, ptk.current_stream())
+            max_active = max(max_active, a)
+            for r in ptk.pt_server_poll(srv):
+                out[tickets[r.ticket]] = r
+            if a == 0 and p == 0:
+                break
+        assert len(out) == len(items)
+        return out, max_active
+    finally:
+        ptk.pt_server_destroy(srv)
+
+
+def _key(r):
+    return list(r.fit.coef) + [r.fit.objective, r.fit.generations, r.fit.flags]
+
+
+def test_alone_equals_mix():
+    items = _stream()
+    mix, max_active = _serve(items)
+    assert max_active >= 2  # blocks of several tracks really shared steps
+    for tr in sorted({it["track"] for it in items}):
+        alone, _ = _serve([it for it in items if it["track"] == tr])
+        for k, r in alone.items():
+            assert _key(r) == _key(mix[k]), k
+    print(f"[server] {len(items)} blocks, up to {max_active} resident together; alone == mix", flush=True)
+
+
+def test_served_fit_equals_fit_block_and_oracle():
+    items = _stream(ntracks=2, nblocks=5, seed=1)
+    res, _ = _serve(items)
+    c = ctx()
+    ptk.pt_ctx_set_tile(c.handle, 16, 4)
+    try:
+        for it in items:
+            r = res[(it["track"], it["seq"])]
+            b = it["block"]
+            blk = _blk(it)
+            blk.box = r.box
+            f = c.fit_block(blk, _settings())
+            assert list(f.coef) == list(r.fit.coef) and f.objective == r.fit.objective
+            assert f.generations == r.fit.generations
+            chi = oracle.chi2(b.samples.astype(np.float64), b.fs, b.ref, list(r.fit.coef))
+            assert_chi2_close([r.fit.objective], [chi], b.n)
+    finally:
+        ptk.pt_ctx_set_tile(c.handle, 0, 0)
+
+
+def test_warm_start_tracks_the_phase():
+    items = _stream(ntracks=2, nblocks=8, seed=2)
+    res, _ = _serve(items)
+    cold, warm = [], []
+    for it in items:
+        r = res[(it["track"], it["seq"])]
+        b = it["block"]
+        err = abs(r.fit.coef[2] - b.truth[2])
+        sig = np.sqrt(6.0) * b.sigma / (np.pi * b.truth[0] * (b.n / b.fs) * np.sqrt(b.n))
+        assert err < 30 * sig, (it["track"], it["seq"], err, sig)
+        (warm if r.warm else cold).append(r.fit.generations)
+        if r.warm:
+            # the warm box is the cold half-width times 0.7 around the prediction
+            w = (np.array(r.box.hi) - np.array(r.box.lo))[:5]
+            assert np.allclose(w, 0.7 * (b.hi - b.lo)[:5], rtol=1e-12)
+            assert r.box.lo[2] < b.truth[2] < r.box.hi[2]
+    assert len(cold) == 2 and len(warm) == len(items) - 2
+    print(f"[server warm] generations cold {cold} warm mean {np.mean(warm):.0f}", flush=True)
+    assert np.mean(warm) < np.mean(cold)
+
+
+def test_tiny_budget_admits_one_at_a_time():
+    items = _stream(ntracks=3, nblocks=5, seed=3)
+    ref, _ = _serve(items)
+    budget = 830_000  # room for one 200 000-sample block (827 560 B), not for two 100 000-sample ones
+    small, max_active = _serve(items, budget=budget)
+    assert max_active == 1
+    for k in ref:
+        assert _key(ref[k]) == _key(small[k])
+
+
+def test_full_queue_is_busy():
+    items = _stream(ntracks=1, nblocks=3, seed=4)
+    c = ctx()
+    srv = ptk.pt_server_create(c.handle, ptk.make_server_config(_settings(), max_pending=2))
+    try:
+        assert ptk.pt_server_submit(srv, 0, _blk(items[0])) is not None
+        assert ptk.pt_server_submit(srv, 0, _blk(items[1])) is not None
+        assert ptk.pt_server_submit(srv, 0, _blk(items[2])) is None
+        assert ptk.pt_server_stats(srv)[1] == 2
+    finally:
+        ptk.pt_server_destroy(srv)
