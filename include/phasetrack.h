@@ -65,6 +65,13 @@ typedef enum {
 
 typedef enum { PT_F32 = 0, PT_F64 = 1 } pt_dtype;
 
+/* Objective (Sec. 2.2).  PT_OBJ_CHI2: unit-weight chi-square of Eq. (2-2-4)
+ * over the model of Eq. (2-2-2).  PT_OBJ_COR: the correlation objective of
+ * Eq. (2-2-5), F = 1 / (arctan(C) + pi/2) with the unnormalised correlation
+ * C = sum_n s_n (A + Adot t_n) cos phi(t_n) over the constant-amplitude model
+ * of Eq. (2-2-6) (fix A with lo == hi); F tends to 1/pi at the optimum. */
+typedef enum { PT_OBJ_CHI2 = 0, PT_OBJ_COR = 1 } pt_objective_kind;
+
 /* Arithmetic of the objective.  PT_PREC_FP64: phase, cosine, residual and
  * sums in FP64.  PT_PREC_MIXED: FP64 per-chunk phase anchor, FP32 local
  * phase offset (compensated), FP32 cosine and residual, FP32 chunk sums,
@@ -98,7 +105,8 @@ typedef struct {
  *             <= 0: run exactly max_gens generations (fixed iteration
  *             count, the paper's production choice)
  *   window    window length W of that rule (>= 1 when rel_tol > 0)
- *   precision pt_precision */
+ *   precision pt_precision
+ *   objective pt_objective_kind */
 typedef struct {
     int32_t pop;
     int32_t max_gens;
@@ -109,6 +117,8 @@ typedef struct {
     double rel_tol;
     int32_t window;
     int32_t precision;
+    int32_t objective;  /* pt_objective_kind */
+    int32_t reserved;   /* 0 */
 } pt_de_settings;
 
 /* One block of samples.
@@ -188,12 +198,13 @@ int pt_fit_block(pt_ctx* ctx, const pt_block* block, const pt_de_settings* de,
 int pt_fit_batch(pt_ctx* ctx, const pt_block* blocks, int nblk, const pt_de_settings* de,
                  void* hip_stream, pt_fit* out);
 
-/* Objective of an arbitrary population, for parity checks (Eq. 2-2-4).
+/* Objective of an arbitrary population, for parity checks (Eq. 2-2-4 or
+ * Eq. 2-2-5).
  *   pop       device pointer, P x 6 FP64, row-major
  *   out       device pointer, P FP64
- *   precision pt_precision */
+ *   precision pt_precision; objective pt_objective_kind */
 int pt_objective(pt_ctx* ctx, const pt_block* block, const double* pop, int P,
-                 int precision, void* hip_stream, double* out);
+                 int precision, int objective, void* hip_stream, double* out);
 
 /* Final population and objectives of block `index` of the context's most
  * recent pt_fit_block / pt_fit_batch call.  pop_host: P x 6 FP64; fpop_host:

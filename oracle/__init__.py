@@ -6,7 +6,8 @@ links or calls it, and it imports nothing from the product.
 
 Contents
   * ``liboracle.so`` (``oracle.c``): Philox4x32-10, the chi-square objective
-    of Eq. (2-2-4) over the model of Eq. (2-2-2), and DE/rand/1/bin
+    of Eq. (2-2-4) over the model of Eq. (2-2-2), the correlation objective
+    of Eq. (2-2-5) over the constant-amplitude model of Eq. (2-2-6), and DE/rand/1/bin
     (Sec. 1.2, Table 4), all in FP64.
   * :mod:`oracle.derived`: the observables of Sec. 3.1.3 and Sec. 4
     (instantaneous phase and frequency, total-count phase, integration
@@ -25,6 +26,7 @@ from . import derived  # noqa: F401
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 NSLOT = 6
+OBJ_CHI2, OBJ_COR = 0, 1
 TAG_INIT, TAG_MUT, TAG_XOVER = 1, 2, 3
 FLAG_CONVERGED, FLAG_MAXGEN, FLAG_VTR, FLAG_AT_BOUND = 1, 2, 4, 8
 
@@ -44,6 +46,7 @@ class _DeCfg(ctypes.Structure):
         ("window", ctypes.c_int),
         ("lo", ctypes.c_double * NSLOT),
         ("hi", ctypes.c_double * NSLOT),
+        ("objective", ctypes.c_int),
     ]
 
 
@@ -66,6 +69,10 @@ def lib():
         L.orc_chi2.restype = ctypes.c_double
         L.orc_chi2_pop.argtypes = [dp, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
                                    dp, ctypes.c_int, dp, ctypes.c_int]
+        L.orc_cor.argtypes = [dp, ctypes.c_int64, ctypes.c_double, ctypes.c_double, dp]
+        L.orc_cor.restype = ctypes.c_double
+        L.orc_obj_pop.argtypes = [ctypes.c_int, dp, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
+                                  dp, ctypes.c_int, dp, ctypes.c_int]
         L.orc_de_draws.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int, ctypes.c_int,
                                    ctypes.c_int, ctypes.c_int, ip, ip, ip, ip, dp]
         L.orc_de_trial.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
@@ -112,6 +119,22 @@ def chi2(s, fs, ref, x):
     s = _f64(s)
     x = _pad(x)[0].copy()
     return lib().orc_chi2(_dptr(s), s.size, float(fs), float(ref), _dptr(x))
+
+
+def cor(s, fs, ref, x):
+    """Correlation objective of Eq. (2-2-5): 1 / (arctan(C) + pi/2), C = sum s (A + Adot t) cos phi."""
+    s = _f64(s)
+    x = _pad(x)[0].copy()
+    return lib().orc_cor(_dptr(s), s.size, float(fs), float(ref), _dptr(x))
+
+
+def obj_pop(kind, s, fs, ref, pop, nthreads=0):
+    s = _f64(s)
+    pop = _pad(pop)
+    out = np.empty(pop.shape[0], dtype=np.float64)
+    lib().orc_obj_pop(int(kind), _dptr(s), s.size, float(fs), float(ref), _dptr(pop), pop.shape[0],
+                      _dptr(out), int(nthreads))
+    return out
 
 
 def _pad(pop):
@@ -166,12 +189,13 @@ def de_init(seed, stream, P, lo, hi):
 
 
 def de_fit(s, fs, ref, lo, hi, P, max_gens, F=0.5, CR=0.9, seed=0, stream=0,
-           vtr=-np.inf, rel_tol=0.0, window=0, nthreads=0):
+           vtr=-np.inf, rel_tol=0.0, window=0, nthreads=0, objective=OBJ_CHI2):
     """Full DE/rand/1/bin fit; returns a dict with best, objective, history, population."""
     s = _f64(s)
     cfg = _DeCfg()
     cfg.P, cfg.max_gens, cfg.F, cfg.CR = P, max_gens, F, CR
     cfg.seed, cfg.stream, cfg.vtr, cfg.rel_tol, cfg.window = seed, stream, vtr, rel_tol, window
+    cfg.objective = objective
     for j in range(NSLOT):
         cfg.lo[j] = float(lo[j])
         cfg.hi[j] = float(hi[j])

@@ -94,6 +94,38 @@ double orc_chi2(const double* s, int64_t n, double fs, double ref, const double*
     return sum + comp;
 }
 
+double orc_cor(const double* s, int64_t n, double fs, double ref, const double* x) {
+    const double A = x[0], phi0 = x[1], f0 = x[2], f1 = x[3], f2 = x[4], Adot = x[5];
+    const double two_pi = 2.0 * M_PI;
+    double sum = 0.0, comp = 0.0; /* Neumaier */
+    for (int64_t k = 0; k < n; ++k) {
+        double t = ((double)k - ref) / fs;
+        double turns = f0 * t + 0.5 * f1 * t * t + f2 * t * t * t / 6.0;
+        double phi = phi0 + two_pi * turns;
+        double v = s[k] * ((A + Adot * t) * cos(phi));
+        double tsum = sum + v;
+        if (fabs(sum) >= fabs(v))
+            comp += (sum - tsum) + v;
+        else
+            comp += (v - tsum) + sum;
+        sum = tsum;
+    }
+    return 1.0 / (atan(sum + comp) + 0.5 * M_PI);
+}
+
+void orc_obj_pop(int kind, const double* s, int64_t n, double fs, double ref,
+                 const double* pop, int P, double* out, int nthreads) {
+#ifdef _OPENMP
+    int nt = nthreads > 0 ? nthreads : omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nt)
+#endif
+    for (int p = 0; p < P; ++p) {
+        const double* x = pop + (size_t)p * ORC_NSLOT;
+        out[p] = kind == ORC_OBJ_COR ? orc_cor(s, n, fs, ref, x) : orc_chi2(s, n, fs, ref, x);
+    }
+    (void)nthreads;
+}
+
 void orc_chi2_pop(const double* s, int64_t n, double fs, double ref,
                   const double* pop, int P, double* out, int nthreads) {
 #ifdef _OPENMP
@@ -201,7 +233,7 @@ int orc_de_fit(const double* s, int64_t n, double fs, double ref,
     double* h = (double*)malloc(sizeof(double) * (size_t)(cfg->max_gens + 1));
 
     orc_de_init(cfg->seed, cfg->stream, P, cfg->lo, cfg->hi, pop);
-    orc_chi2_pop(s, n, fs, ref, pop, P, f, nthreads);
+    orc_obj_pop(cfg->objective, s, n, fs, ref, pop, P, f, nthreads);
 
     int best = 0;
     for (int p = 1; p < P; ++p)
@@ -220,7 +252,7 @@ int orc_de_fit(const double* s, int64_t n, double fs, double ref,
             orc_de_trial(pop, i, r1, r2, r3, jr, U, D, act, cfg->F, cfg->CR,
                          cfg->lo, cfg->hi, trial + (size_t)i * ORC_NSLOT);
         }
-        orc_chi2_pop(s, n, fs, ref, trial, P, ft, nthreads);
+        orc_obj_pop(cfg->objective, s, n, fs, ref, trial, P, ft, nthreads);
         /* selection: the trial replaces its target when it is not worse */
         for (int i = 0; i < P; ++i) {
             if (ft[i] <= f[i]) {

@@ -55,11 +55,24 @@ void orc_draw_words(uint64_t seed, uint64_t stream, uint32_t i, uint32_t g,
  * Neumaier-compensated, one candidate. */
 double orc_chi2(const double* s, int64_t n, double fs, double ref, const double* x);
 
+/* Correlation objective of Eq. (2-2-5) with the constant-amplitude model of
+ * Eq. (2-2-6): F = 1 / (arctan(C) + pi/2), C = sum_n s_n (A + Adot t_n)
+ * cos(phi(t_n)) -- the unnormalised correlation, which makes F tend to
+ * 1/pi at the optimum as the paper states.  Neumaier-summed C. */
+double orc_cor(const double* s, int64_t n, double fs, double ref, const double* x);
+
+#define ORC_OBJ_CHI2 0
+#define ORC_OBJ_COR 1
+
 /* Objective of P candidates (row-major P x 6); candidates in parallel with
  * nthreads OpenMP threads (<= 0: library default).  Each candidate's sum is
  * sequential, so the result does not depend on the thread count. */
 void orc_chi2_pop(const double* s, int64_t n, double fs, double ref,
                   const double* pop, int P, double* out, int nthreads);
+
+/* Objective `kind` (ORC_OBJ_CHI2 / ORC_OBJ_COR) of P candidates. */
+void orc_obj_pop(int kind, const double* s, int64_t n, double fs, double ref,
+                 const double* pop, int P, double* out, int nthreads);
 
 /* Mutation indices and crossover uniforms of target i in generation g. */
 void orc_de_draws(uint64_t seed, uint64_t stream, int g, int i, int P, int D,
@@ -85,6 +98,7 @@ typedef struct {
     double rel_tol;   /* > 0: window stop rule */
     int window;       /* window length W of the stop rule */
     double lo[ORC_NSLOT], hi[ORC_NSLOT];
+    int objective;    /* ORC_OBJ_CHI2 or ORC_OBJ_COR */
 } orc_de_cfg;
 
 /* Full DE fit.  Outputs: best vector (6), best objective, generations run,

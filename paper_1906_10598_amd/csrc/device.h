@@ -62,7 +62,7 @@ struct BlockDesc {
     DeState* st;       // may be null (bare objective evaluation)
     int* sync;         // persistent kernel: kSyncInts counters (see k_fit_persistent), or null
     int gen_begin;     // persistent kernel: generation whose trial is ready at launch
-    int pad1;
+    int objective;     // 0 = chi-square (Eq. 2-2-4), 1 = correlation (Eq. 2-2-5)
 };
 
 // Persistent-kernel synchronisation words of one block, one 128-byte line each:

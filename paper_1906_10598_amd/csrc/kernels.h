@@ -142,7 +142,7 @@ __device__ __forceinline__ Anchor make_anchor(const Cand& c, double m0) {
 // exactly reduced phase r(j) = Phi(j) - rint(Phi(j)), so the running value
 // stays within one turn (rounding ~1e-16 turns per step, S <= 32 steps).
 // ---------------------------------------------------------------------------
-template <int S, bool TAIL, bool SLOPE>
+template <int S, bool TAIL, bool SLOPE, bool COR = false>
 __device__ __forceinline__ double lane_chi2_f64(const double (&sv)[S], const Anchor& an, double amp0,
                                                 double ad, int valid) {
     // Samples are processed in groups of IL: the phase recurrence runs
@@ -187,19 +187,25 @@ __device__ __forceinline__ double lane_chi2_f64(const double (&sv)[S], const Anc
 #pragma unroll
         for (int q = 0; q < IL; ++q) {
             const int j = g + q;
-            const double amp = SLOPE ? __fma_rn(ad, (double)j, amp0) : amp0;
-            const double rho = __fma_rn(-amp, p[q], sv[j]);
-            if (TAIL) {
-                if (j < valid) acc[q] = __fma_rn(rho, rho, acc[q]);
+            if constexpr (COR) {
+                // masked tail samples are zero, so they add nothing
+                const double m = SLOPE ? __fma_rn(ad, (double)j, amp0) * p[q] : p[q];
+                acc[q] = __fma_rn(sv[j], m, acc[q]);
             } else {
-                acc[q] = (g == 0) ? rho * rho : __fma_rn(rho, rho, acc[q]);
+                const double amp = SLOPE ? __fma_rn(ad, (double)j, amp0) : amp0;
+                const double rho = __fma_rn(-amp, p[q], sv[j]);
+                if (TAIL) {
+                    if (j < valid) acc[q] = __fma_rn(rho, rho, acc[q]);
+                } else {
+                    acc[q] = (g == 0) ? rho * rho : __fma_rn(rho, rho, acc[q]);
+                }
             }
         }
     }
     double tot = 0.0;
 #pragma unroll
     for (int q = 0; q < IL; ++q) tot += acc[q];
-    return tot;
+    return (COR && !SLOPE) ? amp0 * tot : tot;
 }
 
 // ---------------------------------------------------------------------------
@@ -226,7 +232,7 @@ __device__ __forceinline__ void sincos_turns64(double r, double& c, double& sn) 
     sn = r * ps;
 }
 
-template <int S, bool TAIL, bool SLOPE>
+template <int S, bool TAIL, bool SLOPE, bool COR = false>
 __device__ __forceinline__ double lane_chi2_f64_rot(const double (&sv)[S], const Anchor& an, double amp0,
                                                     double ad, int valid) {
     static_assert(kSinDeg64 == kCosDeg64, "sine and cosine tables have one degree");
@@ -242,13 +248,18 @@ __device__ __forceinline__ double lane_chi2_f64_rot(const double (&sv)[S], const
     double acc0 = 0.0, acc1 = 0.0;
 #pragma unroll
     for (int j = 0; j < S; ++j) {
-        const double amp = SLOPE ? __fma_rn(ad, (double)j, amp0) : amp0;
-        const double rho = __fma_rn(-amp, zr, sv[j]);
         double& acc = (j & 1) ? acc1 : acc0;
-        if (TAIL) {
-            if (j < valid) acc = __fma_rn(rho, rho, acc);
+        if constexpr (COR) {
+            const double m = SLOPE ? __fma_rn(ad, (double)j, amp0) * zr : zr;
+            acc = __fma_rn(sv[j], m, acc);
         } else {
-            acc = (j < 2) ? rho * rho : __fma_rn(rho, rho, acc);
+            const double amp = SLOPE ? __fma_rn(ad, (double)j, amp0) : amp0;
+            const double rho = __fma_rn(-amp, zr, sv[j]);
+            if (TAIL) {
+                if (j < valid) acc = __fma_rn(rho, rho, acc);
+            } else {
+                acc = (j < 2) ? rho * rho : __fma_rn(rho, rho, acc);
+            }
         }
         if (j + 1 < S) {
             const double nzr = __fma_rn(zr, wr, -(zi * wi));
@@ -263,7 +274,7 @@ __device__ __forceinline__ double lane_chi2_f64_rot(const double (&sv)[S], const
             }
         }
     }
-    return acc0 + acc1;
+    return (COR && !SLOPE) ? amp0 * (acc0 + acc1) : acc0 + acc1;
 }
 
 // ---------------------------------------------------------------------------
@@ -273,7 +284,7 @@ __device__ __forceinline__ double lane_chi2_f64_rot(const double (&sv)[S], const
 // remainder b0 + j (b1l + j (b2 + j b3)) is small-magnitude FP32.  cos, the
 // residual and the lane sum are FP32.
 // ---------------------------------------------------------------------------
-template <int S, bool TAIL, bool SLOPE>
+template <int S, bool TAIL, bool SLOPE, bool COR = false>
 __device__ __forceinline__ float lane_chi2_mixed(const float (&sv)[S], const Anchor& an, double amp0,
                                                  double ad, int valid) {
     constexpr int IL = 4;  // samples whose cosine chains run in lockstep
@@ -316,16 +327,22 @@ __device__ __forceinline__ float lane_chi2_mixed(const float (&sv)[S], const Anc
 #pragma unroll
         for (int q = 0; q < IL; ++q) {
             const int j = g + q;
-            const float amp = SLOPE ? __fmaf_rn(Ad, (float)j, A) : A;
-            const float rho = __fmaf_rn(-amp, p[q], sv[j]);
-            if (TAIL) {
-                if (j < valid) acc[q] = __fmaf_rn(rho, rho, acc[q]);
+            if constexpr (COR) {
+                const float m = SLOPE ? __fmaf_rn(Ad, (float)j, A) * p[q] : p[q];
+                acc[q] = __fmaf_rn(sv[j], m, acc[q]);
             } else {
-                acc[q] = (g == 0) ? rho * rho : __fmaf_rn(rho, rho, acc[q]);
+                const float amp = SLOPE ? __fmaf_rn(Ad, (float)j, A) : A;
+                const float rho = __fmaf_rn(-amp, p[q], sv[j]);
+                if (TAIL) {
+                    if (j < valid) acc[q] = __fmaf_rn(rho, rho, acc[q]);
+                } else {
+                    acc[q] = (g == 0) ? rho * rho : __fmaf_rn(rho, rho, acc[q]);
+                }
             }
         }
     }
-    return (acc[0] + acc[1]) + (acc[2] + acc[3]);
+    const float tot = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+    return (COR && !SLOPE) ? A * tot : tot;
 }
 
 // ---------------------------------------------------------------------------
@@ -364,6 +381,7 @@ __device__ __forceinline__ void objective_unit(const BlockDesc* __restrict__ d, 
     const int cbase = group * CPG;
     const int ncand = min(CPG, d->P - cbase);
     const int tid = threadIdx.x;
+    const bool cor = d->objective != 0;
     if (tid < ncand) cs[tid] = make_cand(d->trial + (size_t)(cbase + tid) * kStride, d->fs);
     const double m0 = (double)((int64_t)tile * (kThreads * S) + (int64_t)tid * S) - d->ref;
     __syncthreads();
@@ -373,7 +391,15 @@ __device__ __forceinline__ void objective_unit(const BlockDesc* __restrict__ d, 
         const Anchor an = make_anchor(cc, m0);
         const double amp0 = SLOPE ? __fma_rn(cc.Ad, m0, cc.A) : cc.A;
         double acc;
-        if constexpr (MODE == 1) {
+        if (cor) {
+            // correlation objective: masked tail samples are zero, one loop serves both
+            if constexpr (MODE == 1)
+                acc = (double)lane_chi2_mixed<S, false, SLOPE, true>(sv, an, amp0, cc.Ad, valid);
+            else if constexpr (MODE == 2)
+                acc = lane_chi2_f64_rot<S, false, SLOPE, true>(sv, an, amp0, cc.Ad, valid);
+            else
+                acc = lane_chi2_f64<S, false, SLOPE, true>(sv, an, amp0, cc.Ad, valid);
+        } else if constexpr (MODE == 1) {
             acc = full ? (double)lane_chi2_mixed<S, false, SLOPE>(sv, an, amp0, cc.Ad, valid)
                        : (double)lane_chi2_mixed<S, true, SLOPE>(sv, an, amp0, cc.Ad, valid);
         } else if constexpr (MODE == 2) {
@@ -450,6 +476,8 @@ __device__ __forceinline__ double reduce_partials(const BlockDesc* __restrict__ 
     double tot = 0.0;
     if (t < P) {
         for (int q = 0; q < k; ++q) tot += red[t * k + q];
+        // correlation objective, Eq. (2-2-5): F = 1 / (arctan(C) + pi/2)
+        if (d->objective != 0) tot = 1.0 / (atan(tot) + 1.5707963267948966192);
     }
     return tot;
 }

@@ -336,6 +336,8 @@ int check_de(const pt_de_settings* de) {
     if (de->rel_tol > 0 && de->window < 1) return fail(PT_EINVAL, "window must be >= 1 with rel_tol > 0");
     if (de->precision != PT_PREC_FP64 && de->precision != PT_PREC_MIXED)
         return fail(PT_EINVAL, "precision %d", de->precision);
+    if (de->objective != PT_OBJ_CHI2 && de->objective != PT_OBJ_COR)
+        return fail(PT_EINVAL, "objective %d", de->objective);
     if (std::isnan(de->vtr)) return fail(PT_EINVAL, "vtr is NaN");
     return PT_OK;
 }
@@ -538,6 +540,7 @@ int prepare(pt_ctx* ctx, const pt_block* blocks, int nblk, const pt_de_settings*
         d.st = with_state ? st + b : nullptr;
         d.sync = with_state ? static_cast<int*>(ctx->sync.p) + (size_t)b * kSyncInts : nullptr;
         d.gen_begin = 0;
+        d.objective = de->objective;
         hd[b] = d;
     }
     HIPCHK(hipMemcpyAsync(ctx->desc.p, hd, sizeof(BlockDesc) * nblk, hipMemcpyHostToDevice, s));
@@ -742,13 +745,14 @@ int pt_fit_batch(pt_ctx* ctx, const pt_block* blocks, int nblk, const pt_de_sett
 // Shared set-up of the bare objective entry points: descriptor of one block
 // without DE state, the caller's P x 6 rows copied into the stride-8 trial
 // rows, and the objective kernel of the chosen geometry.
-static int eval_setup(pt_ctx* ctx, const pt_block* block, const double* pop, int P, int precision, hipStream_t s,
-                      Plan* pl, ObjKernel* obj) {
+static int eval_setup(pt_ctx* ctx, const pt_block* block, const double* pop, int P, int precision, int objective,
+                      hipStream_t s, Plan* pl, ObjKernel* obj) {
     int rc = check_block(block, 0);
     if (rc) return rc;
     if (!pop) return fail(PT_EINVAL, "pop is null");
     if (P < 1 || P > PT_MAX_POP) return fail(PT_EINVAL, "P = %d outside [1, %d]", P, PT_MAX_POP);
     if (precision != PT_PREC_FP64 && precision != PT_PREC_MIXED) return fail(PT_EINVAL, "precision %d", precision);
+    if (objective != PT_OBJ_CHI2 && objective != PT_OBJ_COR) return fail(PT_EINVAL, "objective %d", objective);
     HIPCHK(hipSetDevice(ctx->device));
     pt_de_settings de;
     std::memset(&de, 0, sizeof de);
@@ -757,6 +761,7 @@ static int eval_setup(pt_ctx* ctx, const pt_block* block, const double* pop, int
     de.F = 0.5;
     de.CR = 0.5;
     de.precision = precision;
+    de.objective = objective;
     void* old_desc = ctx->desc.p;
     if ((rc = prepare(ctx, block, 1, &de, s, pl, false))) return rc;
     if (ctx->desc.p != old_desc) ctx->drop_graphs();
@@ -781,14 +786,14 @@ static int eval_setup(pt_ctx* ctx, const pt_block* block, const double* pop, int
     return PT_OK;
 }
 
-int pt_objective(pt_ctx* ctx, const pt_block* block, const double* pop, int P, int precision, void* hip_stream,
-                 double* out) {
+int pt_objective(pt_ctx* ctx, const pt_block* block, const double* pop, int P, int precision, int objective,
+                 void* hip_stream, double* out) {
     if (!ctx) return fail(PT_EINVAL, "ctx is null");
     if (!out) return fail(PT_EINVAL, "out is null");
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     Plan pl;
     ObjKernel obj = nullptr;
-    int rc = eval_setup(ctx, block, pop, P, precision, s, &pl, &obj);
+    int rc = eval_setup(ctx, block, pop, P, precision, objective, s, &pl, &obj);
     if (rc) return rc;
     const BlockDesc* d = static_cast<const BlockDesc*>(ctx->desc.p);
     hipLaunchKernelGGL(obj, dim3(pl.grid), dim3(kThreads), 0, s, d, 1, pl.total_units);
@@ -807,7 +812,7 @@ int pt_time_objective(pt_ctx* ctx, const pt_block* block, const double* pop, int
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     Plan pl;
     ObjKernel obj = nullptr;
-    int rc = eval_setup(ctx, block, pop, P, precision, s, &pl, &obj);
+    int rc = eval_setup(ctx, block, pop, P, precision, PT_OBJ_CHI2, s, &pl, &obj);
     if (rc) return rc;
     const BlockDesc* d = static_cast<const BlockDesc*>(ctx->desc.p);
     hipLaunchKernelGGL(obj, dim3(pl.grid), dim3(kThreads), 0, s, d, 1, pl.total_units);  // warm
@@ -1329,6 +1334,7 @@ int pt_server_step(pt_server* sv, void* hip_stream, int32_t* n_active, int32_t* 
         d.st = static_cast<DeState*>(sl.state.p);
         d.sync = nullptr;
         d.gen_begin = sl.gen;
+        d.objective = de.objective;
         d.pad0 = sl.fresh ? 1 : 0;  // k_de_init initialises only fresh slots
         any_fresh = any_fresh || sl.fresh;
         hd[q] = d;

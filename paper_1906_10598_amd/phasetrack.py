@@ -23,6 +23,7 @@ PT_PREC_FP64, PT_PREC_MIXED = 0, 1
 PT_FLAG_CONVERGED, PT_FLAG_MAXGEN, PT_FLAG_VTR, PT_FLAG_AT_BOUND = 1, 2, 4, 8
 PT_LAUNCH_AUTO, PT_LAUNCH_GRAPH, PT_LAUNCH_PERSISTENT = 0, 1, 2
 PT_FP64_AUTO, PT_FP64_POLY = 0, 1
+PT_OBJ_CHI2, PT_OBJ_COR = 0, 1
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libphasetrack.so")
 
@@ -48,6 +49,8 @@ class pt_de_settings(ctypes.Structure):
         ("rel_tol", ctypes.c_double),
         ("window", ctypes.c_int32),
         ("precision", ctypes.c_int32),
+        ("objective", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -128,7 +131,7 @@ def _signatures(L):
                           ctypes.POINTER(pt_fit)], i32),
         "pt_fit_batch": ([_CTX, ctypes.POINTER(pt_block), i32, ctypes.POINTER(pt_de_settings), _VP,
                           ctypes.POINTER(pt_fit)], i32),
-        "pt_objective": ([_CTX, ctypes.POINTER(pt_block), _VP, i32, i32, _VP, _VP], i32),
+        "pt_objective": ([_CTX, ctypes.POINTER(pt_block), _VP, i32, i32, i32, _VP, _VP], i32),
         "pt_last_population": ([_CTX, i32, _DP, _DP, i32], i32),
         "pt_last_history": ([_CTX, i32, _DP, i32, ctypes.POINTER(i32)], i32),
         "pt_phase": ([ctypes.POINTER(pt_fit), _DP, i64, _DP, _DP, _DP, _DP], i32),
@@ -210,8 +213,10 @@ def pt_fit_batch(ctx, blocks: Sequence[pt_block], de: pt_de_settings, stream=Non
     return list(out)
 
 
-def pt_objective(ctx, block: pt_block, pop_ptr: int, P: int, precision: int, out_ptr: int, stream=None):
-    _check(lib().pt_objective(ctx, ctypes.byref(block), pop_ptr, P, precision, stream, out_ptr), "pt_objective")
+def pt_objective(ctx, block: pt_block, pop_ptr: int, P: int, precision: int, out_ptr: int, stream=None,
+                 objective: int = PT_OBJ_CHI2):
+    _check(lib().pt_objective(ctx, ctypes.byref(block), pop_ptr, P, precision, objective, stream, out_ptr),
+           "pt_objective")
 
 
 def pt_last_population(ctx, index: int, P: int):
@@ -376,10 +381,11 @@ def make_box(lo, hi) -> pt_box:
 
 def make_settings(pop: int, max_gens: int, F: float = 0.5, CR: float = 0.9, seed: int = 0,
                   vtr: float = -math.inf, rel_tol: float = 0.0, window: int = 0,
-                  precision: int = PT_PREC_FP64) -> pt_de_settings:
+                  precision: int = PT_PREC_FP64, objective: int = PT_OBJ_CHI2) -> pt_de_settings:
     s = pt_de_settings()
     s.pop, s.max_gens, s.F, s.CR, s.seed = pop, max_gens, F, CR, seed
     s.vtr, s.rel_tol, s.window, s.precision = vtr, rel_tol, window, precision
+    s.objective = objective
     return s
 
 
@@ -446,8 +452,8 @@ class Context:
     def fit_batch(self, blocks, de: pt_de_settings):
         return pt_fit_batch(self.handle, blocks, de, current_stream())
 
-    def objective(self, block: pt_block, pop, precision: int = PT_PREC_FP64):
-        """chi^2 of each row of ``pop`` (torch FP64 tensor P x 6 on the GPU)."""
+    def objective(self, block: pt_block, pop, precision: int = PT_PREC_FP64, objective: int = PT_OBJ_CHI2):
+        """Objective (chi^2 or correlation) of each row of ``pop`` (torch FP64 tensor P x 6 on the GPU)."""
         import torch
 
         pop = pop.contiguous()
@@ -455,5 +461,5 @@ class Context:
             raise ValueError("pop must be a CUDA float64 tensor of shape (P, 6)")
         out = torch.empty(pop.shape[0], dtype=torch.float64, device=pop.device)
         pt_objective(self.handle, block, pop.data_ptr(), pop.shape[0], precision, out.data_ptr(),
-                     current_stream())
+                     current_stream(), objective)
         return out

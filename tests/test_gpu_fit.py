@@ -198,3 +198,22 @@ def test_derived_outputs_of_a_fit():
     assert f.total_phase == pytest.approx(oracle.derived.block_total_phase(c, 2 * T2), rel=1e-13)
     assert abs(math.remainder(f.phase_left - float(oracle.derived.phase_mod2pi(c, -T2)), 2 * math.pi)) < 1e-9
     assert f.freq_right == pytest.approx(float(oracle.derived.freq_hz(c, T2)), rel=1e-14)
+
+
+def test_amplitude_slope_fit_matches_oracle():
+    # six-parameter fit with the amplitude slope c5 of Eq. (2-2-2) active
+    rng = np.random.default_rng(17)
+    n, fs = 20_000, 2_000.0
+    t = (np.arange(n) - n / 2) / fs
+    x = np.array([0.8, 1.9, 311.25, 0.75, 0.0, 0.06])
+    s = (x[0] + x[5] * t) * np.cos(x[1] + 2 * np.pi * (x[2] * t + x[3] * t * t / 2)) + rng.normal(0, 0.2, n)
+    half = np.array([0.1, np.pi, 0.5, 0.5, 0.0, 0.1])
+    b = synth.Block(s, fs, n / 2, x, x - half, x + half,
+                    synth.DESettings(pop=40, max_gens=400, seed=99), 0.2, stream=3, name="slope")
+    dev = to_dev(s)
+    f = ctx().fit_block(block_of(b, dev), settings_of(b, gens=25))
+    assert _compare(b, f, _oracle_fit(b, 25), 40, "slope 25 gens") == 40
+    f = ctx().fit_block(block_of(b, dev), settings_of(b))
+    ref = _oracle_fit(b, b.de.max_gens)
+    _compare(b, f, ref, 40, "slope")
+    assert abs(f.coef[5] - x[5]) < 0.01

@@ -192,3 +192,50 @@ def test_population_matches_single():
     many = oracle.chi2_pop(b.samples, b.fs, b.ref, pop, nthreads=3)
     one = [oracle.chi2(b.samples, b.fs, b.ref, p) for p in pop]
     assert np.array_equal(many, np.array(one))
+
+
+# ------------------------------------------------- correlation objective
+def test_correlation_linear_phase_closed_form():
+    # C = A_hat sum s cos(a_hat k + b_hat) with s = A cos(a k + b):
+    # sum cos cos = (D(a - a_hat, b - b_hat) + D(a + a_hat, b + b_hat)) / 2
+    mp = mpmath.mpf
+    n, fs, ref = 3001, 500.0, 1500.0
+    A, f0, phi0 = mp("0.7"), mp("61.25"), mp("2.5")
+    a = 2 * mpmath.pi * f0 / fs
+    b = phi0 - a * ref
+    s = np.array([float(A * mpmath.cos(a * k + b)) for k in range(n)])
+    for Ah, ph, fh in [(1.0, 2.5, 61.25), (1.3, 0.4, 61.0), (0.9, -1.0, 70.5)]:
+        ah = 2 * mpmath.pi * mp(fh) / fs
+        bh = mp(ph) - ah * ref
+        C = mp(Ah) * A * (_dirichlet(a - ah, b - bh, n) + _dirichlet(a + ah, b + bh, n)) / 2
+        want = float(1 / (mpmath.atan(C) + mpmath.pi / 2))
+        got = oracle.cor(s, fs, ref, [Ah, ph, fh, 0, 0, 0])
+        assert got == pytest.approx(want, rel=1e-13)
+
+
+def test_correlation_tends_to_one_over_pi_and_orders_like_chi2():
+    # at the truth C ~ N A^2 / 2 is large, so F -> 1/pi from above; F is a
+    # decreasing function of C, and with a fixed amplitude chi2 = sum s^2 -
+    # 2 C + A^2 sum cos^2, so near the truth both objectives rank candidates alike
+    b = synth.config0(0)
+    x = b.truth.copy()
+    f = oracle.cor(b.samples, b.fs, b.ref, x)
+    assert 1 / np.pi < f < 1 / np.pi + 1e-3
+    worse = x.copy()
+    worse[2] += 0.05
+    assert oracle.cor(b.samples, b.fs, b.ref, worse) > f
+    zero = x.copy()
+    zero[0] = 0.0
+    assert oracle.cor(b.samples, b.fs, b.ref, zero) == pytest.approx(2 / np.pi, rel=1e-15)  # C = 0
+    neg = x.copy()
+    neg[1] += np.pi  # anti-correlated model: C -> -C, F -> 1/(pi/2 - atan C) > 2/pi
+    assert oracle.cor(b.samples, b.fs, b.ref, neg) > 2 / np.pi
+
+
+def test_obj_pop_dispatch():
+    b = synth.config0(1)
+    pop = oracle.de_init(2, 0, 6, b.lo, b.hi)
+    c = oracle.obj_pop(oracle.OBJ_COR, b.samples, b.fs, b.ref, pop)
+    assert np.array_equal(c, [oracle.cor(b.samples, b.fs, b.ref, p) for p in pop])
+    q = oracle.obj_pop(oracle.OBJ_CHI2, b.samples, b.fs, b.ref, pop)
+    assert np.array_equal(q, oracle.chi2_pop(b.samples, b.fs, b.ref, pop))
