@@ -25,10 +25,15 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6    # MI355X FP64 vector
 PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector (published, packed)
-# Algorithmic FLOP per candidate*sample (see the design notes): phase cubic
-# (3 FMA) + turn reduction (1) + r^2 (1) + cosine polynomial (degree 10 FP64
-# / degree 6 FP32, one FMA per degree) + residual FMA + square-accumulate FMA.
-FLOP_PER_PAIR = {"fp64": 6 + 1 + 1 + 20 + 2 + 2, "mixed": 6 + 1 + 1 + 12 + 2 + 2}
+# Algorithmic FLOP per candidate*sample of each objective arithmetic (see the
+# design notes), keyed by the library's PT_ARITH_* code:
+#   per-sample FP64 (0): phase cubic (3 FMA) + turn reduction (1) + r^2 (1) +
+#     degree-10 cosine polynomial (10 FMA) + residual FMA + square-accumulate FMA;
+#   mixed (1): the same with a degree-6 FP32 polynomial;
+#   FP64 phasor (2): two complex multiplies (2 MUL + 2 FMA each) + residual FMA
+#     + square-accumulate FMA.
+FLOP_PER_PAIR = {0: 6 + 1 + 1 + 20 + 2 + 2, 1: 6 + 1 + 1 + 12 + 2 + 2, 2: 6 + 6 + 2 + 2}
+ARITH_NAME = {0: "fp64-per-sample", 1: "mixed", 2: "fp64-phasor"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_objective_fp64_paper400k.md")
 KERNEL_SRC = [os.path.join(ROOT, "paper_1906_10598_amd", "csrc", f) for f in ("kernels.h", "device.h")]
 
@@ -131,6 +136,52 @@ def run_serving(ctx, ptk, synth, np, torch, nblocks):
             "warm_fraction": warm / len(items)}
 
 
+def objective_comparison(ctx, ptk, synth, np, torch, nseeds):
+    """Chi-square (Eq. 2-2-4) against the correlation objective (Eq. 2-2-5
+    with the constant-amplitude model of Eq. 2-2-6) on paper-scale blocks.
+
+    Both fits run 2000 generations from the same seed; the correlation fit
+    fixes A at the block's RMS amplitude sqrt(2 mean s^2) (its optimum does
+    not depend on that scale).  Convergence generation: first g with
+    best[g] - best[G] <= 1e-3 (best[0] - best[G]) on the best-so-far history."""
+    out = {"chi2": {"gens": [], "ms_per_gen": [], "f0_err_over_crlb": []},
+           "cor": {"gens": [], "ms_per_gen": [], "f0_err_over_crlb": []}}
+    for seed in range(nseeds):
+        b = synth.config1(seed)
+        dev = torch.from_numpy(b.samples).cuda()
+        a_rms = math.sqrt(2.0 * float(np.mean(b.samples.astype(np.float64) ** 2)))
+        lo_c, hi_c = b.lo.copy(), b.hi.copy()
+        lo_c[0] = hi_c[0] = a_rms
+        sig = math.sqrt(6.0) * b.sigma / (math.pi * b.truth[0] * (b.n / b.fs) * math.sqrt(b.n))
+        for name, kind, lo, hi in (("chi2", ptk.PT_OBJ_CHI2, b.lo, b.hi), ("cor", ptk.PT_OBJ_COR, lo_c, hi_c)):
+            blk = ptk.make_block(dev, b.fs, lo, hi, ref=b.ref, stream=b.stream)
+            de = ptk.make_settings(pop=b.de.pop, max_gens=b.de.max_gens, F=b.de.F, CR=b.de.CR, seed=b.de.seed,
+                                   objective=kind)
+            ctx.fit_block(blk, de)  # warm (graph capture)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            f = ctx.fit_block(blk, de)
+            dt = time.perf_counter() - t0
+            h = ptk.pt_last_history(ctx.handle, 0, f.generations + 1)
+            drop = h[0] - h[-1]
+            g = int(np.argmax(h - h[-1] <= 1e-3 * drop)) if drop > 0 else 0
+            out[name]["gens"].append(g)
+            out[name]["ms_per_gen"].append(dt * 1e3 / (f.generations + 1))
+            out[name]["f0_err_over_crlb"].append(abs(f.coef[2] - b.truth[2]) / sig)
+    res = {"workload": f"{nseeds} paper-scale blocks (400000 samples, 50 kHz, 0 dB), P=40, 2000 generations; "
+                       "correlation fit with A fixed at the RMS amplitude",
+           "convergence": "first generation within 1e-3 of the total decrease of the best-so-far objective"}
+    for name, v in out.items():
+        res[name] = {"median_gens_to_converge": pct(v["gens"], 50), "max_gens_to_converge": max(v["gens"]),
+                     "ms_per_generation": pct(v["ms_per_gen"], 50),
+                     "f0_err_over_crlb": {"median": pct(v["f0_err_over_crlb"], 50),
+                                          "max": max(v["f0_err_over_crlb"])}}
+    res["cor_gens_over_chi2_gens"] = (res["cor"]["median_gens_to_converge"] /
+                                      max(res["chi2"]["median_gens_to_converge"], 1))
+    res["cor_cost_per_gen_over_chi2"] = res["cor"]["ms_per_generation"] / res["chi2"]["ms_per_generation"]
+    return res
+
+
 def cpu_baseline(b, gens, nthreads):
     import numpy as np
 
@@ -163,6 +214,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-block batched fits")
     ap.add_argument("--no-serve", action="store_true", help="skip the real-time serving run")
     ap.add_argument("--serve-blocks", type=int, default=160)
+    ap.add_argument("--no-objcmp", action="store_true", help="skip the chi-square vs correlation comparison")
+    ap.add_argument("--objcmp-seeds", type=int, default=8)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -218,6 +271,7 @@ def main():
     run_fits(ctx, blk, de(ptk.PT_PREC_FP64), args.warmup, "warmup")
     elapsed, lat_steps, fits64 = run_fits(ctx, blk, de(ptk.PT_PREC_FP64), args.steps, "fp64")
     value = pairs_per_fit * args.steps / elapsed
+    arith64 = ARITH_NAME[ptk.pt_ctx_last_arithmetic(ctx.handle)]
     print(f"# fp64: {args.steps} fits in {elapsed:.3f} s", file=sys.stderr, flush=True)
 
     # ---- latency percentiles (distinct seeds), both paths
@@ -249,7 +303,10 @@ def main():
     # kernel (same geometry and grid as the fits, on the fit's final
     # population), plus the in-fit event-bracketed mean for reference
     roof = {}
-    for name, prec in (("fp64", ptk.PT_PREC_FP64), ("mixed", ptk.PT_PREC_MIXED)):
+    for name, prec, method in (("fp64", ptk.PT_PREC_FP64, ptk.PT_FP64_AUTO),
+                               ("fp64_per_sample", ptk.PT_PREC_FP64, ptk.PT_FP64_POLY),
+                               ("mixed", ptk.PT_PREC_MIXED, ptk.PT_FP64_AUTO)):
+        ptk.pt_ctx_set_fp64_method(ctx.handle, method)
         ptk.pt_ctx_set_timing(ctx.handle, True)
         ctx.fit_block(blk, de(prec)(0))
         nl, ms = ptk.pt_ctx_kernel_stats(ctx.handle)
@@ -257,11 +314,14 @@ def main():
         pop, _ = ptk.pt_last_population(ctx.handle, 0, P)
         popd = torch.from_numpy(pop).cuda()
         avg_ms = ptk.pt_time_objective(ctx.handle, blk, popd.data_ptr(), P, prec, 400, stream)
-        flop = FLOP_PER_PAIR[name] * P * N
+        arith = ptk.pt_ctx_last_arithmetic(ctx.handle)
+        ptk.pt_ctx_set_fp64_method(ctx.handle, ptk.PT_FP64_AUTO)
+        flop = FLOP_PER_PAIR[arith] * P * N
         ach = flop / (avg_ms * 1e-3) / 1e12
-        peak = PEAK_FP64_TFLOPS if name == "fp64" else PEAK_FP32_TFLOPS
+        peak = PEAK_FP64_TFLOPS if prec == ptk.PT_PREC_FP64 else PEAK_FP32_TFLOPS
         roof[name] = {"avg_launch_ms": avg_ms, "in_fit_event_ms": ms / max(nl, 1), "launches": nl,
-                      "achieved": ach, "peak": peak}
+                      "achieved": ach, "peak": peak, "arithmetic": ARITH_NAME[arith],
+                      "flop_per_candidate_sample": FLOP_PER_PAIR[arith]}
 
     traffic = read_traffic()
 
@@ -299,6 +359,13 @@ def main():
         print(f"# serving: p50 {serving['latency_ms']['p50']:.1f} ms p99 {serving['latency_ms']['p99']:.1f} ms",
               file=sys.stderr, flush=True)
 
+    # ---- chi-square vs correlation objective (Sec. 2.2 comparison, synthetic)
+    objcmp = None
+    if not args.no_objcmp:
+        objcmp = objective_comparison(ctx, ptk, synth, np, torch, args.objcmp_seeds)
+        print(f"# objectives: chi2 {objcmp['chi2']['median_gens_to_converge']} gens, "
+              f"cor {objcmp['cor']['median_gens_to_converge']} gens", file=sys.stderr, flush=True)
+
     # ---- CPU oracle baseline (bounded sample of the same fit)
     cpu = None
     if not args.no_cpu:
@@ -325,6 +392,7 @@ def main():
         "config": {"workload": "paper-scale block fit: N=400000 int16-quantised FP32 samples at 50 kHz, "
                                "cubic phase, SNR 0 dB; DE/rand/1/bin P=40, F=0.5, CR=0.9, 2000 generations",
                    "n_samples": N, "population": P, "generations": G, "precision": "fp64",
+                   "arithmetic": arith64,
                    "geometry": {"samples_per_lane": tiles["fp64"][0], "cand_per_group": tiles["fp64"][1]}},
         "latency_ms": {
             "fp64": {"p50": pct(lat64, 50), "p99": pct(lat64, 99), "fits": len(lat64)},
@@ -338,12 +406,16 @@ def main():
                                "avg_launch_ms": roof["mixed"]["avg_launch_ms"]}},
         "roofline": {"bound": "alu", "achieved": r64["achieved"], "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": r64["achieved"] / PEAK_FP64_TFLOPS, "traffic": traffic,
-                     "kernel": "k_objective (FP64)", "avg_launch_ms": r64["avg_launch_ms"],
+                     "kernel": "k_objective (FP64, %s)" % r64["arithmetic"], "avg_launch_ms": r64["avg_launch_ms"],
                      "in_fit_event_ms": r64["in_fit_event_ms"], "launches_per_fit": r64["launches"],
-                     "flop_per_candidate_sample": FLOP_PER_PAIR["fp64"],
-                     "kernel_hash": kernel_hash()},
+                     "flop_per_candidate_sample": r64["flop_per_candidate_sample"],
+                     "kernel_hash": kernel_hash(),
+                     "fp64_per_sample_path": {k: roof["fp64_per_sample"][k] for k in
+                                              ("avg_launch_ms", "achieved", "flop_per_candidate_sample")} |
+                                             {"frac": roof["fp64_per_sample"]["achieved"] / PEAK_FP64_TFLOPS}},
         "batch": batch,
         "serving": serving,
+        "objective_comparison": objcmp,
         "cpu_baseline": cpu,
         "paper_context": {"gtx580_fit_s": 6.5, "evaluations": 80000, "block": "~400K samples"},
     }

@@ -338,6 +338,12 @@ enum { PT_FP64_AUTO = 0, PT_FP64_POLY = 1 };
 
 int pt_ctx_set_fp64_method(pt_ctx* ctx, int method);
 
+/* Objective arithmetic of the context's most recent fit or objective
+ * evaluation: per-sample FP64 cosine, mixed precision, or FP64 phasor. */
+enum { PT_ARITH_FP64_POLY = 0, PT_ARITH_MIXED = 1, PT_ARITH_FP64_PHASOR = 2 };
+
+int pt_ctx_last_arithmetic(pt_ctx* ctx, int* arith);
+
 /* ---- instrumentation ---- */
 
 /* Turn per-kernel timing of the objective kernel on (1) or off (0).  While

@@ -116,7 +116,7 @@ int size_class(int64_t n) {
 using ObjKernel = void (*)(const BlockDesc*, int, int);
 
 // Kernel arithmetic modes (template argument MODE of the kernels).
-enum { kModePoly = 0, kModeMixed = 1, kModePhasor = 2 };
+enum { kModePoly = PT_ARITH_FP64_POLY, kModeMixed = PT_ARITH_MIXED, kModePhasor = PT_ARITH_FP64_PHASOR };
 
 template <typename T, int S, int C, int M>
 ObjKernel pick_slope(bool slope) {
@@ -249,6 +249,7 @@ struct pt_ctx {
     int launch_mode = PT_LAUNCH_AUTO;
     int fp64_method = PT_FP64_AUTO;
     int last_launch = PT_LAUNCH_GRAPH;
+    int last_arith = PT_ARITH_FP64_POLY;
     uint64_t spin_ticks = 0;
     DevBuf errflag;
     // geometry
@@ -620,6 +621,7 @@ int run_fit(pt_ctx* ctx, const pt_block* blocks, int nblk, const pt_de_settings*
         }
     }
     ctx->last_launch = persistent ? PT_LAUNCH_PERSISTENT : PT_LAUNCH_GRAPH;
+    ctx->last_arith = pl.mode;
     if (persistent) {
         // nothing else to enqueue
     } else if (ctx->timing) {
@@ -783,6 +785,7 @@ static int eval_setup(pt_ctx* ctx, const pt_block* block, const double* pop, int
             pl->mode = kModePoly;
     }
     *obj = objective_kernel(pl->dtype, pl->geo, pl->mode, pl->slope);
+    ctx->last_arith = pl->mode;
     return PT_OK;
 }
 
@@ -941,6 +944,12 @@ int pt_ctx_set_fp64_method(pt_ctx* ctx, int method) {
 int pt_ctx_last_launch(pt_ctx* ctx, int* mode) {
     if (!ctx || !mode) return fail(PT_EINVAL, "ctx / mode is null");
     *mode = ctx->last_launch;
+    return PT_OK;
+}
+
+int pt_ctx_last_arithmetic(pt_ctx* ctx, int* arith) {
+    if (!ctx || !arith) return fail(PT_EINVAL, "ctx / arith is null");
+    *arith = ctx->last_arith;
     return PT_OK;
 }
 

@@ -24,6 +24,7 @@ PT_FLAG_CONVERGED, PT_FLAG_MAXGEN, PT_FLAG_VTR, PT_FLAG_AT_BOUND = 1, 2, 4, 8
 PT_LAUNCH_AUTO, PT_LAUNCH_GRAPH, PT_LAUNCH_PERSISTENT = 0, 1, 2
 PT_FP64_AUTO, PT_FP64_POLY = 0, 1
 PT_OBJ_CHI2, PT_OBJ_COR = 0, 1
+PT_ARITH_FP64_POLY, PT_ARITH_MIXED, PT_ARITH_FP64_PHASOR = 0, 1, 2
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libphasetrack.so")
 
@@ -151,6 +152,7 @@ def _signatures(L):
         "pt_ctx_set_launch_mode": ([_CTX, i32], i32),
         "pt_ctx_set_fp64_method": ([_CTX, i32], i32),
         "pt_ctx_last_launch": ([_CTX, ctypes.POINTER(i32)], i32),
+        "pt_ctx_last_arithmetic": ([_CTX, ctypes.POINTER(i32)], i32),
         "pt_ctx_set_timing": ([_CTX, i32], i32),
         "pt_ctx_kernel_stats": ([_CTX, ctypes.POINTER(i64), _DP], i32),
         "pt_ctx_get_tile": ([_CTX, i64, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)], i32),
@@ -340,6 +342,12 @@ def pt_ctx_set_fp64_method(ctx, method: int):
 def pt_ctx_last_launch(ctx) -> int:
     m = ctypes.c_int()
     _check(lib().pt_ctx_last_launch(ctx, ctypes.byref(m)), "pt_ctx_last_launch")
+    return m.value
+
+
+def pt_ctx_last_arithmetic(ctx) -> int:
+    m = ctypes.c_int32()
+    _check(lib().pt_ctx_last_arithmetic(ctx, ctypes.byref(m)), "pt_ctx_last_arithmetic")
     return m.value
 
 
