@@ -242,41 +242,144 @@ int pt_connect_phase(const pt_fit* fits, int nblk, double* phi_total_rad, double
 int pt_los_accel(const pt_fit* fit, double t, double f_carrier_hz, double M2, int three_way,
                  double* a_m_s2);
 
+/* ---- range determination and continuity (Sec. 3.1.1, Sec. 3.1.3) ---- */
+
+/* Options of pt_seed_block.
+ *   snippet  M, samples per snippet: a power of two in [64, pt_seed_max_snippet()];
+ *            0 selects 4096 (or the maximum, if smaller)
+ *   spacing  samples between the middle snippet's centre and each outer one;
+ *            0 selects n / 4 */
+typedef struct {
+    int32_t snippet;
+    int32_t reserved;  /* 0 */
+    int64_t spacing;
+} pt_seed_opts;
+
+/* Estimates of pt_seed_block.  Snippet k (0 = left, 1 = middle, 2 = right)
+ * holds samples [c_k - M/2, c_k + M/2) with c_k = floor(ref) + (k - 1) spacing;
+ * t[k] is the mid-time of its samples, seconds from the reference sample.
+ * A real signal shows |frequency|: f[k] lies in (0, fs/2), so for a negative
+ * carrier offset the estimates describe the mirror-image phase (phi0, f0,
+ * f1, f2) -> (-phi0, -f0, -f1, -f2), which gives the same samples.
+ * Standard errors: single-tone Cramer-Rao bound with the measured noise,
+ * sd_f = sqrt(6) sigma / (pi A T_s sqrt(M)), T_s = M / fs, propagated
+ * through the difference formulas. */
+typedef struct {
+    double f[3];      /* peak frequency of each snippet [Hz] */
+    double amp[3];    /* amplitude of each snippet at f[k] */
+    double noise[3];  /* noise standard deviation of each snippet */
+    double t[3];      /* [s] */
+    int32_t bin[3];   /* FFT peak bin of each snippet */
+    int32_t snippet;  /* M used */
+    double f0;        /* f[1] moved to the reference time with f1 [Hz] */
+    double f1;        /* (f[2] - f[0]) / (t[2] - t[0]) [Hz/s] */
+    double f2;        /* (f[2] - 2 f[1] + f[0]) / dt^2, dt = spacing / fs [Hz/s^2] */
+    double A, sigma;  /* amplitude and noise std of the middle snippet */
+    double sd_f0, sd_f1, sd_f2, sd_A;
+} pt_seed;
+
+/* Largest snippet pt_seed_block accepts on the context's device (limited by
+ * the LDS one workgroup may hold: 16 bytes per sample). */
+int pt_seed_max_snippet(pt_ctx* ctx);
+
+/* Initial-range estimates of Sec. 3.1.1 for one block: each of three
+ * equally spaced snippets is transformed by an FFT on the device, its peak
+ * bin refined by Candan's interpolator and its amplitude measured at the
+ * refined frequency; the host then forms f0, f1 (central difference) and f2
+ * (second difference).  The block's box is not used.  Errors: PT_EINVAL
+ * for a bad block or options, or a snippet reaching outside the block.
+ * Returns after `out` is filled (synchronises hip_stream). */
+int pt_seed_block(pt_ctx* ctx, const pt_block* block, const pt_seed_opts* opts, void* hip_stream,
+                  pt_seed* out);
+
+/* Box rules of pt_seed_box.
+ * PT_RANGE_PAPER, Sec. 3.1.1 as printed: phi0 in [0, 2 pi]; f0 +-10 % of
+ *   |f0|; f1 +-10 % of |f1| (the paper gives the value only; it is widened
+ *   to at least nsig sd_f1); f2 in +-150/pi Hz/s^2 (c3 in [-50, 50] rad/s^3);
+ *   A +-10 %; Adot in +-0.2 A / T when `slope`, else fixed at 0.
+ * PT_RANGE_SIGMA: phi0 in [0, 2 pi]; f0, f1, f2 each +-nsig standard errors
+ *   around the estimate; A +-max(10 %, nsig sd_A); Adot as above.  This is the
+ *   default of the server's seeding: a 10 % frequency range is thousands of
+ *   chi-square peak widths (1 / T) for a kHz carrier, beyond what a 40-member
+ *   population finds. */
+enum { PT_RANGE_PAPER = 0, PT_RANGE_SIGMA = 1 };
+
+/* Search box from seed estimates; T is the block length [s] (n / fs). */
+int pt_seed_box(const pt_seed* seed, int rule, double nsig, double T, int slope, pt_box* out);
+
+/* Phase continuity at the border of two adjacent blocks (Eq. 3-1-2): block
+ * `a` ends where block `b` starts.  dphi = phi_a(a.t_right) - phi_b(b.t_left)
+ * wrapped to [-pi, pi] [rad]; dfreq = F_a(a.t_right) - F_b(b.t_left) [Hz]. */
+int pt_continuity(const pt_fit* a, const pt_fit* b, double* dphi_rad, double* dfreq_hz);
+
 /* ---- serving: continuous batching of arriving blocks ----
  * A server keeps up to max_slots blocks resident on the device (samples,
  * population, partial sums and DE state of each).  pt_server_step runs
  * gens_per_step generations of every resident block in shared launches (one
- * objective grid over all resident blocks, then each block's DE step), then
- * retires the blocks whose stop rule fired into the result queue; blocks
- * submitted meanwhile are admitted at the start of the next step as slots
- * and the HBM budget free up.  A track's blocks are fitted in submission
- * order: the next one is admitted once the previous fit is done and starts
- * warm -- the previous fitted phase re-expanded about the new block's
- * reference time (the running range of Sec. 3.1.1), with the block's own box
- * half-widths scaled by warm_narrow around that prediction.  The first block
- * of a track uses its box as given.  Every block of a server uses the same
- * DE settings and one objective geometry, so a block's result does not
- * depend on which other blocks share its steps. */
+ * objective grid per objective arithmetic over the resident blocks, then
+ * each block's DE step), then retires the blocks whose stop rule fired;
+ * blocks submitted meanwhile are admitted at the start of the next step as
+ * slots and the HBM budget free up.
+ *
+ * A track's blocks are contiguous in time and fitted in submission order,
+ * which makes the server a tracker (Sec. 3.1.1, 3.1.3):
+ *   - first block: its own box, or (seed_first) a box from pt_seed_block on
+ *     its samples with PT_RANGE_SIGMA and seed_nsig standard errors; slots the
+ *     given box fixes stay fixed;
+ *   - later blocks start warm from the track's last accepted fit, whose phase
+ *     is re-expanded about the new block's reference time.  range_rule
+ *     PT_RUN_WARM: the block's own box half-widths times warm_narrow around
+ *     that prediction.  PT_RUN_EXTRAPOLATE (the running range of Sec. 3.1.1):
+ *     f0 spans the previous fit's frequency from the new block's start to its
+ *     end, f1 likewise its frequency rate, each widened to at least
+ *     warm_narrow times the block's own half-width; A is the prediction +-10 %;
+ *     phi0, f2 and Adot as PT_RUN_WARM;
+ *   - a fit fails when its best member sits at a non-phase bound
+ *     (PT_FLAG_AT_BOUND) or, when qc_phase_rad / qc_freq_hz are set and the
+ *     track's previous block was accepted, when the border phase or frequency
+ *     jump (pt_continuity) exceeds them.  A failed block is fitted again with
+ *     every half-width times `enlarge` (the phase one capped at pi), up to
+ *     max_attempts fits in all; after the last it is delivered with
+ *     PT_FLAG_ABANDONED (and PT_FLAG_DISCONTINUOUS when continuity failed),
+ *     and the track's next block is predicted from the last accepted fit.
+ * A block's arithmetic (mixed, FP64 phasor or FP64 per-sample) follows from
+ * its own box, and every block uses the same DE settings and geometry, so a
+ * block's result does not depend on which other blocks share its steps. */
 typedef struct pt_server pt_server;
+
+enum { PT_RUN_WARM = 0, PT_RUN_EXTRAPOLATE = 1 };
+enum { PT_FLAG_ABANDONED = 16, PT_FLAG_DISCONTINUOUS = 32 };
 
 typedef struct {
     int32_t max_slots;          /* resident blocks, 1..1024 */
     int32_t gens_per_step;      /* generations per scheduler step, >= 1 */
     int32_t max_pending;        /* queued (not yet admitted) blocks, >= 1 */
     int32_t spl, cpg;           /* objective geometry; 0, 0 = default for 400K samples */
-    int32_t reserved;
-    double warm_narrow;         /* box scale of warm starts, 0 (off) .. 1 */
+    int32_t range_rule;         /* PT_RUN_WARM or PT_RUN_EXTRAPOLATE */
+    double warm_narrow;         /* box scale of warm starts, 0 (no warm start) .. 1 */
     uint64_t hbm_budget_bytes;  /* device bytes resident blocks may hold */
     pt_de_settings de;          /* settings of every block (pop <= 256) */
+    int32_t seed_first;         /* 1: seed each track's first box from its samples */
+    int32_t seed_snippet;       /* pt_seed_opts.snippet (0 = default) */
+    double seed_nsig;           /* standard errors per seeded half-width (> 0) */
+    int32_t max_attempts;       /* fits per block, 1..16 (0 = 1: no retry) */
+    int32_t reserved;           /* 0 */
+    double enlarge;             /* half-width factor per retry (>= 1) */
+    double qc_phase_rad;        /* continuity limit on the border phase jump; 0 = off */
+    double qc_freq_hz;          /* continuity limit on the border frequency jump; 0 = off */
 } pt_server_config;
 
 typedef struct {
     uint64_t ticket;            /* from pt_server_submit */
     int32_t track;
-    int32_t warm;               /* 1: warm-started from the track's previous fit */
+    int32_t warm;               /* 0: given box, 1: warm start, 2: seeded from its samples */
     double t_submit, t_done;    /* seconds on the server clock */
-    pt_box box;                 /* search box the fit used */
+    pt_box box;                 /* search box of the delivered fit */
     pt_fit fit;
+    int32_t attempts;           /* fits run for this block */
+    int32_t qc;                 /* continuity check: 0 not made, 1 passed, -1 failed */
+    double border_dphi;         /* pt_continuity against the previous block, when qc != 0 */
+    double border_dfreq;
 } pt_server_result;
 
 int pt_server_create(pt_ctx* ctx, const pt_server_config* cfg, pt_server** out);
@@ -286,7 +389,8 @@ void pt_server_destroy(pt_server* srv);
 
 /* Queue a block of `track` (samples copied by the call, host or device).
  * PT_EBUSY when max_pending blocks are already queued; PT_EINVAL when the
- * block alone exceeds the HBM budget. */
+ * block alone exceeds the HBM budget, or, with seed_first, when it is too
+ * short for the three seeding snippets. */
 int pt_server_submit(pt_server* srv, int32_t track, const pt_block* block, uint64_t* ticket);
 
 /* One scheduler step on hip_stream (admit, run gens_per_step generations,

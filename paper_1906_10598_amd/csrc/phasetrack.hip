@@ -21,6 +21,7 @@
 
 #include "../../include/phasetrack.h"
 #include "kernels.h"
+#include "seed.h"
 
 using namespace pt;
 
@@ -252,6 +253,10 @@ struct pt_ctx {
     int last_arith = PT_ARITH_FP64_POLY;
     uint64_t spin_ticks = 0;
     DevBuf errflag;
+    // initial-range estimation
+    int seed_max_log = 0;  // largest log2(snippet) the device's LDS allows
+    DevBuf seed_out, seed_stage;
+    PinBuf hseed;
     // geometry
     Geometry forced{0, 0};
     std::map<std::tuple<int, int, int>, Geometry> tuned;  // (size class, P, mixed)
@@ -705,6 +710,15 @@ int pt_ctx_create(int device, pt_ctx** out) {
     if (hipDeviceGetAttribute(&clk_khz, hipDeviceAttributeWallClockRate, device) != hipSuccess || clk_khz <= 0)
         clk_khz = 100000;
     c->spin_ticks = (uint64_t)clk_khz * 1000ull * 5ull;  // 5 s
+    int lds_max = 0;
+    if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess)
+        lds_max = 65536;
+    // 16 bytes of LDS per snippet sample plus the kernel's 1 KiB of reduction space
+    for (int lg = kSeedMaxLog; lg >= 6; --lg)
+        if ((16 << lg) + 1024 <= lds_max) {
+            c->seed_max_log = lg;
+            break;
+        }
     HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
     *out = c.release();
     return PT_OK;
@@ -722,10 +736,11 @@ void pt_ctx_destroy(pt_ctx* ctx) {
     }
     DevBuf* bufs[] = {&ctx->desc,    &ctx->pop,      &ctx->trial,   &ctx->fpop,  &ctx->partials, &ctx->hist,
                       &ctx->state,   &ctx->rec,      &ctx->staging, &ctx->eval_pop, &ctx->scratch, &ctx->errflag,
-                      &ctx->sync};
+                      &ctx->sync,    &ctx->seed_out, &ctx->seed_stage};
     for (DevBuf* b : bufs) b->release();
     ctx->hdesc.release();
     ctx->hrec.release();
+    ctx->hseed.release();
     ctx->hstate.release();
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     delete ctx;
@@ -925,6 +940,146 @@ int pt_los_accel(const pt_fit* fit, double t, double f_carrier_hz, double M2, in
     return PT_OK;
 }
 
+int pt_continuity(const pt_fit* a, const pt_fit* b, double* dphi_rad, double* dfreq_hz) {
+    if (!a || !b) return fail(PT_EINVAL, "fit is null");
+    const double ta = a->t_right, tb = b->t_left;
+    const double d = fit_phase(a, ta) - fit_phase(b, tb);
+    if (dphi_rad) *dphi_rad = std::remainder(d, 2.0 * M_PI);
+    if (dfreq_hz) {
+        const double fa = a->coef[2] + a->coef[3] * ta + a->coef[4] * ta * ta / 2.0;
+        const double fb = b->coef[2] + b->coef[3] * tb + b->coef[4] * tb * tb / 2.0;
+        *dfreq_hz = fa - fb;
+    }
+    return PT_OK;
+}
+
+// ------------------------------------------------- range determination (seed)
+int pt_seed_max_snippet(pt_ctx* ctx) { return ctx && ctx->seed_max_log ? 1 << ctx->seed_max_log : 0; }
+
+int pt_seed_block(pt_ctx* ctx, const pt_block* block, const pt_seed_opts* opts, void* hip_stream, pt_seed* out) {
+    if (!ctx || !block || !out) return fail(PT_EINVAL, "ctx / block / out is null");
+    if (!block->samples) return fail(PT_EINVAL, "samples is null");
+    if (block->dtype != PT_F32 && block->dtype != PT_F64) return fail(PT_EINVAL, "dtype %d", block->dtype);
+    if (!(block->fs > 0) || !std::isfinite(block->fs)) return fail(PT_EINVAL, "fs must be > 0");
+    if (!std::isnan(block->ref) && !std::isfinite(block->ref)) return fail(PT_EINVAL, "ref not finite");
+    if (ctx->seed_max_log == 0) return fail(PT_EUNSUPPORTED, "device LDS too small for the spectrum kernel");
+    const int maxM = 1 << ctx->seed_max_log;
+    int M = opts && opts->snippet ? opts->snippet : std::min(4096, maxM);
+    if (M < 64 || M > maxM || (M & (M - 1))) return fail(PT_EINVAL, "snippet %d: a power of two in [64, %d]", M, maxM);
+    const int64_t n = block->n;
+    if (n < M) return fail(PT_EINVAL, "block of %lld samples is shorter than one snippet (%d)", (long long)n, M);
+    const int64_t spacing = opts && opts->spacing ? opts->spacing : n / 4;
+    if (spacing < 1) return fail(PT_EINVAL, "spacing %lld < 1", (long long)spacing);
+    const double ref = block_ref(block);
+    SeedStarts st;
+    for (int k = 0; k < 3; ++k) {
+        const int64_t c = (int64_t)std::floor(ref) + (int64_t)(k - 1) * spacing;
+        st.v[k] = c - M / 2;
+        if (st.v[k] < 0 || st.v[k] + M > n)
+            return fail(PT_EINVAL, "snippet %d [%lld, %lld) outside the block of %lld samples", k,
+                        (long long)st.v[k], (long long)(st.v[k] + M), (long long)n);
+    }
+    HIPCHK(hipSetDevice(ctx->device));
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const size_t esz = block->dtype == PT_F64 ? 8 : 4;
+    const void* src = block->samples;
+    SeedStarts dst = st;
+    int rc;
+    if (!block->on_device) {
+        // host samples: only the three snippets travel
+        if ((rc = ctx->seed_stage.ensure(3 * (size_t)M * esz))) return rc;
+        for (int k = 0; k < 3; ++k) {
+            HIPCHK(hipMemcpyAsync(static_cast<char*>(ctx->seed_stage.p) + (size_t)k * M * esz,
+                                  static_cast<const char*>(block->samples) + (size_t)st.v[k] * esz, (size_t)M * esz,
+                                  hipMemcpyHostToDevice, s));
+            dst.v[k] = (int64_t)k * M;
+        }
+        src = ctx->seed_stage.p;
+    }
+    if ((rc = ctx->seed_out.ensure(3 * sizeof(SeedSnippet))) || (rc = ctx->hseed.ensure(3 * sizeof(SeedSnippet))))
+        return rc;
+    int lg = 0;
+    while ((1 << lg) < M) ++lg;
+    const size_t lds = (size_t)16 * M;
+    SeedSnippet* dout = static_cast<SeedSnippet*>(ctx->seed_out.p);
+    if (block->dtype == PT_F64) {
+        auto k = k_seed_spectrum<double>;
+        if (lds > 65536) HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(k),
+                                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        hipLaunchKernelGGL(k, dim3(3), dim3(kSeedThreads), lds, s, static_cast<const double*>(src), dst, lg,
+                           block->fs, dout);
+    } else {
+        auto k = k_seed_spectrum<float>;
+        if (lds > 65536) HIPCHK(hipFuncSetAttribute(reinterpret_cast<const void*>(k),
+                                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        hipLaunchKernelGGL(k, dim3(3), dim3(kSeedThreads), lds, s, static_cast<const float*>(src), dst, lg,
+                           block->fs, dout);
+    }
+    HIPCHK(hipGetLastError());
+    SeedSnippet* h = static_cast<SeedSnippet*>(ctx->hseed.p);
+    HIPCHK(hipMemcpyAsync(h, dout, 3 * sizeof(SeedSnippet), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+
+    pt_seed r;
+    std::memset(&r, 0, sizeof r);
+    for (int k = 0; k < 3; ++k) {
+        r.f[k] = h[k].f;
+        r.amp[k] = h[k].amp;
+        r.noise[k] = h[k].noise;
+        r.bin[k] = h[k].bin;
+        r.t[k] = ((double)st.v[k] + 0.5 * (M - 1) - ref) / block->fs;
+    }
+    r.snippet = M;
+    const double dt = (double)spacing / block->fs;
+    r.f1 = (r.f[2] - r.f[0]) / (2.0 * dt);
+    r.f0 = r.f[1] - r.f1 * r.t[1];
+    r.f2 = (r.f[2] - 2.0 * r.f[1] + r.f[0]) / (dt * dt);
+    r.A = r.amp[1];
+    r.sigma = r.noise[1];
+    const double Ts = (double)M / block->fs;
+    const double sdf = r.A > 0 ? std::sqrt(6.0) * r.sigma / (M_PI * r.A * Ts * std::sqrt((double)M)) : INFINITY;
+    r.sd_f0 = sdf;
+    r.sd_f1 = std::sqrt(2.0) * sdf / (2.0 * dt);
+    r.sd_f2 = std::sqrt(6.0) * sdf / (dt * dt);
+    r.sd_A = r.sigma * std::sqrt(2.0 / M);
+    *out = r;
+    return PT_OK;
+}
+
+int pt_seed_box(const pt_seed* sd, int rule, double nsig, double T, int slope, pt_box* out) {
+    if (!sd || !out) return fail(PT_EINVAL, "seed / out is null");
+    if (rule != PT_RANGE_PAPER && rule != PT_RANGE_SIGMA) return fail(PT_EINVAL, "range rule %d", rule);
+    if (!(nsig >= 0) || !std::isfinite(nsig)) return fail(PT_EINVAL, "nsig must be finite and >= 0");
+    if (!(T > 0) || !std::isfinite(T)) return fail(PT_EINVAL, "T must be > 0");
+    if (!(sd->A > 0) || !std::isfinite(sd->sd_f0)) return fail(PT_EINVAL, "seed has no signal estimate");
+    double half[PT_NSLOT], mid[PT_NSLOT];
+    mid[0] = sd->A;
+    mid[1] = M_PI;
+    half[1] = M_PI;
+    mid[2] = sd->f0;
+    mid[3] = sd->f1;
+    mid[5] = 0.0;
+    half[5] = slope ? 0.2 * sd->A / T : 0.0;
+    if (rule == PT_RANGE_PAPER) {
+        half[0] = 0.1 * sd->A;
+        half[2] = 0.1 * std::fabs(sd->f0);
+        half[3] = std::max(0.1 * std::fabs(sd->f1), nsig * sd->sd_f1);
+        mid[4] = 0.0;
+        half[4] = 150.0 / M_PI;  // c3 = pi f2 / 3 in [-50, 50] rad/s^3
+    } else {
+        half[0] = std::max(0.1 * sd->A, nsig * sd->sd_A);
+        half[2] = nsig * sd->sd_f0;
+        half[3] = nsig * sd->sd_f1;
+        mid[4] = sd->f2;
+        half[4] = nsig * sd->sd_f2;
+    }
+    for (int j = 0; j < PT_NSLOT; ++j) {
+        out->lo[j] = mid[j] - half[j];
+        out->hi[j] = mid[j] + half[j];
+    }
+    return PT_OK;
+}
+
 // ------------------------------------------------------------ instrumentation
 int pt_ctx_set_launch_mode(pt_ctx* ctx, int mode) {
     if (!ctx) return fail(PT_EINVAL, "ctx is null");
@@ -1047,23 +1202,27 @@ int pt_ctx_autotune(pt_ctx* ctx, int64_t n, int P, int precision, void* hip_stre
 }  // extern "C"
 
 // ==================================================================== server
-// Continuous batching of arriving blocks.  Each admitted block owns a device
-// slot (samples, population, partials, DE state).  A scheduler step runs
-// `gens_per_step` generations of every active slot in shared launches (one
-// objective grid over all slots' work units, then every slot's DE step);
-// blocks admitted while others are running join at the next step, and a
-// block that meets its stop rule is retired at the end of the step in which
-// it stopped.  A track's next block waits for its previous fit and starts
-// from it (warm start): the previous phase is re-expanded about the new
-// block's reference time (Sec. 3.1.1 running range) and the search box is
-// the block's own box narrowed by `warm_narrow` around that prediction.
+// Continuous batching of arriving blocks, run as a tracker (Sec. 3.1.1,
+// 3.1.3).  Each admitted block owns a device slot (samples, population,
+// partials, DE state).  A scheduler step runs `gens_per_step` generations of
+// every active slot in shared launches (per objective arithmetic one grid
+// over those slots' work units, then every slot's DE step); blocks admitted
+// while others run join at the next step, and a block that meets its stop
+// rule is checked (bound, continuity) and either retired, or re-initialised
+// in a wider box and run again, in the step in which it stopped.  A track's
+// next block waits for its previous block and starts from the last accepted
+// fit (warm start).
 struct pt_server {
     struct Slot {
         bool active = false, fresh = false;
         int track = -1;
         uint64_t ticket = 0;
         int gen = 0;
-        int warm = 0;
+        int warm = 0;      // 0 given box, 1 warm start, 2 seeded
+        int mode = 0;      // objective arithmetic of this block
+        int attempts = 0;  // fits started for this block
+        bool has_prev = false;  // `prev` is the accepted fit of the track's preceding block
+        pt_fit prev{};
         double t_submit = 0.0;
         size_t bytes = 0;
         pt_block blk{};
@@ -1078,14 +1237,14 @@ struct pt_server {
     };
     struct Track {
         bool busy = false, has_fit = false;
-        pt_fit last{};
-        int64_t n = 0;
-        double fs = 0.0, ref = 0.0;
+        bool contiguous = false;  // the most recent block was accepted (it is `last`)
+        pt_fit last{};            // last accepted fit
+        double t_since = 0.0;     // seconds from last's reference sample to the end of the latest block
+        double fs = 0.0;
     };
     pt_ctx* ctx = nullptr;
     pt_server_config cfg{};
     Geometry geo{16, 4};
-    int mode = 0;  // kernel arithmetic, fixed for the server's lifetime
     std::vector<Slot> slots;
     std::deque<Pending> pending;
     std::map<int, Track> tracks;
@@ -1125,6 +1284,59 @@ size_t slot_bytes(const pt_block& b, int P, int max_gens, int tile) {
            (size_t)(max_gens + 1) * 8 + sizeof(DeState);
 }
 
+// Objective arithmetic of one server block, from its own box only.
+int slot_mode(const pt_server* sv, const pt_block& b) {
+    if (sv->cfg.de.precision == PT_PREC_MIXED) return kModeMixed;
+    if (sv->ctx->fp64_method == PT_FP64_POLY) return kModePoly;
+    const double f1 = std::max(std::fabs(b.box.lo[3]), std::fabs(b.box.hi[3]));
+    const double f2 = std::max(std::fabs(b.box.lo[4]), std::fabs(b.box.hi[4]));
+    const double span = (double)b.n + std::fabs(b.ref);
+    return phasor_ok(sv->geo.spl, b.fs, span, f1, f2) ? kModePhasor : kModePoly;
+}
+
+// Warm box of a track's next block around the prediction from its last fit.
+void warm_box(const pt_server* sv, const pt_server::Track& tr, const pt_block& given, pt_block& b) {
+    const double dt = tr.t_since + b.ref / b.fs;
+    double pred[PT_NSLOT];
+    predict(tr.last.coef, dt, pred);
+    const double wn = sv->cfg.warm_narrow;
+    for (int j = 0; j < PT_NSLOT; ++j) {
+        const double half = 0.5 * (given.box.hi[j] - given.box.lo[j]);
+        if (half > 0) {
+            b.box.lo[j] = pred[j] - wn * half;
+            b.box.hi[j] = pred[j] + wn * half;
+        }
+    }
+    if (sv->cfg.range_rule != PT_RUN_EXTRAPOLATE) return;
+    // Sec. 3.1.1 running range: frequency and rate over the new block's span
+    const double* c = tr.last.coef;
+    const double ta = tr.t_since, tb = tr.t_since + (double)b.n / b.fs;
+    const double fa = c[2] + c[3] * ta + c[4] * ta * ta / 2.0, fb = c[2] + c[3] * tb + c[4] * tb * tb / 2.0;
+    const double ra = c[3] + c[4] * ta, rb = c[3] + c[4] * tb;
+    const double lo_v[2] = {std::min(fa, fb), std::min(ra, rb)}, hi_v[2] = {std::max(fa, fb), std::max(ra, rb)};
+    for (int q = 0; q < 2; ++q) {
+        const int j = 2 + q;
+        const double half = 0.5 * (given.box.hi[j] - given.box.lo[j]);
+        if (!(half > 0)) continue;
+        const double mid = 0.5 * (lo_v[q] + hi_v[q]);
+        b.box.lo[j] = std::min(lo_v[q], mid - wn * half);
+        b.box.hi[j] = std::max(hi_v[q], mid + wn * half);
+    }
+    if (given.box.hi[0] > given.box.lo[0]) {
+        b.box.lo[0] = pred[0] - 0.1 * std::fabs(pred[0]);
+        b.box.hi[0] = pred[0] + 0.1 * std::fabs(pred[0]);
+    }
+}
+
+// Snippet placement of the seeding step, or an error when it does not fit.
+int seed_fits(const pt_block* b, int M) {
+    const int64_t spacing = b->n / 4;
+    const int64_t c = (int64_t)std::floor(block_ref(b));
+    if (spacing < 1 || c - spacing - M / 2 < 0 || c + spacing + M / 2 > b->n)
+        return fail(PT_EINVAL, "block of %lld samples is too short for seeding snippets of %d", (long long)b->n, M);
+    return PT_OK;
+}
+
 int server_admit(pt_server* sv, hipStream_t s) {
     const int P = sv->cfg.de.pop;
     const int tile = kThreads * sv->geo.spl;
@@ -1158,19 +1370,29 @@ int server_admit(pt_server* sv, hipStream_t s) {
         sl.blk.on_device = 1;
         sl.blk.ref = block_ref(&it->blk);
         sl.warm = 0;
+        sl.has_prev = false;
         if (tr.has_fit && sv->cfg.warm_narrow > 0.0 && tr.fs == it->blk.fs) {
-            const double dt = ((double)tr.n - tr.ref) / tr.fs + sl.blk.ref / sl.blk.fs;
-            double pred[PT_NSLOT];
-            predict(tr.last.coef, dt, pred);
-            for (int j = 0; j < PT_NSLOT; ++j) {
-                const double half = 0.5 * (it->blk.box.hi[j] - it->blk.box.lo[j]);
-                if (half > 0) {
-                    sl.blk.box.lo[j] = pred[j] - sv->cfg.warm_narrow * half;
-                    sl.blk.box.hi[j] = pred[j] + sv->cfg.warm_narrow * half;
-                }
-            }
+            warm_box(sv, tr, it->blk, sl.blk);
             sl.warm = 1;
+            sl.has_prev = tr.contiguous;
+            sl.prev = tr.last;
+        } else if (!tr.has_fit && sv->cfg.seed_first) {
+            pt_seed_opts so{sv->cfg.seed_snippet, 0, 0};
+            pt_seed sd;
+            if ((rc = pt_seed_block(sv->ctx, &sl.blk, &so, s, &sd))) return rc;
+            pt_box bx;
+            const int slope = it->blk.box.lo[5] != it->blk.box.hi[5];
+            if ((rc = pt_seed_box(&sd, PT_RANGE_SIGMA, sv->cfg.seed_nsig, (double)sl.blk.n / sl.blk.fs, slope, &bx)))
+                return rc;
+            for (int j = 0; j < PT_NSLOT; ++j)
+                if (it->blk.box.lo[j] < it->blk.box.hi[j]) {  // slots the caller fixes stay fixed
+                    sl.blk.box.lo[j] = bx.lo[j];
+                    sl.blk.box.hi[j] = bx.hi[j];
+                }
+            sl.warm = 2;
         }
+        sl.mode = slot_mode(sv, sl.blk);
+        sl.attempts = 1;
         sl.active = true;
         sl.fresh = true;
         sl.track = it->track;
@@ -1180,14 +1402,25 @@ int server_admit(pt_server* sv, hipStream_t s) {
         sl.bytes = need;
         sv->used_bytes += need;
         tr.busy = true;
-        tr.n = it->blk.n;
         tr.fs = it->blk.fs;
-        tr.ref = sl.blk.ref;
         // the host copy can go once the stream has consumed it
         HIPCHK(hipStreamSynchronize(s));
         it = sv->pending.erase(it);
     }
     return PT_OK;
+}
+
+// Widen a failed block's box for its next attempt (same centres).
+void enlarge_box(pt_box& b, double k) {
+    for (int j = 0; j < PT_NSLOT; ++j) {
+        double half = 0.5 * (b.hi[j] - b.lo[j]);
+        if (!(half > 0)) continue;
+        const double mid = 0.5 * (b.lo[j] + b.hi[j]);
+        half *= k;
+        if (j == 1) half = std::min(half, M_PI);
+        b.lo[j] = mid - half;
+        b.hi[j] = mid + half;
+    }
 }
 
 }  // namespace
@@ -1205,17 +1438,28 @@ int pt_server_create(pt_ctx* ctx, const pt_server_config* cfg, pt_server** out) 
         return fail(PT_EINVAL, "gens_per_step %d", cfg->gens_per_step);
     if (cfg->max_pending < 1) return fail(PT_EINVAL, "max_pending %d", cfg->max_pending);
     if (!(cfg->warm_narrow >= 0.0 && cfg->warm_narrow <= 1.0)) return fail(PT_EINVAL, "warm_narrow outside [0, 1]");
+    if (cfg->range_rule != PT_RUN_WARM && cfg->range_rule != PT_RUN_EXTRAPOLATE)
+        return fail(PT_EINVAL, "range_rule %d", cfg->range_rule);
     if ((cfg->spl || cfg->cpg) && !(spl_ok(cfg->spl) && cpg_ok(cfg->cpg)))
         return fail(PT_EINVAL, "unsupported geometry (%d, %d)", cfg->spl, cfg->cpg);
+    if (cfg->seed_first != 0 && cfg->seed_first != 1) return fail(PT_EINVAL, "seed_first %d", cfg->seed_first);
+    if (cfg->seed_first) {
+        const int maxM = pt_seed_max_snippet(ctx);
+        const int M = cfg->seed_snippet;
+        if (M && (M < 64 || M > maxM || (M & (M - 1))))
+            return fail(PT_EINVAL, "seed_snippet %d: a power of two in [64, %d]", M, maxM);
+        if (!(cfg->seed_nsig > 0) || !std::isfinite(cfg->seed_nsig)) return fail(PT_EINVAL, "seed_nsig must be > 0");
+    }
+    if (cfg->max_attempts < 0 || cfg->max_attempts > 16) return fail(PT_EINVAL, "max_attempts %d", cfg->max_attempts);
+    if (cfg->max_attempts > 1 && !(cfg->enlarge >= 1.0 && std::isfinite(cfg->enlarge)))
+        return fail(PT_EINVAL, "enlarge must be >= 1");
+    if (!(cfg->qc_phase_rad >= 0) || !(cfg->qc_freq_hz >= 0)) return fail(PT_EINVAL, "qc limits must be >= 0");
     std::unique_ptr<pt_server> sv(new (std::nothrow) pt_server());
     if (!sv) return fail(PT_ENOMEM, "out of host memory");
     sv->ctx = ctx;
     sv->cfg = *cfg;
+    if (sv->cfg.max_attempts == 0) sv->cfg.max_attempts = 1;
     sv->geo = cfg->spl ? Geometry{cfg->spl, cfg->cpg} : default_geometry(400000, cfg->de.pop);
-    // one arithmetic for every block of the server, so that a block's result
-    // never depends on which blocks share its steps
-    sv->mode = cfg->de.precision == PT_PREC_MIXED ? kModeMixed
-                                                  : (ctx->fp64_method == PT_FP64_POLY ? kModePoly : kModePhasor);
     sv->slots.resize(cfg->max_slots);
     *out = sv.release();
     return PT_OK;
@@ -1247,14 +1491,9 @@ int pt_server_submit(pt_server* sv, int32_t track, const pt_block* block, uint64
     const int tile = kThreads * sv->geo.spl;
     if (slot_bytes(*block, sv->cfg.de.pop, sv->cfg.de.max_gens, tile) > sv->cfg.hbm_budget_bytes)
         return fail(PT_EINVAL, "block needs more than the whole HBM budget");
-    if (sv->mode == kModePhasor) {
-        // warm boxes move the f1 centre by f2 dt; check with generous margins
-        const pt_box& bx = block->box;
-        const double f1 = 2.0 * std::max(std::fabs(bx.lo[3]), std::fabs(bx.hi[3])) + 1.0;
-        const double f2 = 2.0 * std::max(std::fabs(bx.lo[4]), std::fabs(bx.hi[4]));
-        const double span = 2.0 * ((double)block->n + std::fabs(block_ref(block)));
-        if (!phasor_ok(sv->geo.spl, block->fs, span, f1, f2))
-            return fail(PT_EINVAL, "block needs the per-sample FP64 path: create the server with PT_FP64_POLY");
+    if (sv->cfg.seed_first) {
+        const int M = sv->cfg.seed_snippet ? sv->cfg.seed_snippet : std::min(4096, pt_seed_max_snippet(sv->ctx));
+        if ((rc = seed_fits(block, M))) return rc;
     }
     pt_server::Pending pd;
     pd.ticket = sv->next_ticket++;
@@ -1282,9 +1521,16 @@ int pt_server_step(pt_server* sv, void* hip_stream, int32_t* n_active, int32_t* 
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
     int rc = server_admit(sv, s);
     if (rc) return rc;
+    // active slots, grouped by objective kernel (arithmetic, dtype, slope)
+    auto kernel_key = [&](int k) {
+        const pt_server::Slot& sl = sv->slots[k];
+        const bool slope = sl.blk.box.lo[5] != 0.0 || sl.blk.box.hi[5] != 0.0;
+        return std::make_tuple(sl.mode, sl.blk.dtype, (int)slope);
+    };
     std::vector<int> act;
     for (int k = 0; k < (int)sv->slots.size(); ++k)
         if (sv->slots[k].active) act.push_back(k);
+    std::stable_sort(act.begin(), act.end(), [&](int a, int b) { return kernel_key(a) < kernel_key(b); });
     const int nb = (int)act.size();
     if (n_pending) *n_pending = (int)sv->pending.size();
     if (nb == 0) {
@@ -1300,13 +1546,21 @@ int pt_server_step(pt_server* sv, void* hip_stream, int32_t* n_active, int32_t* 
         (rc = sv->hstate.ensure(sizeof(DeState) * nb)))
         return rc;
     BlockDesc* hd = static_cast<BlockDesc*>(sv->hdesc.p);
-    int units = 0, dtype = -1;
-    bool slope = false, any_fresh = false;
+    struct Launch {
+        int first, count, units;
+        ObjKernel k;
+    };
+    std::vector<Launch> launches;
+    bool any_fresh = false;
     for (int q = 0; q < nb; ++q) {
         pt_server::Slot& sl = sv->slots[act[q]];
         const pt_block& B = sl.blk;
-        if (dtype < 0) dtype = B.dtype;
-        if (B.dtype != dtype) return fail(PT_EINVAL, "server blocks must share one sample dtype");
+        if (launches.empty() || kernel_key(act[q]) != kernel_key(act[launches.back().first])) {
+            const auto key = kernel_key(act[q]);
+            launches.push_back({q, 0, 0, objective_kernel(std::get<1>(key), sv->geo, std::get<0>(key),
+                                                          std::get<2>(key) != 0)});
+        }
+        Launch& L = launches.back();
         BlockDesc d;
         std::memset(&d, 0, sizeof d);
         d.samples = B.samples;
@@ -1321,12 +1575,12 @@ int pt_server_step(pt_server* sv, void* hip_stream, int32_t* n_active, int32_t* 
             d.hi[j] = B.box.hi[j];
             if (B.box.lo[j] < B.box.hi[j]) d.act[D++] = j;
         }
-        if (B.box.lo[5] != 0.0 || B.box.hi[5] != 0.0) slope = true;
         d.D = D;
         d.ntiles = (int)((B.n + tile - 1) / tile);
         d.ngroups = groups;
-        d.unit_begin = units;
-        units += d.ntiles * groups;
+        d.unit_begin = L.units;  // units count from the start of this block's launch group
+        L.units += d.ntiles * groups;
+        ++L.count;
         d.window = de.window;
         d.max_gens = de.max_gens;
         d.F = de.F;
@@ -1348,7 +1602,6 @@ int pt_server_step(pt_server* sv, void* hip_stream, int32_t* n_active, int32_t* 
         any_fresh = any_fresh || sl.fresh;
         hd[q] = d;
     }
-    const int mode = sv->mode;
     HIPCHK(hipMemcpyAsync(sv->desc.p, hd, sizeof(BlockDesc) * nb, hipMemcpyHostToDevice, s));
     const BlockDesc* dd = static_cast<const BlockDesc*>(sv->desc.p);
     const unsigned de_threads = pow2_at_least(P);
@@ -1357,10 +1610,11 @@ int pt_server_step(pt_server* sv, void* hip_stream, int32_t* n_active, int32_t* 
         hipLaunchKernelGGL(k_de_init_fresh, dim3(nb), dim3(de_threads), 0, s, dd);
         HIPCHK(hipGetLastError());
     }
-    ObjKernel obj = objective_kernel(dtype, sv->geo, mode, slope);
-    const int grid = (units + 7) / 8 * 8;
     for (int k = 0; k < sv->cfg.gens_per_step; ++k) {
-        hipLaunchKernelGGL(obj, dim3(grid), dim3(kThreads), 0, s, dd, nb, units);
+        for (const Launch& L : launches) {
+            const int grid = (L.units + 7) / 8 * 8;
+            hipLaunchKernelGGL(L.k, dim3(grid), dim3(kThreads), 0, s, dd + L.first, L.count, L.units);
+        }
         hipLaunchKernelGGL(k_de_step, dim3(nb), dim3(de_threads), de_lds, s, dd);
     }
     HIPCHK(hipGetLastError());
@@ -1373,12 +1627,43 @@ int pt_server_step(pt_server* sv, void* hip_stream, int32_t* n_active, int32_t* 
     HIPCHK(hipStreamSynchronize(s));
     const double now = sv->clock();
     const FitRecord* r = static_cast<const FitRecord*>(sv->hrec.p);
+    const pt_server_config& cf = sv->cfg;
+    const bool qc_on = cf.qc_phase_rad > 0 || cf.qc_freq_hz > 0;
     int still = 0;
     for (int q = 0; q < nb; ++q) {
         pt_server::Slot& sl = sv->slots[act[q]];
         sl.fresh = false;
         sl.gen = hst[q].gen;
         if (!hst[q].done) {
+            ++still;
+            continue;
+        }
+        pt_fit f;
+        std::memset(&f, 0, sizeof f);
+        for (int j = 0; j < PT_NSLOT; ++j) f.coef[j] = r[q].x[j];
+        f.objective = r[q].f;
+        f.generations = r[q].gens;
+        f.flags = r[q].flags;
+        f.ref = sl.blk.ref;
+        f.t_left = (0.0 - f.ref) / sl.blk.fs;
+        f.t_right = ((double)sl.blk.n - f.ref) / sl.blk.fs;
+        derive(&f);
+        int qc = 0;
+        double dphi = 0.0, dfreq = 0.0;
+        if (qc_on && sl.has_prev) {
+            pt_continuity(&sl.prev, &f, &dphi, &dfreq);
+            const bool bad = (cf.qc_phase_rad > 0 && !(std::fabs(dphi) <= cf.qc_phase_rad)) ||
+                             (cf.qc_freq_hz > 0 && !(std::fabs(dfreq) <= cf.qc_freq_hz));
+            qc = bad ? -1 : 1;
+        }
+        const bool failed = (f.flags & PT_FLAG_AT_BOUND) || qc < 0;
+        if (failed && sl.attempts < cf.max_attempts) {
+            // Sec. 3.1.1: enlarge the range and search again
+            enlarge_box(sl.blk.box, cf.enlarge);
+            sl.mode = slot_mode(sv, sl.blk);
+            ++sl.attempts;
+            sl.fresh = true;
+            sl.gen = 0;
             ++still;
             continue;
         }
@@ -1390,20 +1675,24 @@ int pt_server_step(pt_server* sv, void* hip_stream, int32_t* n_active, int32_t* 
         res.t_submit = sl.t_submit;
         res.t_done = now;
         res.box = sl.blk.box;
-        pt_fit& f = res.fit;
-        for (int j = 0; j < PT_NSLOT; ++j) f.coef[j] = r[q].x[j];
-        f.objective = r[q].f;
-        f.generations = r[q].gens;
-        f.flags = r[q].flags;
-        f.ref = sl.blk.ref;
-        f.t_left = (0.0 - f.ref) / sl.blk.fs;
-        f.t_right = ((double)sl.blk.n - f.ref) / sl.blk.fs;
-        derive(&f);
+        if (failed) f.flags |= PT_FLAG_ABANDONED | (qc < 0 ? PT_FLAG_DISCONTINUOUS : 0);
+        res.fit = f;
+        res.attempts = sl.attempts;
+        res.qc = qc;
+        res.border_dphi = dphi;
+        res.border_dfreq = dfreq;
         sv->done.push_back(res);
         pt_server::Track& tr = sv->tracks[sl.track];
         tr.busy = false;
-        tr.has_fit = true;
-        tr.last = f;
+        if (!failed) {
+            tr.has_fit = true;
+            tr.contiguous = true;
+            tr.last = f;
+            tr.t_since = f.t_right;
+        } else {
+            tr.contiguous = false;
+            tr.t_since += (double)sl.blk.n / sl.blk.fs;
+        }
         sv->used_bytes -= sl.bytes;
         sl.active = false;
     }

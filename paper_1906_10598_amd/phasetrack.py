@@ -21,6 +21,9 @@ PT_OK, PT_EINVAL, PT_ENOMEM, PT_EDEVICE, PT_EBUSY, PT_EUNSUPPORTED = 0, -1, -2, 
 PT_F32, PT_F64 = 0, 1
 PT_PREC_FP64, PT_PREC_MIXED = 0, 1
 PT_FLAG_CONVERGED, PT_FLAG_MAXGEN, PT_FLAG_VTR, PT_FLAG_AT_BOUND = 1, 2, 4, 8
+PT_FLAG_ABANDONED, PT_FLAG_DISCONTINUOUS = 16, 32
+PT_RANGE_PAPER, PT_RANGE_SIGMA = 0, 1
+PT_RUN_WARM, PT_RUN_EXTRAPOLATE = 0, 1
 PT_LAUNCH_AUTO, PT_LAUNCH_GRAPH, PT_LAUNCH_PERSISTENT = 0, 1, 2
 PT_FP64_AUTO, PT_FP64_POLY = 0, 1
 PT_OBJ_CHI2, PT_OBJ_COR = 0, 1
@@ -96,10 +99,18 @@ class pt_server_config(ctypes.Structure):
         ("max_pending", ctypes.c_int32),
         ("spl", ctypes.c_int32),
         ("cpg", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("range_rule", ctypes.c_int32),
         ("warm_narrow", ctypes.c_double),
         ("hbm_budget_bytes", ctypes.c_uint64),
         ("de", pt_de_settings),
+        ("seed_first", ctypes.c_int32),
+        ("seed_snippet", ctypes.c_int32),
+        ("seed_nsig", ctypes.c_double),
+        ("max_attempts", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("enlarge", ctypes.c_double),
+        ("qc_phase_rad", ctypes.c_double),
+        ("qc_freq_hz", ctypes.c_double),
     ]
 
 
@@ -112,6 +123,34 @@ class pt_server_result(ctypes.Structure):
         ("t_done", ctypes.c_double),
         ("box", pt_box),
         ("fit", pt_fit),
+        ("attempts", ctypes.c_int32),
+        ("qc", ctypes.c_int32),
+        ("border_dphi", ctypes.c_double),
+        ("border_dfreq", ctypes.c_double),
+    ]
+
+
+class pt_seed_opts(ctypes.Structure):
+    _fields_ = [("snippet", ctypes.c_int32), ("reserved", ctypes.c_int32), ("spacing", ctypes.c_int64)]
+
+
+class pt_seed(ctypes.Structure):
+    _fields_ = [
+        ("f", ctypes.c_double * 3),
+        ("amp", ctypes.c_double * 3),
+        ("noise", ctypes.c_double * 3),
+        ("t", ctypes.c_double * 3),
+        ("bin", ctypes.c_int32 * 3),
+        ("snippet", ctypes.c_int32),
+        ("f0", ctypes.c_double),
+        ("f1", ctypes.c_double),
+        ("f2", ctypes.c_double),
+        ("A", ctypes.c_double),
+        ("sigma", ctypes.c_double),
+        ("sd_f0", ctypes.c_double),
+        ("sd_f1", ctypes.c_double),
+        ("sd_f2", ctypes.c_double),
+        ("sd_A", ctypes.c_double),
     ]
 
 
@@ -140,6 +179,12 @@ def _signatures(L):
         "pt_connect_phase": ([ctypes.POINTER(pt_fit), i32, _DP, _DP], i32),
         "pt_los_accel": ([ctypes.POINTER(pt_fit), ctypes.c_double, ctypes.c_double, ctypes.c_double, i32,
                           _DP], i32),
+        "pt_continuity": ([ctypes.POINTER(pt_fit), ctypes.POINTER(pt_fit), _DP, _DP], i32),
+        "pt_seed_max_snippet": ([_CTX], i32),
+        "pt_seed_block": ([_CTX, ctypes.POINTER(pt_block), ctypes.POINTER(pt_seed_opts), _VP,
+                           ctypes.POINTER(pt_seed)], i32),
+        "pt_seed_box": ([ctypes.POINTER(pt_seed), i32, ctypes.c_double, ctypes.c_double, i32,
+                         ctypes.POINTER(pt_box)], i32),
         "pt_time_objective": ([_CTX, ctypes.POINTER(pt_block), _VP, i32, i32, i32, _VP, _DP], i32),
         "pt_server_create": ([_CTX, ctypes.POINTER(pt_server_config), ctypes.POINTER(_CTX)], i32),
         "pt_server_destroy": ([_CTX], None),
@@ -323,12 +368,43 @@ def pt_server_clock(srv) -> float:
 
 def make_server_config(de: pt_de_settings, max_slots: int = 64, gens_per_step: int = 32,
                        max_pending: int = 4096, spl: int = 16, cpg: int = 4, warm_narrow: float = 0.7,
-                       hbm_budget_bytes: int = 64 << 30) -> pt_server_config:
+                       hbm_budget_bytes: int = 64 << 30, range_rule: int = PT_RUN_WARM, seed_first: bool = False,
+                       seed_snippet: int = 0, seed_nsig: float = 10.0, max_attempts: int = 1,
+                       enlarge: float = 2.0, qc_phase_rad: float = 0.0, qc_freq_hz: float = 0.0) -> pt_server_config:
     c = pt_server_config()
     c.max_slots, c.gens_per_step, c.max_pending = max_slots, gens_per_step, max_pending
     c.spl, c.cpg, c.warm_narrow, c.hbm_budget_bytes = spl, cpg, warm_narrow, hbm_budget_bytes
     c.de = de
+    c.range_rule, c.seed_first, c.seed_snippet, c.seed_nsig = range_rule, int(seed_first), seed_snippet, seed_nsig
+    c.max_attempts, c.enlarge, c.qc_phase_rad, c.qc_freq_hz = max_attempts, enlarge, qc_phase_rad, qc_freq_hz
     return c
+
+
+def pt_continuity(a: pt_fit, b: pt_fit):
+    """(border phase jump [rad, wrapped], border frequency jump [Hz]) of adjacent blocks a, b."""
+    dp, df = ctypes.c_double(), ctypes.c_double()
+    _check(lib().pt_continuity(ctypes.byref(a), ctypes.byref(b), ctypes.byref(dp), ctypes.byref(df)),
+           "pt_continuity")
+    return dp.value, df.value
+
+
+def pt_seed_max_snippet(ctx) -> int:
+    return lib().pt_seed_max_snippet(ctx)
+
+
+def pt_seed_block(ctx, block: pt_block, snippet: int = 0, spacing: int = 0, stream=None) -> pt_seed:
+    o = pt_seed_opts()
+    o.snippet, o.spacing = snippet, spacing
+    out = pt_seed()
+    _check(lib().pt_seed_block(ctx, ctypes.byref(block), ctypes.byref(o), stream, ctypes.byref(out)),
+           "pt_seed_block")
+    return out
+
+
+def pt_seed_box(seed: pt_seed, rule: int, nsig: float, T: float, slope: bool = False) -> pt_box:
+    b = pt_box()
+    _check(lib().pt_seed_box(ctypes.byref(seed), rule, nsig, T, int(slope), ctypes.byref(b)), "pt_seed_box")
+    return b
 
 
 def pt_ctx_set_launch_mode(ctx, mode: int):

@@ -154,3 +154,51 @@ def test_device_cosine_polynomials():
         err32 = max(err32, abs(q - exact))
     assert err64 < 2e-15  # unfused Horner here; the device fuses each step
     assert err32 < 4e-7
+
+
+def _seed_struct(r):
+    s = ptk.pt_seed()
+    for k in ("f0", "f1", "f2", "A", "sd_f0", "sd_f1", "sd_f2", "sd_A"):
+        setattr(s, k, r[k])
+    s.sigma = 0.1
+    return s
+
+
+def test_seed_box_rules_match_oracle():
+    from oracle import seed as oseed
+
+    rng = np.random.default_rng(9)
+    for _ in range(20):
+        r = dict(A=rng.uniform(0.1, 2), f0=rng.uniform(-2e4, 2e4), f1=rng.uniform(-5, 5), f2=rng.uniform(-.1, .1),
+                 sd_f0=rng.uniform(1e-3, 1), sd_f1=rng.uniform(1e-3, 1), sd_f2=rng.uniform(1e-3, 1),
+                 sd_A=rng.uniform(1e-4, 1e-1))
+        nsig, T = rng.uniform(1, 20), rng.uniform(1, 20)
+        for rule, name in ((ptk.PT_RANGE_PAPER, "paper"), (ptk.PT_RANGE_SIGMA, "sigma")):
+            for slope in (False, True):
+                b = ptk.pt_seed_box(_seed_struct(r), rule, nsig, T, slope)
+                lo, hi = oseed.seed_box(r, name, nsig, T, slope)
+                assert np.allclose(list(b.lo), lo, rtol=1e-15, atol=1e-13)
+                assert np.allclose(list(b.hi), hi, rtol=1e-15, atol=1e-13)
+    with pytest.raises(ptk.PtError):
+        ptk.pt_seed_box(_seed_struct(dict(r, A=0.0)), ptk.PT_RANGE_SIGMA, 10, 8)
+    with pytest.raises(ptk.PtError):
+        ptk.pt_seed_box(_seed_struct(r), 5, 10, 8)
+
+
+def test_continuity_matches_oracle():
+    from oracle import seed as oseed
+
+    rng = np.random.default_rng(11)
+    for _ in range(20):
+        phi0, f0, f1, f2 = rng.uniform(0, 6), rng.uniform(-2e4, 2e4), rng.uniform(-5, 5), rng.uniform(-.05, .05)
+        T = rng.uniform(1, 10)
+        p, g0, g1, g2 = synth.shift_truth(phi0, f0, f1, f2, T)
+        jump, fjump = rng.uniform(-4, 4), rng.uniform(-1, 1)
+        a = _fit_from_coefs(oracle.derived.coefs_from_fit(phi0, f0, f1, f2), T)
+        b = _fit_from_coefs(oracle.derived.coefs_from_fit(p + jump, g0 + fjump, g1, g2), T)
+        dphi, dfreq = ptk.pt_continuity(a, b)
+        da = dict(phi0=phi0, f0=f0, f1=f1, f2=f2, t_left=a.t_left, t_right=a.t_right)
+        db = dict(phi0=p + jump, f0=g0 + fjump, f1=g1, f2=g2, t_left=b.t_left, t_right=b.t_right)
+        wp, wf = oseed.border_continuity(da, db)
+        assert abs(math.remainder(dphi - wp, 2 * math.pi)) < 1e-9 and abs(dfreq - wf) < 1e-9
+        assert abs(math.remainder(dphi + jump + 2 * math.pi * fjump * b.t_left, 2 * math.pi)) < 1e-6

@@ -1,0 +1,192 @@
+"""The serving loop as a tracker (Sec. 3.1.1 ranges, Sec. 3.1.3 continuity).
+
+  * seeded first blocks and warm continuations fit every block of several
+    tracks without a retry; every warm block passes the border-continuity
+    check, and f0 is within 30 CRLB of the truth (mirror-oriented);
+  * the boxes the server reports are the oracle's warm / running-range boxes
+    around the prediction from the previous fit;
+  * a frequency step inside a track: the warm box misses it, the block is
+    refitted in an enlarged box and succeeds; the delivered fit equals
+    pt_fit_block on the same block and box; with the continuity check on,
+    the same block is abandoned after max_attempts fits;
+  * a block's result is the same alone and in a mix of tracks.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle.seed as oseed
+import synth
+from gpu_util import ctx
+from paper_1906_10598_amd import phasetrack as ptk
+
+pytestmark = pytest.mark.gpu
+
+FS = 50_000.0
+
+
+def _de(gens=3000):
+    return ptk.make_settings(pop=40, max_gens=gens, F=0.5, CR=0.9, seed=0x19061059 ^ 0xDE, rel_tol=1e-9, window=50)
+
+
+def _blk(b):
+    return ptk.make_block(torch.from_numpy(b.samples), b.fs, b.lo, b.hi, ref=b.ref, stream=b.stream)
+
+
+def _serve(items, **cfg):
+    c = ctx()
+    srv = ptk.pt_server_create(c.handle, ptk.make_server_config(_de(), max_slots=16, **cfg))
+    try:
+        tickets = {}
+        for it in items:
+            t = ptk.pt_server_submit(srv, it["track"], _blk(it["block"]))
+            assert t is not None
+            tickets[t] = (it["track"], it["seq"])
+        out = {}
+        for _ in range(20000):
+            a, p = ptk.pt_server_step(srv, ptk.current_stream())
+            for r in ptk.pt_server_poll(srv):
+                out[tickets[r.ticket]] = r
+            if a == 0 and p == 0:
+                break
+        assert len(out) == len(items)
+        return out
+    finally:
+        ptk.pt_server_destroy(srv)
+
+
+def _oriented(truth, f0):
+    t = np.array(truth, dtype=np.float64)
+    if t[2] * f0 < 0:
+        t[1:5] = -t[1:5]
+    return t
+
+
+def _crlb(b):
+    return math.sqrt(6.0) * b.sigma / (math.pi * b.truth[0] * (b.n / b.fs) * math.sqrt(b.n))
+
+
+def _key(r):
+    return list(r.fit.coef) + [r.fit.objective, r.fit.generations, r.fit.flags, r.attempts, r.qc]
+
+
+def test_seeded_tracks_pass_continuity():
+    items = synth.config4_stream(seed=5, ntracks=3, nblocks=9, lengths=(200_000, 400_000))
+    mx = ptk.pt_seed_max_snippet(ctx().handle)
+    kw = dict(seed_first=True, seed_snippet=mx, max_attempts=3, qc_phase_rad=0.5, qc_freq_hz=0.5)
+    res = _serve(items, **kw)
+    prev = {}
+    for it in items:
+        r = res[(it["track"], it["seq"])]
+        b = it["block"]
+        assert r.attempts == 1 and not (r.fit.flags & (ptk.PT_FLAG_ABANDONED | ptk.PT_FLAG_AT_BOUND)), it["seq"]
+        truth = _oriented(b.truth, r.fit.coef[2])
+        err = (r.fit.coef[2] - truth[2]) / _crlb(b)
+        print(f"[tracker] track {it['track']} seq {it['seq']} warm {r.warm} qc {r.qc} "
+              f"dphi {r.border_dphi:+.2e} dfreq {r.border_dfreq:+.2e} f0 err {err:+.2f} CRLB "
+              f"gens {r.fit.generations}", flush=True)
+        assert abs(err) < 30
+        if it["seq"] == 0:
+            assert r.warm == 2 and r.qc == 0
+        else:
+            assert r.warm == 1 and r.qc == 1
+            assert abs(r.border_dphi) < 0.5 and abs(r.border_dfreq) < 0.5
+            # the reported box is the warm box around the prediction from the previous fit
+            p = prev[it["track"]]
+            lo, hi = oseed.running_box(list(p.fit.coef), p.fit.t_right, b.n, b.fs, b.ref, b.lo, b.hi, 0.7, False)
+            assert np.allclose(list(r.box.lo), lo, rtol=1e-12, atol=1e-9)
+            assert np.allclose(list(r.box.hi), hi, rtol=1e-12, atol=1e-9)
+            # and the continuity numbers are the oracle's
+            fa = dict(phi0=p.fit.coef[1], f0=p.fit.coef[2], f1=p.fit.coef[3], f2=p.fit.coef[4],
+                      t_left=p.fit.t_left, t_right=p.fit.t_right)
+            fb = dict(phi0=r.fit.coef[1], f0=r.fit.coef[2], f1=r.fit.coef[3], f2=r.fit.coef[4],
+                      t_left=r.fit.t_left, t_right=r.fit.t_right)
+            dp, df = oseed.border_continuity(fa, fb)
+            assert abs(dp - r.border_dphi) < 1e-6 and abs(df - r.border_dfreq) < 1e-9
+        prev[it["track"]] = r
+    # alone == mix
+    for tr in sorted({it["track"] for it in items})[:1]:
+        alone = _serve([it for it in items if it["track"] == tr], **kw)
+        for k, r in alone.items():
+            assert _key(r) == _key(res[k])
+
+
+def test_running_range_rule_boxes():
+    items = synth.config4_stream(seed=6, ntracks=2, nblocks=6, lengths=(200_000,))
+    res = _serve(items, range_rule=ptk.PT_RUN_EXTRAPOLATE)
+    prev = {}
+    for it in items:
+        r = res[(it["track"], it["seq"])]
+        b = it["block"]
+        if it["seq"] > 0:
+            p = prev[it["track"]]
+            lo, hi = oseed.running_box(list(p.fit.coef), p.fit.t_right, b.n, b.fs, b.ref, b.lo, b.hi, 0.7, True)
+            assert np.allclose(list(r.box.lo), lo, rtol=1e-12, atol=1e-9)
+            assert np.allclose(list(r.box.hi), hi, rtol=1e-12, atol=1e-9)
+            # f0 spans |f1| T, up to tens of peak widths: reported, not asserted
+            print(f"[running range] track {it['track']} seq {it['seq']} box f0 +-{(hi[2] - lo[2]) / 2:.2f} Hz "
+                  f"f0 err {(r.fit.coef[2] - b.truth[2]) / _crlb(b):+.1f} CRLB gens {r.fit.generations}",
+                  flush=True)
+        prev[it["track"]] = r
+
+
+def _step_track(seed, jump_hz, nblocks=3, n=200_000):
+    """One track whose frequency steps by jump_hz at the start of block 1
+    (phase continuous), blocks of n samples, int16-quantised at 0 dB."""
+    rng = np.random.default_rng([0x19061059, 0x5EED, seed])
+    phi0, f0, f1, f2 = rng.uniform(0, 2 * math.pi), rng.uniform(2000, 15000), rng.uniform(-2, 2), 0.0
+    items, t0, base = [], 0.0, 0.0
+    for k in range(nblocks):
+        if k == 1:
+            # continue the phase at t0 with the frequency raised by jump_hz
+            phi0, f0, f1, f2 = synth.shift_truth(phi0, f0, f1, f2, t0)
+            f0 += jump_hz
+            base = t0
+        tt = t0 - base
+        s, scale = synth.block_from_phase(n, FS, 1.0, phi0, f0, f1, f2, 1 / math.sqrt(2), rng, True, t0=tt)
+        p, g0, g1, g2 = synth.shift_truth(phi0, f0, f1, f2, tt + n / 2 / FS)
+        a = scale
+        truth = np.array([a, p, g0, g1, g2, 0.0])
+        half = np.array([0.1 * a, math.pi, 0.5, 0.1, 0.01, 0.0])
+        b = synth.Block(s, FS, n / 2, truth, truth - half, truth + half, None, scale / math.sqrt(2),
+                        stream=k, name=f"step{k}")
+        items.append({"track": 0, "seq": k, "block": b})
+        t0 += n / FS
+    return items
+
+
+def test_frequency_step_is_refitted_in_an_enlarged_box():
+    # the warm f0 box is +-0.35 Hz around the prediction: a 0.45 Hz step puts the
+    # truth 0.1 Hz outside, inside the main lobe (first null at 1/T = 0.25 Hz),
+    # so the best member presses against the bound
+    items = _step_track(0, 0.45)
+    res = _serve(items, max_attempts=3, enlarge=2.0)
+    r1 = res[(0, 1)]
+    b1 = items[1]["block"]
+    print(f"[step] attempts {r1.attempts} flags {r1.fit.flags} f0 err {r1.fit.coef[2] - b1.truth[2]:.3e} "
+          f"box f0 +-{(r1.box.hi[2] - r1.box.lo[2]) / 2:.3f}", flush=True)
+    assert r1.attempts >= 2 and not (r1.fit.flags & ptk.PT_FLAG_ABANDONED)
+    assert abs(r1.fit.coef[2] - b1.truth[2]) < 30 * _crlb(b1)
+    assert (r1.box.hi[2] - r1.box.lo[2]) / 2 == pytest.approx(0.35 * 2 ** (r1.attempts - 1), rel=1e-9)
+    # the delivered fit is the plain fit of the same block in the same box
+    blk = _blk(b1)
+    blk.box = r1.box
+    c = ctx()
+    ptk.pt_ctx_set_tile(c.handle, 16, 4)
+    try:
+        f = c.fit_block(blk, _de())
+    finally:
+        ptk.pt_ctx_set_tile(c.handle, 0, 0)
+    assert list(f.coef) == list(r1.fit.coef) and f.generations == r1.fit.generations
+
+
+def test_discontinuity_is_abandoned_after_max_attempts():
+    items = _step_track(1, 0.45)
+    res = _serve(items, max_attempts=3, enlarge=2.0, qc_phase_rad=0.5, qc_freq_hz=0.2)
+    r1 = res[(0, 1)]
+    print(f"[step qc] attempts {r1.attempts} flags {r1.fit.flags} dfreq {r1.border_dfreq:+.3f}", flush=True)
+    assert r1.attempts == 3 and r1.qc == -1
+    assert r1.fit.flags & ptk.PT_FLAG_ABANDONED and r1.fit.flags & ptk.PT_FLAG_DISCONTINUOUS
+    assert res[(0, 2)].qc == 0  # its predecessor was abandoned: no continuity check
