@@ -94,7 +94,8 @@ def run_serving(ctx, ptk, synth, np, torch, nblocks):
     items = synth.config4_stream(seed=0, ntracks=16, nblocks=nblocks, rate=20.0)
     de = ptk.make_settings(pop=40, max_gens=3000, F=0.5, CR=0.9, seed=0x19061059 ^ 0xDE, rel_tol=1e-9, window=50)
     srv = ptk.pt_server_create(ctx.handle, ptk.make_server_config(de, max_slots=64, gens_per_step=32,
-                                                                  hbm_budget_bytes=64 << 30))
+                                                                  hbm_budget_bytes=64 << 30, max_attempts=3,
+                                                                  enlarge=2.0, qc_phase_rad=0.5, qc_freq_hz=0.1))
     stream = ptk.current_stream()
     host = [torch.from_numpy(it["block"].samples) for it in items]
     blks = [ptk.make_block(h, it["block"].fs, it["block"].lo, it["block"].hi, ref=it["block"].ref,
@@ -118,20 +119,26 @@ def run_serving(ctx, ptk, synth, np, torch, nblocks):
             res[tick[r.ticket]] = r
     elapsed = ptk.pt_server_clock(srv) - t0
     ptk.pt_server_destroy(srv)
-    lat, errs, gens, warm = [], [], [], 0
+    lat, errs, gens, warm, retried, abandoned, qc_fail = [], [], [], 0, 0, 0, 0
     for k, it in enumerate(items):
         r = res[k]
         lat.append((r.t_done - t0 - it["arrival"]) * 1e3)
         b = it["block"]
         sig = math.sqrt(6.0) * b.sigma / (math.pi * b.truth[0] * (b.n / b.fs) * math.sqrt(b.n))
-        errs.append(abs(r.fit.coef[2] - b.truth[2]) / sig)
+        if not (r.fit.flags & ptk.PT_FLAG_ABANDONED):
+            errs.append(abs(r.fit.coef[2] - b.truth[2]) / sig)
         gens.append(r.fit.generations)
-        warm += r.warm
+        warm += r.warm == 1
+        retried += r.attempts > 1
+        abandoned += bool(r.fit.flags & ptk.PT_FLAG_ABANDONED)
+        qc_fail += r.qc < 0
     return {"workload": f"{len(items)} blocks from 16 tracks, Poisson arrivals at 20 blocks/s, N in "
-                        "{1e5, 2e5, 4e5, 1e6} at 50 kHz, window stop 1e-9/50 (cap 3000), warm starts 0.7x box",
+                        "{1e5, 2e5, 4e5, 1e6} at 50 kHz, window stop 1e-9/50 (cap 3000), warm starts 0.7x box, "
+                        "up to 3 fits per block (range x2 per retry), continuity limits 0.5 rad / 0.1 Hz",
+            "retried_blocks": retried, "abandoned_blocks": abandoned, "continuity_failures": qc_fail,
             "latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99), "max": max(lat)},
             "blocks_per_s": len(items) / elapsed, "offered_blocks_per_s": 20.0,
-            "f0_err_over_crlb": {"median": pct(errs, 50), "p99": pct(errs, 99)},
+            "f0_err_over_crlb": {"median": pct(errs, 50), "p99": pct(errs, 99), "of_accepted_blocks": len(errs)},
             "generations": {"mean": float(sum(gens) / len(gens)), "max": max(gens)},
             "warm_fraction": warm / len(items)}
 

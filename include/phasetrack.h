@@ -334,14 +334,17 @@ int pt_continuity(const pt_fit* a, const pt_fit* b, double* dphi_rad, double* df
  *     end, f1 likewise its frequency rate, each widened to at least
  *     warm_narrow times the block's own half-width; A is the prediction +-10 %;
  *     phi0, f2 and Adot as PT_RUN_WARM;
- *   - a fit fails when its best member sits at a non-phase bound
- *     (PT_FLAG_AT_BOUND) or, when qc_phase_rad / qc_freq_hz are set and the
- *     track's previous block was accepted, when the border phase or frequency
- *     jump (pt_continuity) exceeds them.  A failed block is fitted again with
- *     every half-width times `enlarge` (the phase one capped at pi), up to
- *     max_attempts fits in all; after the last it is delivered with
- *     PT_FLAG_ABANDONED (and PT_FLAG_DISCONTINUOUS when continuity failed),
- *     and the track's next block is predicted from the last accepted fit.
+ *   - with max_attempts > 1 or a continuity limit set, a fit fails when its
+ *     best member sits on a bound of A, f0 or f1 (the range missed the
+ *     signal; f2 and Adot of short blocks are noise-dominated and may sit on
+ *     their bounds, which only sets PT_FLAG_AT_BOUND) or, when qc_phase_rad /
+ *     qc_freq_hz are set and the track's previous block was accepted, when
+ *     the border phase or frequency jump (pt_continuity) exceeds them.  A
+ *     failed block is fitted again with every half-width times `enlarge`
+ *     (the phase one capped at pi), up to max_attempts fits in all; after the
+ *     last it is delivered with PT_FLAG_ABANDONED (and PT_FLAG_DISCONTINUOUS
+ *     when continuity failed), and the track's next block is predicted from
+ *     the last accepted fit.  Otherwise every fit is accepted as it is.
  * A block's arithmetic (mixed, FP64 phasor or FP64 per-sample) follows from
  * its own box, and every block uses the same DE settings and geometry, so a
  * block's result does not depend on which other blocks share its steps. */
@@ -441,6 +444,13 @@ int pt_ctx_last_launch(pt_ctx* ctx, int* mode);
 enum { PT_FP64_AUTO = 0, PT_FP64_POLY = 1 };
 
 int pt_ctx_set_fp64_method(pt_ctx* ctx, int method);
+
+/* ---- step fusion ----
+ * 1 (default): for P <= 256 each generation is one launch -- the DE step of
+ *   a block runs in the objective workgroup that finishes the block's last
+ *   work unit (arrival counters, no waiting).  0: objective and DE step as
+ *   two launches.  Both give bit-identical fits. */
+int pt_ctx_set_step_fusion(pt_ctx* ctx, int on);
 
 /* Objective arithmetic of the context's most recent fit or objective
  * evaluation: per-sample FP64 cosine, mixed precision, or FP64 phasor. */

@@ -421,30 +421,6 @@ __device__ __forceinline__ void objective_unit(const BlockDesc* __restrict__ d, 
     }
 }
 
-// Objective kernel: one work unit per workgroup.  Units are remapped so
-// that the candidate groups of a tile run on one XCD.
-template <typename T, int S, int CPG, int MODE, bool SLOPE>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_objective(
-    const BlockDesc* __restrict__ descs, int nblk, int total_units) {
-    const int nwg = gridDim.x;  // multiple of 8
-    const int bid = blockIdx.x;
-    const int unit = (bid & 7) * (nwg >> 3) + (bid >> 3);
-    if (unit >= total_units) return;
-    const BlockDesc* __restrict__ d = descs + find_block(descs, nblk, unit);
-    if (d->st != nullptr && d->st->done) return;
-    const int local = unit - d->unit_begin;
-    const int tile = local / d->ngroups;
-    const int group = local - tile * d->ngroups;
-
-    __shared__ Cand cs[CPG];
-    __shared__ double red[CPG][kThreads];
-    using V = typename std::conditional<MODE == 1, float, double>::type;
-    V sv[S];
-    bool full;
-    int valid;
-    load_lane<V, T, S>(d, tile, sv, full, valid);
-    objective_unit<S, CPG, MODE, SLOPE>(d, tile, group, sv, full, valid, cs, red);
-}
 
 // ---------------------------------------------------------------------------
 // Objective of every candidate from its tile partials, by the whole
@@ -761,6 +737,78 @@ __device__ __forceinline__ int units_in_range(const BlockDesc* d, int x, int Ux,
     const int rb = x * Ux, re = min(total_units, rb + Ux);
     return max(0, min(ue, re) - max(ub, rb));
 }
+
+// Objective kernel: one work unit per workgroup.  Units are remapped so
+// that the candidate groups of a tile run on one XCD (workgroup ids are dealt
+// round-robin to the 8 XCDs, so XCD x runs units [x Ux, (x + 1) Ux), Ux =
+// gridDim / 8).
+//
+// fused != 0 (fits with P <= 256): the DE step of each block runs in the
+// same launch, in the workgroup that finishes the block's last unit.  Every
+// workgroup counts its finished unit on the block's counter for its XCD
+// range; the one completing a range counts the range on the block's range
+// counter; the one completing that runs de_step_body (the same code, thread
+// count and reduction order as k_de_step, so fits are bit-identical to the
+// two-launch form) and clears the counters for the next launch.  No
+// workgroup waits for another.  Partial sums are coherent stores and loads
+// (xst / xld), so the fences only order each wave's accesses around its
+// counter update.  Dynamic LDS: the DE step's (P * kSlots + 2 * 256 doubles
+// + 256 ints).
+template <typename T, int S, int CPG, int MODE, bool SLOPE>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_objective(
+    const BlockDesc* __restrict__ descs, int nblk, int total_units, int fused) {
+    const int nwg = gridDim.x;  // multiple of 8
+    const int bid = blockIdx.x;
+    const int Ux = nwg >> 3;
+    const int unit = (bid & 7) * Ux + (bid >> 3);
+    if (unit >= total_units) return;
+    const BlockDesc* __restrict__ d = descs + find_block(descs, nblk, unit);
+    if (d->st != nullptr && d->st->done) return;
+    const int local = unit - d->unit_begin;
+    const int tile = local / d->ngroups;
+    const int group = local - tile * d->ngroups;
+
+    __shared__ Cand cs[CPG];
+    __shared__ double red[CPG][kThreads];
+    __shared__ int s_last;
+    using V = typename std::conditional<MODE == 1, float, double>::type;
+    V sv[S];
+    bool full;
+    int valid;
+    load_lane<V, T, S>(d, tile, sv, full, valid);
+    objective_unit<S, CPG, MODE, SLOPE>(d, tile, group, sv, full, valid, cs, red);
+    if (!fused) return;
+
+    int* sync = d->sync;
+    const int xcd = bid & 7;
+    __syncthreads();  // every wave's partial stores are issued
+    if (threadIdx.x == 0) {
+        const int nx = units_in_range(d, xcd, Ux, total_units);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, PT_REL_SCOPE);
+        const int old = __hip_atomic_fetch_add(sync + xcd * kSyncLine, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        bool last = false;
+        if (old == nx - 1) {
+            int nranges = 0;
+            for (int x = 0; x < 8; ++x) nranges += units_in_range(d, x, Ux, total_units) > 0;
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, PT_ACQ_SCOPE);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, PT_REL_SCOPE);
+            const int old2 =
+                __hip_atomic_fetch_add(sync + 16 * kSyncLine, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            last = old2 == nranges - 1;
+            if (last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, PT_ACQ_SCOPE);
+        }
+        s_last = last;
+    }
+    __syncthreads();
+    if (!s_last) return;
+    extern __shared__ double de_lds[];
+    de_step_body(d, de_lds);
+    __syncthreads();
+    if (threadIdx.x < 8) __hip_atomic_store(sync + threadIdx.x * kSyncLine, 0, __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x == 8) __hip_atomic_store(sync + 16 * kSyncLine, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 
 template <typename T, int S, int CPG, int MODE, bool SLOPE>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_fit_persistent(

@@ -114,7 +114,7 @@ int size_class(int64_t n) {
 }
 
 // ----------------------------------------------------------------- launchers
-using ObjKernel = void (*)(const BlockDesc*, int, int);
+using ObjKernel = void (*)(const BlockDesc*, int, int, int);
 
 // Kernel arithmetic modes (template argument MODE of the kernels).
 enum { kModePoly = PT_ARITH_FP64_POLY, kModeMixed = PT_ARITH_MIXED, kModePhasor = PT_ARITH_FP64_PHASOR };
@@ -226,6 +226,7 @@ struct Plan {
     size_t de_lds = 0;
     int max_gens = 0;
     bool window = false;
+    bool fused = false;    // DE step inside the objective launch (k_objective, fused != 0)
 };
 
 }  // namespace
@@ -251,6 +252,7 @@ struct pt_ctx {
     int fp64_method = PT_FP64_AUTO;
     int last_launch = PT_LAUNCH_GRAPH;
     int last_arith = PT_ARITH_FP64_POLY;
+    int step_fusion = 1;
     uint64_t spin_ticks = 0;
     DevBuf errflag;
     // initial-range estimation
@@ -266,11 +268,11 @@ struct pt_ctx {
         int nblk, grid, total_units, spl, cpg, dtype, mixed, slope;
         unsigned de_threads;
         size_t de_lds;
-        int iters;
+        int iters, fused;
         bool operator<(const GraphKey& o) const {
-            return std::tie(desc, nblk, grid, total_units, spl, cpg, dtype, mixed, slope, de_threads, de_lds,
-                            iters) < std::tie(o.desc, o.nblk, o.grid, o.total_units, o.spl, o.cpg, o.dtype,
-                                              o.mixed, o.slope, o.de_threads, o.de_lds, o.iters);
+            return std::tie(desc, nblk, grid, total_units, spl, cpg, dtype, mixed, slope, de_threads, de_lds, iters,
+                            fused) < std::tie(o.desc, o.nblk, o.grid, o.total_units, o.spl, o.cpg, o.dtype,
+                                              o.mixed, o.slope, o.de_threads, o.de_lds, o.iters, o.fused);
         }
     };
     std::map<GraphKey, hipGraphExec_t> graphs;
@@ -384,7 +386,13 @@ int enqueue_generation(pt_ctx* ctx, const Plan& pl, ObjKernel obj, hipStream_t s
         if (!e0 || !e1) return fail(PT_EDEVICE, "hipEventCreate failed");
         HIPCHK(hipEventRecord(e0, s));
     }
-    hipLaunchKernelGGL(obj, dim3(pl.grid), dim3(kThreads), 0, s, d, pl.nblk, pl.total_units);
+    if (pl.fused && !timed) {
+        // the DE step runs in each block's last objective workgroup
+        hipLaunchKernelGGL(obj, dim3(pl.grid), dim3(kThreads), pl.de_lds, s, d, pl.nblk, pl.total_units, 1);
+        HIPCHK(hipGetLastError());
+        return PT_OK;
+    }
+    hipLaunchKernelGGL(obj, dim3(pl.grid), dim3(kThreads), 0, s, d, pl.nblk, pl.total_units, 0);
     HIPCHK(hipGetLastError());
     if (timed) {
         HIPCHK(hipEventRecord(e1, s));
@@ -397,7 +405,7 @@ int enqueue_generation(pt_ctx* ctx, const Plan& pl, ObjKernel obj, hipStream_t s
 
 int get_graph(pt_ctx* ctx, const Plan& pl, ObjKernel obj, int iters, hipGraphExec_t* out) {
     pt_ctx::GraphKey key{ctx->desc.p, pl.nblk, pl.grid, pl.total_units, pl.geo.spl, pl.geo.cpg, pl.dtype,
-                         pl.mode, (int)pl.slope, pl.de_threads, pl.de_lds, iters};
+                         pl.mode, (int)pl.slope, pl.de_threads, pl.de_lds, iters, (int)pl.fused};
     auto it = ctx->graphs.find(key);
     if (it != ctx->graphs.end()) {
         *out = it->second;
@@ -474,6 +482,7 @@ int prepare(pt_ctx* ctx, const pt_block* blocks, int nblk, const pt_de_settings*
     pl->grid = (int)((units + 7) / 8 * 8);
     pl->de_threads = pow2_at_least(P);  // >= 256 and >= P: also fixes the partial-sum order
     pl->de_lds = (size_t)P * kSlots * 8 + (size_t)pl->de_threads * (8 + 8 + 4);
+    pl->fused = with_state && ctx->step_fusion && pl->de_threads == (unsigned)kThreads;
 
     const size_t rows = (size_t)nblk * P * kStride * sizeof(double);
     int rc;
@@ -785,8 +794,8 @@ static int eval_setup(pt_ctx* ctx, const pt_block* block, const double* pop, int
     const BlockDesc* hd = static_cast<const BlockDesc*>(ctx->hdesc.p);
     HIPCHK(hipMemcpy2DAsync(hd[0].trial, kStride * sizeof(double), pop, PT_NSLOT * sizeof(double),
                             PT_NSLOT * sizeof(double), P, hipMemcpyDeviceToDevice, s));
-    if (pl->mode == kModePhasor) {
-        // an arbitrary population may leave the box: decide on its own f1, f2
+    if (!pl->mixed && ctx->fp64_method != PT_FP64_POLY) {
+        // the arithmetic follows the population itself (which may leave the box)
         std::vector<double> hp((size_t)P * PT_NSLOT);
         HIPCHK(hipMemcpyAsync(hp.data(), pop, hp.size() * sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
@@ -796,8 +805,9 @@ static int eval_setup(pt_ctx* ctx, const pt_block* block, const double* pop, int
             f2 = std::max(f2, std::fabs(hp[(size_t)p * PT_NSLOT + 4]));
         }
         const double span = (double)block->n + std::fabs(block_ref(block));
-        if (!(std::isfinite(f1) && std::isfinite(f2) && phasor_ok(pl->geo.spl, block->fs, span, f1, f2)))
-            pl->mode = kModePoly;
+        pl->mode = std::isfinite(f1) && std::isfinite(f2) && phasor_ok(pl->geo.spl, block->fs, span, f1, f2)
+                       ? kModePhasor
+                       : kModePoly;
     }
     *obj = objective_kernel(pl->dtype, pl->geo, pl->mode, pl->slope);
     ctx->last_arith = pl->mode;
@@ -814,7 +824,7 @@ int pt_objective(pt_ctx* ctx, const pt_block* block, const double* pop, int P, i
     int rc = eval_setup(ctx, block, pop, P, precision, objective, s, &pl, &obj);
     if (rc) return rc;
     const BlockDesc* d = static_cast<const BlockDesc*>(ctx->desc.p);
-    hipLaunchKernelGGL(obj, dim3(pl.grid), dim3(kThreads), 0, s, d, 1, pl.total_units);
+    hipLaunchKernelGGL(obj, dim3(pl.grid), dim3(kThreads), 0, s, d, 1, pl.total_units, 0);
     HIPCHK(hipGetLastError());
     hipLaunchKernelGGL(k_reduce_out, dim3(1), dim3(pl.de_threads), pl.de_threads * sizeof(double), s, d, out);
     HIPCHK(hipGetLastError());
@@ -833,12 +843,12 @@ int pt_time_objective(pt_ctx* ctx, const pt_block* block, const double* pop, int
     int rc = eval_setup(ctx, block, pop, P, precision, PT_OBJ_CHI2, s, &pl, &obj);
     if (rc) return rc;
     const BlockDesc* d = static_cast<const BlockDesc*>(ctx->desc.p);
-    hipLaunchKernelGGL(obj, dim3(pl.grid), dim3(kThreads), 0, s, d, 1, pl.total_units);  // warm
+    hipLaunchKernelGGL(obj, dim3(pl.grid), dim3(kThreads), 0, s, d, 1, pl.total_units, 0);  // warm
     HIPCHK(hipGetLastError());
     hipEvent_t e0 = take_event(ctx), e1 = take_event(ctx);
     if (!e0 || !e1) return fail(PT_EDEVICE, "hipEventCreate failed");
     HIPCHK(hipEventRecord(e0, s));
-    for (int r = 0; r < reps; ++r) hipLaunchKernelGGL(obj, dim3(pl.grid), dim3(kThreads), 0, s, d, 1, pl.total_units);
+    for (int r = 0; r < reps; ++r) hipLaunchKernelGGL(obj, dim3(pl.grid), dim3(kThreads), 0, s, d, 1, pl.total_units, 0);
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(e1, s));
     HIPCHK(hipEventSynchronize(e1));
@@ -1102,6 +1112,13 @@ int pt_ctx_last_launch(pt_ctx* ctx, int* mode) {
     return PT_OK;
 }
 
+int pt_ctx_set_step_fusion(pt_ctx* ctx, int on) {
+    if (!ctx) return fail(PT_EINVAL, "ctx is null");
+    if (on != 0 && on != 1) return fail(PT_EINVAL, "step fusion %d", on);
+    ctx->step_fusion = on;
+    return PT_OK;
+}
+
 int pt_ctx_last_arithmetic(pt_ctx* ctx, int* arith) {
     if (!ctx || !arith) return fail(PT_EINVAL, "ctx / arith is null");
     *arith = ctx->last_arith;
@@ -1159,10 +1176,12 @@ int pt_ctx_autotune(pt_ctx* ctx, int64_t n, int P, int precision, void* hip_stre
         const size_t cnt = (size_t)std::min<int64_t>((int64_t)hs.size(), n - off);
         HIPCHK(hipMemcpy(static_cast<float*>(ctx->scratch.p) + off, hs.data(), cnt * 4, hipMemcpyHostToDevice));
     }
+    // a population near one carrier, as in a fit (the FP64 path then uses the
+    // arithmetic it uses in a fit of a paper-scale box)
     std::vector<double> hp((size_t)P * PT_NSLOT);
     for (int p = 0; p < P; ++p) {
         double* x = &hp[(size_t)p * PT_NSLOT];
-        x[0] = 1.0; x[1] = 0.1 * p; x[2] = 1000.0 + p; x[3] = 0.5; x[4] = 0.01; x[5] = 0.0;
+        x[0] = 1.0; x[1] = 0.1 * p; x[2] = 1000.0 + 1e-3 * p; x[3] = 0.5; x[4] = 0.01; x[5] = 0.0;
     }
     HIPCHK(hipMemcpy(ctx->eval_pop.p, hp.data(), hp.size() * 8, hipMemcpyHostToDevice));
     pt_block b;
@@ -1178,12 +1197,25 @@ int pt_ctx_autotune(pt_ctx* ctx, int64_t n, int P, int precision, void* hip_stre
     const Geometry saved = ctx->forced;
     Geometry best{0, 0};
     double best_ms = 1e30;
+    // two passes of 100 back-to-back launches per geometry; the faster pass counts
+    std::map<std::pair<int, int>, double> t;
+    for (int pass = 0; pass < 2 && !rc; ++pass)
+        for (int spl : kSpl) {
+            for (int cpg : kCpg) {
+                ctx->forced = {spl, cpg};
+                double ms = 0.0;
+                rc = pt_time_objective(ctx, &b, static_cast<const double*>(ctx->eval_pop.p), P, precision, 100, s,
+                                       &ms);
+                if (rc) break;
+                auto key = std::make_pair(spl, cpg);
+                t[key] = pass ? std::min(t[key], ms) : ms;
+            }
+            if (rc) break;
+        }
     for (int spl : kSpl) {
         for (int cpg : kCpg) {
-            ctx->forced = {spl, cpg};
-            double ms = 0.0;
-            rc = pt_time_objective(ctx, &b, static_cast<const double*>(ctx->eval_pop.p), P, precision, 20, s, &ms);
             if (rc) break;
+            const double ms = t[std::make_pair(spl, cpg)];
             if (ms < best_ms) {
                 best_ms = ms;
                 best = {spl, cpg};
@@ -1613,7 +1645,7 @@ int pt_server_step(pt_server* sv, void* hip_stream, int32_t* n_active, int32_t* 
     for (int k = 0; k < sv->cfg.gens_per_step; ++k) {
         for (const Launch& L : launches) {
             const int grid = (L.units + 7) / 8 * 8;
-            hipLaunchKernelGGL(L.k, dim3(grid), dim3(kThreads), 0, s, dd + L.first, L.count, L.units);
+            hipLaunchKernelGGL(L.k, dim3(grid), dim3(kThreads), 0, s, dd + L.first, L.count, L.units, 0);
         }
         hipLaunchKernelGGL(k_de_step, dim3(nb), dim3(de_threads), de_lds, s, dd);
     }
@@ -1656,7 +1688,16 @@ int pt_server_step(pt_server* sv, void* hip_stream, int32_t* n_active, int32_t* 
                              (cf.qc_freq_hz > 0 && !(std::fabs(dfreq) <= cf.qc_freq_hz));
             qc = bad ? -1 : 1;
         }
-        const bool failed = (f.flags & PT_FLAG_AT_BOUND) || qc < 0;
+        // a missed range: the best member on a bound of A, f0 or f1 (f2 and Adot
+        // of short blocks are noise-dominated and may sit on their bounds)
+        bool miss = false;
+        for (int j : {0, 2, 3}) {
+            const double w = sl.blk.box.hi[j] - sl.blk.box.lo[j];
+            if (w > 0 && (f.coef[j] - sl.blk.box.lo[j] <= 1e-6 * w || sl.blk.box.hi[j] - f.coef[j] <= 1e-6 * w))
+                miss = true;
+        }
+        const bool policy = cf.max_attempts > 1 || qc_on;  // otherwise every fit is accepted as it is
+        const bool failed = policy && (miss || qc < 0);
         if (failed && sl.attempts < cf.max_attempts) {
             // Sec. 3.1.1: enlarge the range and search again
             enlarge_box(sl.blk.box, cf.enlarge);

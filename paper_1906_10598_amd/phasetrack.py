@@ -198,6 +198,7 @@ def _signatures(L):
         "pt_ctx_set_fp64_method": ([_CTX, i32], i32),
         "pt_ctx_last_launch": ([_CTX, ctypes.POINTER(i32)], i32),
         "pt_ctx_last_arithmetic": ([_CTX, ctypes.POINTER(i32)], i32),
+        "pt_ctx_set_step_fusion": ([_CTX, i32], i32),
         "pt_ctx_set_timing": ([_CTX, i32], i32),
         "pt_ctx_kernel_stats": ([_CTX, ctypes.POINTER(i64), _DP], i32),
         "pt_ctx_get_tile": ([_CTX, i64, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)], i32),
@@ -419,6 +420,10 @@ def pt_ctx_last_launch(ctx) -> int:
     m = ctypes.c_int()
     _check(lib().pt_ctx_last_launch(ctx, ctypes.byref(m)), "pt_ctx_last_launch")
     return m.value
+
+
+def pt_ctx_set_step_fusion(ctx, on: bool):
+    _check(lib().pt_ctx_set_step_fusion(ctx, int(on)), "pt_ctx_set_step_fusion")
 
 
 def pt_ctx_last_arithmetic(ctx) -> int:

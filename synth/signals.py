@@ -17,7 +17,8 @@ Recipe (also stated in the design notes):
     1500 generations.
   * serving stream: 16 tracks with a continuous cubic phase over the whole
     track, contiguous blocks with N drawn from {1e5, 2e5, 4e5, 1e6}, Poisson
-    arrivals at an aggregate 20 blocks/s.
+    arrivals at an aggregate 20 blocks/s; int16 with a fixed full scale of
+    A + 6 sigma per track (a receiver of fixed gain).
 
 The truths are drawn at the block start (t = n / fs) and reported at the
 block's reference sample (the block centre N / 2, Sec. 2.2) by an exact
@@ -89,8 +90,12 @@ def shift_truth(phi0, f0, f1, f2, dt):
     return phi, f0n, f1n, float(F2)
 
 
-def block_from_phase(n, fs, amp, phi0, f0, f1, f2, sigma, rng, quantise, t0=0.0):
-    """Samples amp * cos(phase(t0 + k/fs)) + noise for k < n (phase at absolute time)."""
+def block_from_phase(n, fs, amp, phi0, f0, f1, f2, sigma, rng, quantise, t0=0.0, full_scale=None):
+    """Samples amp * cos(phase(t0 + k/fs)) + noise for k < n (phase at absolute time).
+
+    quantise: int16 codes q / 32767 as FP32, with the block's own peak as full
+    scale, or a fixed ``full_scale`` (a receiver with fixed gain; values beyond
+    it clip)."""
     k = np.arange(n, dtype=np.float64)
     t = t0 + k / fs
     # phase in turns with exact-integer removal of f0*t0 style large parts
@@ -101,8 +106,8 @@ def block_from_phase(n, fs, amp, phi0, f0, f1, f2, sigma, rng, quantise, t0=0.0)
         s = s + rng.normal(0.0, sigma, size=n)
     scale = 1.0
     if quantise:
-        peak = float(np.max(np.abs(s)))
-        q = np.rint(32767.0 * s / peak)
+        peak = float(np.max(np.abs(s))) if full_scale is None else float(full_scale)
+        q = np.rint(32767.0 * np.clip(s / peak, -1.0, 1.0))
         s = (q / 32767.0).astype(np.float32)
         scale = 1.0 / peak
     return s, scale
@@ -194,7 +199,7 @@ def config4_stream(seed: int = 0, ntracks: int = 16, nblocks: int = 160,
         sigma = A / math.sqrt(2.0)
         t0 = tr["t"]
         s, scale = block_from_phase(n, fs, A, tr["phi0"], tr["f0"], tr["f1"], tr["f2"], sigma,
-                                    tr["rng"], quantise=True, t0=t0)
+                                    tr["rng"], quantise=True, t0=t0, full_scale=A + 6.0 * sigma)
         ref = n / 2.0
         p, g0, g1, g2 = shift_truth(tr["phi0"], tr["f0"], tr["f1"], tr["f2"], t0 + ref / fs)
         a = A * scale

@@ -81,7 +81,7 @@ def test_seeded_tracks_pass_continuity():
     for it in items:
         r = res[(it["track"], it["seq"])]
         b = it["block"]
-        assert r.attempts == 1 and not (r.fit.flags & (ptk.PT_FLAG_ABANDONED | ptk.PT_FLAG_AT_BOUND)), it["seq"]
+        assert r.attempts == 1 and not (r.fit.flags & ptk.PT_FLAG_ABANDONED), it["seq"]
         truth = _oriented(b.truth, r.fit.coef[2])
         err = (r.fit.coef[2] - truth[2]) / _crlb(b)
         print(f"[tracker] track {it['track']} seq {it['seq']} warm {r.warm} qc {r.qc} "
