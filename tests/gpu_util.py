@@ -48,18 +48,32 @@ def phase_rounding_bound(s, pop, fs, ref):
     return 8 * phi_max * 2.0 ** -53, np.abs(pop[:, 0])
 
 
-def assert_chi2_close(got, ref, n, amp=1.0, rel=1e-10, eps_phi=None):
-    """Objectives agree within `rel` relative.  For noise-free data, where
-    chi^2 -> 0 and a relative error is undefined, pass eps_phi (per-candidate
-    phase rounding, see phase_rounding_bound): the bound becomes
-    2 sqrt(n chi^2) A eps_phi + n (1e-13 A)^2."""
+# Per-sample phase error [rad] of the FP64 arithmetics beyond the phase
+# rounding: the per-sample cosine path ~1e-16 turns; the phasor path drops the
+# cubic term inside a lane's chunk only where that term stays below 1e-12
+# turns, plus its recurrence rounding.
+MODEL_PHASE_ERR = {ptk.PT_ARITH_FP64_POLY: 1e-13, ptk.PT_ARITH_FP64_PHASOR: 2 * math.pi * 1e-12 + 1e-13}
+
+
+def model_phase_err(c=None):
+    """MODEL_PHASE_ERR of the arithmetic the context's last evaluation used."""
+    return MODEL_PHASE_ERR.get(ptk.pt_ctx_last_arithmetic((c or ctx()).handle), 1e-13)
+
+
+def assert_chi2_close(got, ref, n, amp=1.0, rel=1e-10, eps_phi=None, floor=1e-13):
+    """Objectives agree within `rel` relative, with an absolute floor
+    n (floor A)^2 (floor: per-sample phase error of the arithmetic, see
+    MODEL_PHASE_ERR).  For noise-free data, where chi^2 -> 0 and a relative
+    error is undefined, pass eps_phi (per-candidate phase rounding, see
+    phase_rounding_bound): the bound becomes
+    2 sqrt(n chi^2) A (eps_phi + floor) + n (floor A)^2."""
     got = np.asarray(got, dtype=np.float64)
     ref = np.asarray(ref, dtype=np.float64)
     amp = np.broadcast_to(np.asarray(amp, dtype=np.float64), ref.shape)
     err = np.abs(got - ref)
-    tol = np.maximum(rel * np.abs(ref), n * (1e-13 * amp) ** 2)
+    tol = np.maximum(rel * np.abs(ref), n * (floor * amp) ** 2)
     if eps_phi is not None:
-        tol = np.maximum(tol, 2 * np.sqrt(n * np.abs(ref)) * amp * eps_phi + n * (1e-13 * amp) ** 2)
+        tol = np.maximum(tol, 2 * np.sqrt(n * np.abs(ref)) * amp * (eps_phi + floor) + n * (floor * amp) ** 2)
     bad = np.nonzero(err > tol)[0]
     assert bad.size == 0, (
         f"{bad.size} objectives outside tolerance; worst rel err "
