@@ -218,6 +218,9 @@ def main():
                     help="profiling mode: one fit, then --reps back-to-back objective launches; "
                          "also one 256 MiB device copy as the traffic-counter calibration")
     ap.add_argument("--reps", type=int, default=200)
+    ap.add_argument("--fit-only", action="store_true",
+                    help="profiling mode: --warmup + --steps fits of the paper-scale block (FP64, default "
+                         "launch form), then one JSON line with the fit times")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-block batched fits")
     ap.add_argument("--no-serve", action="store_true", help="skip the real-time serving run")
     ap.add_argument("--serve-blocks", type=int, default=160)
@@ -255,8 +258,12 @@ def main():
 
     if args.kernel_only:
         prec = ptk.PT_PREC_FP64 if args.kernel_only == "fp64" else ptk.PT_PREC_MIXED
+        # two-launch generations here, so every k_objective launch of this run is
+        # the bare objective the roofline times
+        ptk.pt_ctx_set_step_fusion(ctx.handle, False)
         ctx.fit_block(blk, ptk.make_settings(pop=P, max_gens=G, F=b.de.F, CR=b.de.CR, seed=b.de.seed,
                                              precision=prec))
+        ptk.pt_ctx_set_step_fusion(ctx.handle, True)
         pop, _ = ptk.pt_last_population(ctx.handle, 0, P)
         popd = torch.from_numpy(pop).cuda()
         avg_ms = ptk.pt_time_objective(ctx.handle, blk, popd.data_ptr(), P, prec, args.reps, stream)
@@ -273,6 +280,16 @@ def main():
     def de(prec):
         return lambda k: ptk.make_settings(pop=P, max_gens=G, F=b.de.F, CR=b.de.CR, seed=b.de.seed + k,
                                            precision=prec)
+
+    if args.fit_only:
+        run_fits(ctx, blk, de(ptk.PT_PREC_FP64), args.warmup, "warmup")
+        el, lat, _ = run_fits(ctx, blk, de(ptk.PT_PREC_FP64), args.steps, "fp64")
+        print(json.dumps({"fit_only": True, "fits": args.steps, "ms_per_fit": el / args.steps * 1e3,
+                          "p50_ms": pct(lat, 50), "geometry": tiles["fp64"],
+                          "arithmetic": ARITH_NAME[ptk.pt_ctx_last_arithmetic(ctx.handle)],
+                          "kernel_hash": kernel_hash()}), flush=True)
+        ctx.close()
+        return
 
     # ---- plain FP64: warmup + timed steps
     run_fits(ctx, blk, de(ptk.PT_PREC_FP64), args.warmup, "warmup")

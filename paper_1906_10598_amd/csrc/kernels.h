@@ -232,49 +232,61 @@ __device__ __forceinline__ void sincos_turns64(double r, double& c, double& sn) 
     sn = r * ps;
 }
 
-template <int S, bool TAIL, bool SLOPE, bool COR = false>
-__device__ __forceinline__ double lane_chi2_f64_rot(const double (&sv)[S], const Anchor& an, double amp0,
-                                                    double ad, int valid) {
+// NC candidates at once (NC = 1 or 2): their recurrences are independent, so
+// interleaving two of them gives the FMA pipeline two dependency chains per
+// wave.  Each candidate's arithmetic is the same as alone, so results do not
+// depend on the pairing.
+template <int S, bool TAIL, bool SLOPE, bool COR, int NC>
+__device__ __forceinline__ void lane_rot(const double (&sv)[S], const Anchor* an, const double* amp0,
+                                         const double* ad, int valid, double* out) {
     static_assert(kSinDeg64 == kCosDeg64, "sine and cosine tables have one degree");
-    double zr, zi, wr, wi;
-    sincos_turns64(an.b0, zr, zi);  // b0 is already reduced to [-1/2, 1/2]
-    double d = an.b1 + an.b2;
-    d -= rint(d);
-    sincos_turns64(d, wr, wi);
-    const double x = 12.566370614359172954 * an.b2;  // 2 pi (2 b2) radians
-    const double x2 = x * x;
-    const double vr = __fma_rn(x2, __fma_rn(x2, __fma_rn(x2, -1.0 / 720.0, 1.0 / 24.0), -0.5), 1.0);
-    const double vi = x * __fma_rn(x2, __fma_rn(x2, __fma_rn(x2, -1.0 / 5040.0, 1.0 / 120.0), -1.0 / 6.0), 1.0);
-    double acc0 = 0.0, acc1 = 0.0;
+    double zr[NC], zi[NC], wr[NC], wi[NC], vr[NC], vi[NC], acc0[NC], acc1[NC];
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+        sincos_turns64(an[q].b0, zr[q], zi[q]);  // b0 is already reduced to [-1/2, 1/2]
+        double d = an[q].b1 + an[q].b2;
+        d -= rint(d);
+        sincos_turns64(d, wr[q], wi[q]);
+        const double x = 12.566370614359172954 * an[q].b2;  // 2 pi (2 b2) radians
+        const double x2 = x * x;
+        vr[q] = __fma_rn(x2, __fma_rn(x2, __fma_rn(x2, -1.0 / 720.0, 1.0 / 24.0), -0.5), 1.0);
+        vi[q] = x * __fma_rn(x2, __fma_rn(x2, __fma_rn(x2, -1.0 / 5040.0, 1.0 / 120.0), -1.0 / 6.0), 1.0);
+        acc0[q] = 0.0;
+        acc1[q] = 0.0;
+    }
 #pragma unroll
     for (int j = 0; j < S; ++j) {
-        double& acc = (j & 1) ? acc1 : acc0;
-        if constexpr (COR) {
-            const double m = SLOPE ? __fma_rn(ad, (double)j, amp0) * zr : zr;
-            acc = __fma_rn(sv[j], m, acc);
-        } else {
-            const double amp = SLOPE ? __fma_rn(ad, (double)j, amp0) : amp0;
-            const double rho = __fma_rn(-amp, zr, sv[j]);
-            if (TAIL) {
-                if (j < valid) acc = __fma_rn(rho, rho, acc);
+#pragma unroll
+        for (int q = 0; q < NC; ++q) {
+            double& acc = (j & 1) ? acc1[q] : acc0[q];
+            if constexpr (COR) {
+                const double m = SLOPE ? __fma_rn(ad[q], (double)j, amp0[q]) * zr[q] : zr[q];
+                acc = __fma_rn(sv[j], m, acc);
             } else {
-                acc = (j < 2) ? rho * rho : __fma_rn(rho, rho, acc);
+                const double amp = SLOPE ? __fma_rn(ad[q], (double)j, amp0[q]) : amp0[q];
+                const double rho = __fma_rn(-amp, zr[q], sv[j]);
+                if (TAIL) {
+                    if (j < valid) acc = __fma_rn(rho, rho, acc);
+                } else {
+                    acc = (j < 2) ? rho * rho : __fma_rn(rho, rho, acc);
+                }
             }
-        }
-        if (j + 1 < S) {
-            const double nzr = __fma_rn(zr, wr, -(zi * wi));
-            const double nzi = __fma_rn(zr, wi, zi * wr);
-            zr = nzr;
-            zi = nzi;
-            if (j + 2 < S) {
-                const double nwr = __fma_rn(wr, vr, -(wi * vi));
-                const double nwi = __fma_rn(wr, vi, wi * vr);
-                wr = nwr;
-                wi = nwi;
+            if (j + 1 < S) {
+                const double nzr = __fma_rn(zr[q], wr[q], -(zi[q] * wi[q]));
+                const double nzi = __fma_rn(zr[q], wi[q], zi[q] * wr[q]);
+                zr[q] = nzr;
+                zi[q] = nzi;
+                if (j + 2 < S) {
+                    const double nwr = __fma_rn(wr[q], vr[q], -(wi[q] * vi[q]));
+                    const double nwi = __fma_rn(wr[q], vi[q], wi[q] * vr[q]);
+                    wr[q] = nwr;
+                    wi[q] = nwi;
+                }
             }
         }
     }
-    return (COR && !SLOPE) ? amp0 * (acc0 + acc1) : acc0 + acc1;
+#pragma unroll
+    for (int q = 0; q < NC; ++q) out[q] = (COR && !SLOPE) ? amp0[q] * (acc0[q] + acc1[q]) : acc0[q] + acc1[q];
 }
 
 // ---------------------------------------------------------------------------
@@ -386,7 +398,26 @@ __device__ __forceinline__ void objective_unit(const BlockDesc* __restrict__ d, 
     const double m0 = (double)((int64_t)tile * (kThreads * S) + (int64_t)tid * S) - d->ref;
     __syncthreads();
 
-    for (int c = 0; c < ncand; ++c) {
+    int c0 = 0;
+    if constexpr (MODE == 2) {
+        // phasor path: candidates in pairs (two independent recurrences per lane)
+        for (; c0 + 1 < ncand; c0 += 2) {
+            const Cand ca = cs[c0], cb = cs[c0 + 1];
+            const Anchor an[2] = {make_anchor(ca, m0), make_anchor(cb, m0)};
+            const double amp0[2] = {SLOPE ? __fma_rn(ca.Ad, m0, ca.A) : ca.A, SLOPE ? __fma_rn(cb.Ad, m0, cb.A) : cb.A};
+            const double ad[2] = {ca.Ad, cb.Ad};
+            double acc[2];
+            if (cor)
+                lane_rot<S, false, SLOPE, true, 2>(sv, an, amp0, ad, valid, acc);
+            else if (full)
+                lane_rot<S, false, SLOPE, false, 2>(sv, an, amp0, ad, valid, acc);
+            else
+                lane_rot<S, true, SLOPE, false, 2>(sv, an, amp0, ad, valid, acc);
+            red[c0][tid] = acc[0];
+            red[c0 + 1][tid] = acc[1];
+        }
+    }
+    for (int c = c0; c < ncand; ++c) {
         const Cand cc = cs[c];
         const Anchor an = make_anchor(cc, m0);
         const double amp0 = SLOPE ? __fma_rn(cc.Ad, m0, cc.A) : cc.A;
@@ -396,15 +427,17 @@ __device__ __forceinline__ void objective_unit(const BlockDesc* __restrict__ d, 
             if constexpr (MODE == 1)
                 acc = (double)lane_chi2_mixed<S, false, SLOPE, true>(sv, an, amp0, cc.Ad, valid);
             else if constexpr (MODE == 2)
-                acc = lane_chi2_f64_rot<S, false, SLOPE, true>(sv, an, amp0, cc.Ad, valid);
+                lane_rot<S, false, SLOPE, true, 1>(sv, &an, &amp0, &cc.Ad, valid, &acc);
             else
                 acc = lane_chi2_f64<S, false, SLOPE, true>(sv, an, amp0, cc.Ad, valid);
         } else if constexpr (MODE == 1) {
             acc = full ? (double)lane_chi2_mixed<S, false, SLOPE>(sv, an, amp0, cc.Ad, valid)
                        : (double)lane_chi2_mixed<S, true, SLOPE>(sv, an, amp0, cc.Ad, valid);
         } else if constexpr (MODE == 2) {
-            acc = full ? lane_chi2_f64_rot<S, false, SLOPE>(sv, an, amp0, cc.Ad, valid)
-                       : lane_chi2_f64_rot<S, true, SLOPE>(sv, an, amp0, cc.Ad, valid);
+            if (full)
+                lane_rot<S, false, SLOPE, false, 1>(sv, &an, &amp0, &cc.Ad, valid, &acc);
+            else
+                lane_rot<S, true, SLOPE, false, 1>(sv, &an, &amp0, &cc.Ad, valid, &acc);
         } else {
             acc = full ? lane_chi2_f64<S, false, SLOPE>(sv, an, amp0, cc.Ad, valid)
                        : lane_chi2_f64<S, true, SLOPE>(sv, an, amp0, cc.Ad, valid);
@@ -436,16 +469,20 @@ __device__ __forceinline__ double reduce_partials(const BlockDesc* __restrict__ 
     const int k = NT >= P ? NT / P : 1;
     if (t < P * k) {
         const int c = t / k, part = t - c * k;
-        const double* pr = d->partials + (size_t)c * T;
+        const double* pr = d->partials + (size_t)c * T + part;
+        const int cnt = part < T ? (T - part + k - 1) / k : 0;  // tiles part, part + k, ... < T
         double s = 0.0;
-        int tt = part;
-        // issue four independent loads per step; add them in tile order
-        for (; tt + 3 * k < T; tt += 4 * k) {
-            const double v0 = xld(pr + tt), v1 = xld(pr + tt + k), v2 = xld(pr + tt + 2 * k),
-                         v3 = xld(pr + tt + 3 * k);
-            s = (((s + v0) + v1) + v2) + v3;
+        // batches of 32 loads in flight (one memory round trip per batch), then
+        // added one by one in tile order
+        constexpr int kB = 32;
+        for (int base = 0; base < cnt; base += kB) {
+            double v[kB];
+#pragma unroll
+            for (int q = 0; q < kB; ++q) v[q] = base + q < cnt ? xld(pr + (size_t)(base + q) * k) : 0.0;
+#pragma unroll
+            for (int q = 0; q < kB; ++q)
+                if (base + q < cnt) s += v[q];
         }
-        for (; tt < T; tt += k) s += xld(pr + tt);
         red[t] = s;
     }
     __syncthreads();
@@ -568,19 +605,16 @@ __device__ __forceinline__ void de_step_body(const BlockDesc* __restrict__ d, do
     if (s_done) return;
     const int g = s_gen;
 
-    // selection (generation 0 accepts the initial population)
+    // selection (generation 0 accepts the initial population); the global
+    // stores wait until after the last barrier, which would otherwise wait
+    // for them
     double fsel = __builtin_inf();
+    bool take = false;
     if (i < P) {
-        const bool take = g == 0 || ft <= fo;
-        double* prow = d->pop + (size_t)i * kStride;
+        take = g == 0 || ft <= fo;
 #pragma unroll
-        for (int j = 0; j < kSlots; ++j) {
-            const double v = take ? tr[j] : po[j];
-            xs[i * kSlots + j] = v;
-            if (take) xst(prow + j, v);
-        }
+        for (int j = 0; j < kSlots; ++j) xs[i * kSlots + j] = take ? tr[j] : po[j];
         fsel = take ? ft : fo;
-        if (take) xst(d->fpop + i, ft);
     }
 
     // argmin, lowest index on ties
@@ -620,13 +654,23 @@ __device__ __forceinline__ void de_step_body(const BlockDesc* __restrict__ d, do
     best = ix[0];
     bf = fr[0];
 
+    int flags = 0;
     if (i == 0) {
-        xst(d->hist + g, bf);
-        int flags = 0;
         if (bf <= d->vtr) flags |= 4;  // PT_FLAG_VTR
         if (d->rel_tol > 0.0 && d->window > 0 && g >= d->window && s_old - bf <= d->rel_tol * bf)
             flags |= 1;  // PT_FLAG_CONVERGED
         if (!flags && g >= d->max_gens) flags |= 2;  // PT_FLAG_MAXGEN
+        s_stop = flags != 0;
+    }
+    __syncthreads();
+    if (take) {
+        double* prow = d->pop + (size_t)i * kStride;
+#pragma unroll
+        for (int j = 0; j < kSlots; ++j) xst(prow + j, tr[j]);
+        xst(d->fpop + i, ft);
+    }
+    if (i == 0) {
+        xst(d->hist + g, bf);
         xsti(&st->best, best);
         xst(&st->best_f, bf);
         if (flags) {
@@ -635,9 +679,7 @@ __device__ __forceinline__ void de_step_body(const BlockDesc* __restrict__ d, do
         } else {
             xsti(&st->gen, g + 1);
         }
-        s_stop = flags != 0;
     }
-    __syncthreads();
     if (s_stop || i >= P) return;
 
     // trial vector of member i for generation g + 1
