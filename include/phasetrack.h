@@ -8,6 +8,7 @@
  *
  *     s(t) = (A + Adot t) cos(phi(t)),
  *     phi(t) = phi0 + 2 pi (f0 t + f1 t^2 / 2 + f2 t^3 / 6)          (Eq. 2-2-1..2-2-3)
+ *              [+ 2 pi f3 t^4 / 24, the fourth Taylor order of Sec. 3.2.1]
  *
  * by minimising the unit-weight chi-square of Eq. (2-2-4) with Differential
  * Evolution (Sec. 1.2; control parameters of Table 4) in the DE/rand/1/bin
@@ -19,13 +20,15 @@
  * 4-1-2) and line-of-sight acceleration (Eq. 4-2-1).
  *
  * Conventions shared by every entry point
- *   - Parameter vectors have PT_NSLOT = 6 FP64 slots in this order:
+ *   - Parameter vectors have PT_NSLOT = 7 FP64 slots in this order:
  *       0 A     amplitude, sample units
  *       1 phi0  phase at the reference sample [rad]
  *       2 f0    frequency [Hz]
  *       3 f1    frequency rate [Hz/s]
  *       4 f2    frequency acceleration [Hz/s^2]
  *       5 Adot  amplitude slope [sample units / s] (c5 of Eq. 2-2-2)
+ *       6 f3    third frequency derivative [Hz/s^3]: the fourth-order phase
+ *               term of Sec. 3.2.1 (perigee arcs); box [0, 0] for the cubic
  *     A slot whose box has lo == hi is fixed at lo and takes no part in the
  *     DE; the others are the active dimensions, in slot order.
  *   - Return value: PT_OK (0) or a negative pt_status.  No C++ exception
@@ -51,7 +54,7 @@
 extern "C" {
 #endif
 
-#define PT_NSLOT 6
+#define PT_NSLOT 7
 #define PT_MAX_POP 1024
 
 typedef enum {
@@ -144,7 +147,7 @@ typedef struct {
 
 /* Result of one block fit, with the per-block output record of the
  * paper's Appendix 1.
- *   coef         best member (6 slots, as found inside the box)
+ *   coef         best member (PT_NSLOT slots, as found inside the box)
  *   objective    chi-square at coef (RSS)
  *   generations  generations run after the initial population
  *   flags        PT_FLAG_* bits
@@ -200,14 +203,14 @@ int pt_fit_batch(pt_ctx* ctx, const pt_block* blocks, int nblk, const pt_de_sett
 
 /* Objective of an arbitrary population, for parity checks (Eq. 2-2-4 or
  * Eq. 2-2-5).
- *   pop       device pointer, P x 6 FP64, row-major
+ *   pop       device pointer, P x PT_NSLOT FP64, row-major
  *   out       device pointer, P FP64
  *   precision pt_precision; objective pt_objective_kind */
 int pt_objective(pt_ctx* ctx, const pt_block* block, const double* pop, int P,
                  int precision, int objective, void* hip_stream, double* out);
 
 /* Final population and objectives of block `index` of the context's most
- * recent pt_fit_block / pt_fit_batch call.  pop_host: P x 6 FP64; fpop_host:
+ * recent pt_fit_block / pt_fit_batch call.  pop_host: P x PT_NSLOT FP64; fpop_host:
  * P FP64 (either may be NULL); P must equal that call's population size. */
 int pt_last_population(pt_ctx* ctx, int index, double* pop_host, double* fpop_host, int P);
 
@@ -470,7 +473,7 @@ int pt_ctx_set_timing(pt_ctx* ctx, int on);
 int pt_ctx_kernel_stats(pt_ctx* ctx, int64_t* launches, double* total_ms);
 
 /* Time `reps` back-to-back launches of the objective kernel alone on the
- * population `pop` (device, P x 6) with HIP events on hip_stream; *avg_ms
+ * population `pop` (device, P x PT_NSLOT) with HIP events on hip_stream; *avg_ms
  * receives the mean duration of one launch.  Same kernel, geometry and
  * grid as a fit of this block uses. */
 int pt_time_objective(pt_ctx* ctx, const pt_block* block, const double* pop, int P, int precision, int reps,

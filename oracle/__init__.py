@@ -25,7 +25,7 @@ from . import derived  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
-NSLOT = 6
+NSLOT = 7
 OBJ_CHI2, OBJ_COR = 0, 1
 TAG_INIT, TAG_MUT, TAG_XOVER = 1, 2, 3
 FLAG_CONVERGED, FLAG_MAXGEN, FLAG_VTR, FLAG_AT_BOUND = 1, 2, 4, 8
@@ -137,6 +137,14 @@ def obj_pop(kind, s, fs, ref, pop, nthreads=0):
     return out
 
 
+def _padv(v):
+    """A parameter vector or bound of <= NSLOT slots, missing slots 0."""
+    v = np.asarray(v, dtype=np.float64).ravel()
+    if v.size < NSLOT:
+        v = np.concatenate([v, np.zeros(NSLOT - v.size)])
+    return _f64(v)
+
+
 def _pad(pop):
     pop = np.asarray(pop, dtype=np.float64)
     if pop.ndim == 1:
@@ -147,7 +155,7 @@ def _pad(pop):
 
 
 def chi2_pop(s, fs, ref, pop, nthreads=0):
-    """chi^2 of every row of ``pop`` (P x <=6, missing slots are 0)."""
+    """chi^2 of every row of ``pop`` (P x <= NSLOT, missing slots are 0)."""
     s = _f64(s)
     pop = _pad(pop)
     out = np.empty(pop.shape[0], dtype=np.float64)
@@ -157,6 +165,7 @@ def chi2_pop(s, fs, ref, pop, nthreads=0):
 
 
 def active_slots(lo, hi):
+    lo, hi = _padv(lo), _padv(hi)
     return [j for j in range(NSLOT) if lo[j] < hi[j]]
 
 
@@ -172,8 +181,8 @@ def de_trial(pop, i, r1, r2, r3, jrand, U, act, F, CR, lo, hi):
     pop = _pad(pop)
     U = _f64(U)
     act_a = (ctypes.c_int * len(act))(*act)
-    lo = _f64(lo)
-    hi = _f64(hi)
+    lo = _padv(lo)
+    hi = _padv(hi)
     out = np.empty(NSLOT, dtype=np.float64)
     lib().orc_de_trial(_dptr(pop), i, r1, r2, r3, jrand, _dptr(U), len(act), act_a, F, CR,
                        _dptr(lo), _dptr(hi), _dptr(out))
@@ -181,8 +190,8 @@ def de_trial(pop, i, r1, r2, r3, jrand, U, act, F, CR, lo, hi):
 
 
 def de_init(seed, stream, P, lo, hi):
-    lo = _f64(lo)
-    hi = _f64(hi)
+    lo = _padv(lo)
+    hi = _padv(hi)
     out = np.empty((P, NSLOT), dtype=np.float64)
     lib().orc_de_init(seed, stream, P, _dptr(lo), _dptr(hi), _dptr(out))
     return out
@@ -196,6 +205,7 @@ def de_fit(s, fs, ref, lo, hi, P, max_gens, F=0.5, CR=0.9, seed=0, stream=0,
     cfg.P, cfg.max_gens, cfg.F, cfg.CR = P, max_gens, F, CR
     cfg.seed, cfg.stream, cfg.vtr, cfg.rel_tol, cfg.window = seed, stream, vtr, rel_tol, window
     cfg.objective = objective
+    lo, hi = _padv(lo), _padv(hi)
     for j in range(NSLOT):
         cfg.lo[j] = float(lo[j])
         cfg.hi[j] = float(hi[j])

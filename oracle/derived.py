@@ -13,20 +13,29 @@ import numpy as np
 C_LIGHT = 299792458.0  # m/s
 
 
-def coefs_from_fit(phi0, f0, f1, f2):
-    """(c0, c1, c2, c3) of Eq. (2-2-3) from the fit's parameters."""
-    return phi0, 2.0 * math.pi * f0, math.pi * f1, math.pi * f2 / 3.0
+def coefs_from_fit(phi0, f0, f1, f2, f3=None):
+    """(c0, c1, c2, c3) of Eq. (2-2-3) from the fit's parameters; with f3 also
+    the fourth-order phase coefficient phi^(4)(0) / 4! = pi f3 / 12 (Sec. 3.2.1)."""
+    c = (phi0, 2.0 * math.pi * f0, math.pi * f1, math.pi * f2 / 3.0)
+    return c if f3 is None else c + (math.pi * f3 / 12.0,)
 
 
-def fit_from_coefs(c0, c1, c2, c3):
+def fit_from_coefs(c0, c1, c2, c3, c4=None):
     """Inverse of :func:`coefs_from_fit`."""
-    return c0, c1 / (2.0 * math.pi), c2 / math.pi, 3.0 * c3 / math.pi
+    f = (c0, c1 / (2.0 * math.pi), c2 / math.pi, 3.0 * c3 / math.pi)
+    return f if c4 is None else f + (12.0 * c4 / math.pi,)
+
+
+def _c5(c):
+    """Phase coefficients padded to the fourth order (c4 = 0 for a cubic)."""
+    return tuple(c[:4]) + ((c[4],) if len(c) > 4 else (0.0,))
 
 
 def phase(c, t):
-    """phi(t) = c0 + c1 t + c2 t^2 + c3 t^3 [rad], Eq. (3-1-1)."""
+    """phi(t) = c0 + c1 t + c2 t^2 + c3 t^3 (+ c4 t^4) [rad], Eq. (3-1-1)."""
+    c = _c5(c)
     t = np.asarray(t, dtype=np.float64)
-    return c[0] + c[1] * t + c[2] * t ** 2 + c[3] * t ** 3
+    return c[0] + c[1] * t + c[2] * t ** 2 + c[3] * t ** 3 + c[4] * t ** 4
 
 
 def phase_mod2pi(c, t):
@@ -35,9 +44,10 @@ def phase_mod2pi(c, t):
 
 
 def freq_rad(c, t):
-    """F(t) = d phi / dt = c1 + 2 c2 t + 3 c3 t^2 [rad/s], Eq. (3-1-1)."""
+    """F(t) = d phi / dt = c1 + 2 c2 t + 3 c3 t^2 (+ 4 c4 t^3) [rad/s], Eq. (3-1-1)."""
+    c = _c5(c)
     t = np.asarray(t, dtype=np.float64)
-    return c[1] + 2.0 * c[2] * t + 3.0 * c[3] * t ** 2
+    return c[1] + 2.0 * c[2] * t + 3.0 * c[3] * t ** 2 + 4.0 * c[4] * t ** 3
 
 
 def freq_hz(c, t):
@@ -45,9 +55,10 @@ def freq_hz(c, t):
 
 
 def phase_accel(c, t):
-    """Second derivative of the phase, phi''(t) = 2 c2 + 6 c3 t [rad/s^2]."""
+    """Second derivative of the phase, phi''(t) = 2 c2 + 6 c3 t (+ 12 c4 t^2) [rad/s^2]."""
+    c = _c5(c)
     t = np.asarray(t, dtype=np.float64)
-    return 2.0 * c[2] + 6.0 * c[3] * t
+    return 2.0 * c[2] + 6.0 * c[3] * t + 12.0 * c[4] * t ** 2
 
 
 def total_phase(c, t_start, t_end):

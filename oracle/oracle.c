@@ -69,17 +69,18 @@ static int word_to_index(uint32_t w, int m) { return (int)(((uint64_t)w * (uint6
  *   s(t) = (c4 + c5 t) cos(c0 + c1 t + c2 t^2 + c3 t^3)
  * with c0 = phi0, c1 = 2 pi f0, c2 = pi f1, c3 = pi f2 / 3 (Eq. 2-2-3), i.e.
  *   phi(t) = phi0 + 2 pi (f0 t + f1 t^2 / 2 + f2 t^3 / 6),
+ * extended by the fourth-order term 2 pi f3 t^4 / 24 (Sec. 3.2.1, n = 4),
  * t measured from the block's reference sample (Sec. 2.2: phase origin at
  * the block centre).  The phase is evaluated directly in radians and the
  * cosine is the C library's.
  * ------------------------------------------------------------------------- */
 double orc_chi2(const double* s, int64_t n, double fs, double ref, const double* x) {
-    const double A = x[0], phi0 = x[1], f0 = x[2], f1 = x[3], f2 = x[4], Adot = x[5];
+    const double A = x[0], phi0 = x[1], f0 = x[2], f1 = x[3], f2 = x[4], Adot = x[5], f3 = x[6];
     const double two_pi = 2.0 * M_PI;
     double sum = 0.0, comp = 0.0; /* Neumaier */
     for (int64_t k = 0; k < n; ++k) {
         double t = ((double)k - ref) / fs;
-        double turns = f0 * t + 0.5 * f1 * t * t + f2 * t * t * t / 6.0;
+        double turns = f0 * t + 0.5 * f1 * t * t + f2 * t * t * t / 6.0 + f3 * t * t * t * t / 24.0;
         double phi = phi0 + two_pi * turns;
         double model = (A + Adot * t) * cos(phi);
         double r = s[k] - model;
@@ -95,12 +96,12 @@ double orc_chi2(const double* s, int64_t n, double fs, double ref, const double*
 }
 
 double orc_cor(const double* s, int64_t n, double fs, double ref, const double* x) {
-    const double A = x[0], phi0 = x[1], f0 = x[2], f1 = x[3], f2 = x[4], Adot = x[5];
+    const double A = x[0], phi0 = x[1], f0 = x[2], f1 = x[3], f2 = x[4], Adot = x[5], f3 = x[6];
     const double two_pi = 2.0 * M_PI;
     double sum = 0.0, comp = 0.0; /* Neumaier */
     for (int64_t k = 0; k < n; ++k) {
         double t = ((double)k - ref) / fs;
-        double turns = f0 * t + 0.5 * f1 * t * t + f2 * t * t * t / 6.0;
+        double turns = f0 * t + 0.5 * f1 * t * t + f2 * t * t * t / 6.0 + f3 * t * t * t * t / 24.0;
         double phi = phi0 + two_pi * turns;
         double v = s[k] * ((A + Adot * t) * cos(phi));
         double tsum = sum + v;

@@ -18,7 +18,9 @@
  *
  * Parameter slots (all FP64): 0 = A (amplitude, sample units),
  * 1 = phi0 [rad], 2 = f0 [Hz], 3 = f1 [Hz/s], 4 = f2 [Hz/s^2],
- * 5 = Adot (amplitude slope, sample units per second).
+ * 5 = Adot (amplitude slope, sample units per second),
+ * 6 = f3 [Hz/s^3], the fourth-order Taylor term of Sec. 3.2.1 (phase term
+ *     2 pi f3 t^4 / 24; fixed at 0 for the cubic model).
  * Time of sample n: t_n = (n - ref) / fs seconds, ref in sample units.
  */
 #ifndef PT_ORACLE_H
@@ -30,7 +32,7 @@
 extern "C" {
 #endif
 
-#define ORC_NSLOT 6
+#define ORC_NSLOT 7
 
 /* Random-stream tags (high 16 bits of the fourth counter word). */
 #define ORC_TAG_INIT 1u
@@ -52,7 +54,8 @@ void orc_draw_words(uint64_t seed, uint64_t stream, uint32_t i, uint32_t g,
                     uint32_t tag, uint32_t call, uint32_t out[4]);
 
 /* chi^2 = sum_n (s_n - (A + Adot t_n) cos(phi(t_n)))^2, Eq. (2-2-2)/(2-2-4),
- * Neumaier-compensated, one candidate. */
+ * phi(t) = phi0 + 2 pi (f0 t + f1 t^2/2 + f2 t^3/6 + f3 t^4/24) (Eq. 2-2-1 to
+ * order 3, or 4 with slot 6), Neumaier-compensated, one candidate. */
 double orc_chi2(const double* s, int64_t n, double fs, double ref, const double* x);
 
 /* Correlation objective of Eq. (2-2-5) with the constant-amplitude model of

@@ -95,12 +95,14 @@ def seed_block(s, fs, ref, M, spacing=0):
 def border_continuity(fit_a, fit_b):
     """Eq. (3-1-2) at the border of block a (left) and block b (right):
     (phase difference wrapped to (-pi, pi] [rad], frequency difference [Hz]).
-    fit_x holds phi0, f0, f1, f2 at its own reference and t_left / t_right."""
+    fit_x holds phi0, f0, f1, f2 (and optionally f3) at its own reference and
+    t_left / t_right."""
     def ph(x, t):
-        return x["phi0"] + 2.0 * math.pi * (x["f0"] * t + x["f1"] * t * t / 2.0 + x["f2"] * t ** 3 / 6.0)
+        return x["phi0"] + 2.0 * math.pi * (x["f0"] * t + x["f1"] * t * t / 2.0 + x["f2"] * t ** 3 / 6.0
+                                            + x.get("f3", 0.0) * t ** 4 / 24.0)
 
     def fr(x, t):
-        return x["f0"] + x["f1"] * t + x["f2"] * t * t / 2.0
+        return x["f0"] + x["f1"] * t + x["f2"] * t * t / 2.0 + x.get("f3", 0.0) * t ** 3 / 6.0
 
     d = ph(fit_a, fit_a["t_right"]) - ph(fit_b, fit_b["t_left"])
     d = math.remainder(d, 2.0 * math.pi)
@@ -114,8 +116,8 @@ def seed_box(r, rule, nsig, T, slope=False):
     standard errors (no width is printed for it), f2 from c3 in [-50, 50]
     rad/s^3, i.e. +-150/pi Hz/s^2; rule "sigma" takes nsig standard errors for
     f0, f1, f2 and max(10 %, nsig sd_A) for A.  Adot: +-0.2 A / T with slope."""
-    mid = [r["A"], math.pi, r["f0"], r["f1"], 0.0, 0.0]
-    half = [0.0, math.pi, 0.0, 0.0, 0.0, 0.2 * r["A"] / T if slope else 0.0]
+    mid = [r["A"], math.pi, r["f0"], r["f1"], 0.0, 0.0, 0.0]
+    half = [0.0, math.pi, 0.0, 0.0, 0.0, 0.2 * r["A"] / T if slope else 0.0, 0.0]
     if rule == "paper":
         half[0] = 0.1 * r["A"]
         half[2] = 0.1 * abs(r["f0"])
@@ -131,11 +133,14 @@ def seed_box(r, rule, nsig, T, slope=False):
 
 
 def predict(c, dt):
-    """The fitted phase (A, phi0, f0, f1, f2, Adot) re-expanded dt seconds
-    later (exact Taylor shift of the cubic; phi0 reduced to [0, 2 pi))."""
-    A, phi0, f0, f1, f2, Ad = c
-    ph = phi0 + 2.0 * math.pi * (f0 * dt + f1 * dt * dt / 2.0 + f2 * dt ** 3 / 6.0)
-    return [A + Ad * dt, ph % (2.0 * math.pi), f0 + f1 * dt + f2 * dt * dt / 2.0, f1 + f2 * dt, f2, Ad]
+    """The fitted phase (A, phi0, f0, f1, f2, Adot[, f3]) re-expanded dt seconds
+    later (exact Taylor shift of the quartic; phi0 reduced to [0, 2 pi))."""
+    A, phi0, f0, f1, f2, Ad = c[:6]
+    f3 = c[6] if len(c) > 6 else 0.0
+    ph = phi0 + 2.0 * math.pi * (f0 * dt + f1 * dt * dt / 2.0 + f2 * dt ** 3 / 6.0 + f3 * dt ** 4 / 24.0)
+    out = [A + Ad * dt, ph % (2.0 * math.pi), f0 + f1 * dt + f2 * dt * dt / 2.0 + f3 * dt ** 3 / 6.0,
+           f1 + f2 * dt + f3 * dt * dt / 2.0, f2 + f3 * dt, Ad]
+    return out + [f3] if len(c) > 6 else out
 
 
 def running_box(c, t_since, n, fs, ref, given_lo, given_hi, narrow, extrapolate):
@@ -151,14 +156,15 @@ def running_box(c, t_since, n, fs, ref, given_lo, given_hi, narrow, extrapolate)
     pred = predict(c, t_since + ref / fs)
     lo, hi = list(given_lo), list(given_hi)
     half = [(h - l) / 2.0 for l, h in zip(given_lo, given_hi)]
-    for j in range(6):
+    for j in range(min(len(half), len(pred))):
         if half[j] > 0:
             lo[j] = pred[j] - narrow * half[j]
             hi[j] = pred[j] + narrow * half[j]
     if extrapolate:
         ta, tb = t_since, t_since + n / fs
-        F = lambda t: c[2] + c[3] * t + c[4] * t * t / 2.0  # noqa: E731
-        R = lambda t: c[3] + c[4] * t  # noqa: E731
+        g3 = c[6] if len(c) > 6 else 0.0
+        F = lambda t: c[2] + c[3] * t + c[4] * t * t / 2.0 + g3 * t ** 3 / 6.0  # noqa: E731
+        R = lambda t: c[3] + c[4] * t + g3 * t * t / 2.0  # noqa: E731
         for j, g in ((2, F), (3, R)):
             if half[j] > 0:
                 a, b = sorted((g(ta), g(tb)))

@@ -3,9 +3,10 @@
 // Notation follows Sec. 2.2 of arXiv:1906.10598: the phase of a candidate
 // is phi(t) = phi0 + 2 pi (f0 t + f1 t^2 / 2 + f2 t^3 / 6) with t measured
 // from the block's reference sample.  On the device the phase is carried in
-// turns (phi / 2 pi) as a cubic in the sample offset m = n - ref:
-//     Phi(m) = a0 + a1 m + a2 m^2 + a3 m^3,
+// turns (phi / 2 pi) as a polynomial in the sample offset m = n - ref:
+//     Phi(m) = a0 + a1 m + a2 m^2 + a3 m^3 + a4 m^4,
 //     a0 = phi0 / 2 pi, a1 = f0 / fs, a2 = f1 / (2 fs^2), a3 = f2 / (6 fs^3),
+//     a4 = f3 / (24 fs^4) (the fourth Taylor order of Sec. 3.2.1; 0 for a cubic),
 // which is the same polynomial (Eq. 2-2-3 with c_i = 2 pi a_i fs^i).  Turns
 // make the reduction to one period exact: r = Phi - rint(Phi).
 #pragma once
@@ -17,7 +18,7 @@
 
 namespace pt {
 
-constexpr int kSlots = 6;        // A, phi0, f0, f1, f2, Adot
+constexpr int kSlots = 7;        // A, phi0, f0, f1, f2, Adot, f3
 constexpr int kStride = 8;       // doubles per population row (64-byte rows)
 constexpr int kThreads = 256;    // objective workgroup size (4 wave64)
 constexpr int kMaxCpg = 8;       // largest candidates-per-workgroup instantiated
@@ -63,6 +64,8 @@ struct BlockDesc {
     int* sync;         // persistent kernel: kSyncInts counters (see k_fit_persistent), or null
     int gen_begin;     // persistent kernel: generation whose trial is ready at launch
     int objective;     // 0 = chi-square (Eq. 2-2-4), 1 = correlation (Eq. 2-2-5)
+    int quartic;       // nonzero: the phase has the fourth-order term f3 (slot 6)
+    int pad2;
 };
 
 // Persistent-kernel synchronisation words of one block, one 128-byte line each:

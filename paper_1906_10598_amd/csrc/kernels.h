@@ -94,7 +94,7 @@ __device__ __forceinline__ int find_block(const BlockDesc* __restrict__ descs, i
 
 // Turn-domain coefficients of one candidate (see device.h).
 struct Cand {
-    double a0, a1, a2, a3, A, Ad;  // Ad = Adot / fs: amplitude slope per sample
+    double a0, a1, a2, a3, a4, A, Ad;  // Ad = Adot / fs: amplitude slope per sample
 };
 
 __device__ __forceinline__ Cand make_cand(const double* x, double fs) {
@@ -106,15 +106,17 @@ __device__ __forceinline__ Cand make_cand(const double* x, double fs) {
     c.a3 = xld(x + 4) / (6.0 * fs * fs * fs);
     c.A = xld(x + 0);
     c.Ad = xld(x + 5) / fs;
+    c.a4 = xld(x + 6) / (24.0 * fs * fs * fs * fs);
     return c;
 }
 
 // Phase (turns) and its Taylor coefficients at sample offset m0: anchor
-// b0 = frac(Phi(m0)) and Phi(m0 + j) = b0 + j (b1 + j (b2 + j b3)).  The
-// product a1 m0 (up to ~1e5 turns) is split exactly with an FMA so b0 keeps
-// ~1e-16 turns; m0^2 is exact for |m0| < 2^26.
+// b0 = frac(Phi(m0)) and Phi(m0 + j) = b0 + j (b1 + j (b2 + j (b3 + j b4))).
+// The product a1 m0 (up to ~1e5 turns) is split exactly with an FMA so b0
+// keeps ~1e-16 turns; m0^2 is exact for |m0| < 2^26.  With a4 = 0 every
+// value equals the cubic's (the quartic terms enter as exact zeros).
 struct Anchor {
-    double b0, b1, b2, b3;
+    double b0, b1, b2, b3, b4;
 };
 
 __device__ __forceinline__ Anchor make_anchor(const Cand& c, double m0) {
@@ -123,14 +125,16 @@ __device__ __forceinline__ Anchor make_anchor(const Cand& c, double m0) {
     const double e = __fma_rn(c.a1, m0, -p);
     p -= rint(p);
     const double mm = m0 * m0;
-    double q = __fma_rn(c.a3, m0, c.a2) * mm;
+    double q = __fma_rn(__fma_rn(c.a4, m0, c.a3), m0, c.a2) * mm;
     q -= rint(q);
     double b0 = (c.a0 + p) + (q + e);
     a.b0 = b0 - rint(b0);
     const double t3 = 3.0 * c.a3;
-    a.b2 = __fma_rn(t3, m0, c.a2);
-    a.b1 = __fma_rn(__fma_rn(t3, m0, 2.0 * c.a2), m0, c.a1);
-    a.b3 = c.a3;
+    // b2 = a2 + 3 a3 m0 + 6 a4 m0^2, b1 = a1 + 2 a2 m0 + 3 a3 m0^2 + 4 a4 m0^3, b3 = a3 + 4 a4 m0
+    a.b2 = __fma_rn(__fma_rn(6.0 * c.a4, m0, t3), m0, c.a2);
+    a.b1 = __fma_rn(__fma_rn(__fma_rn(4.0 * c.a4, m0, t3), m0, 2.0 * c.a2), m0, c.a1);
+    a.b3 = __fma_rn(4.0 * c.a4, m0, c.a3);
+    a.b4 = c.a4;
     return a;
 }
 
@@ -142,7 +146,7 @@ __device__ __forceinline__ Anchor make_anchor(const Cand& c, double m0) {
 // exactly reduced phase r(j) = Phi(j) - rint(Phi(j)), so the running value
 // stays within one turn (rounding ~1e-16 turns per step, S <= 32 steps).
 // ---------------------------------------------------------------------------
-template <int S, bool TAIL, bool SLOPE, bool COR = false>
+template <int S, bool TAIL, bool SLOPE, bool COR = false, bool QUART = false>
 __device__ __forceinline__ double lane_chi2_f64(const double (&sv)[S], const Anchor& an, double amp0,
                                                 double ad, int valid) {
     // Samples are processed in groups of IL: the phase recurrence runs
@@ -162,9 +166,18 @@ __device__ __forceinline__ double lane_chi2_f64(const double (&sv)[S], const Anc
 #pragma unroll
     for (int q = 0; q < IL; ++q) acc[q] = 0.0;
     double ph = an.b0;
+    // forward differences of the local cubic, or quartic: d1(0) = b1 + b2 + b3
+    // (+ b4), d2(0) = 2 b2 + 6 b3 (+ 14 b4), d3(0) = 6 b3 (+ 36 b4), d4 = 24 b4
     double d1 = (an.b1 + an.b2) + an.b3;
     double d2 = __fma_rn(6.0, an.b3, 2.0 * an.b2);
-    const double d3 = 6.0 * an.b3;
+    double d3 = 6.0 * an.b3;
+    double d4 = 0.0;
+    if constexpr (QUART) {
+        d1 += an.b4;
+        d2 = __fma_rn(14.0, an.b4, d2);
+        d3 = __fma_rn(36.0, an.b4, d3);
+        d4 = 24.0 * an.b4;
+    }
 #pragma unroll
     for (int g = 0; g < S; g += IL) {
         double u[IL], p[IL];
@@ -175,6 +188,7 @@ __device__ __forceinline__ double lane_chi2_f64(const double (&sv)[S], const Anc
                 ph = r + d1;
                 d1 += d2;
                 d2 += d3;
+                if constexpr (QUART) d3 += d4;
             }
             u[q] = r * r;
             p[q] = PT_COS64[0];
@@ -296,7 +310,7 @@ __device__ __forceinline__ void lane_rot(const double (&sv)[S], const Anchor* an
 // remainder b0 + j (b1l + j (b2 + j b3)) is small-magnitude FP32.  cos, the
 // residual and the lane sum are FP32.
 // ---------------------------------------------------------------------------
-template <int S, bool TAIL, bool SLOPE, bool COR = false>
+template <int S, bool TAIL, bool SLOPE, bool COR = false, bool QUART = false>
 __device__ __forceinline__ float lane_chi2_mixed(const float (&sv)[S], const Anchor& an, double amp0,
                                                  double ad, int valid) {
     constexpr int IL = 4;  // samples whose cosine chains run in lockstep
@@ -306,6 +320,7 @@ __device__ __forceinline__ float lane_chi2_mixed(const float (&sv)[S], const Anc
     const float b0 = (float)an.b0;
     const float b2 = (float)an.b2;
     const float b3 = (float)an.b3;
+    const float b4 = (float)an.b4;
     const float A = (float)amp0;
     const float Ad = (float)ad;
     float acc[IL];
@@ -324,7 +339,8 @@ __device__ __forceinline__ float lane_chi2_mixed(const float (&sv)[S], const Anc
             } else {
                 float lin = jj * b1h;  // exact: b1h has 18 significant bits, j < 64
                 lin -= rintf(lin);
-                const float sm = __fmaf_rn(__fmaf_rn(__fmaf_rn(b3, jj, b2), jj, b1l), jj, b0);
+                const float c3 = QUART ? __fmaf_rn(b4, jj, b3) : b3;
+                const float sm = __fmaf_rn(__fmaf_rn(__fmaf_rn(c3, jj, b2), jj, b1l), jj, b0);
                 ph = lin + sm;
             }
             const float r = ph - rintf(ph);
@@ -384,6 +400,23 @@ __device__ __forceinline__ void load_lane(const BlockDesc* __restrict__ d, int t
     }
 }
 
+// Lane sum of the per-sample paths (MODE 0 FP64, 1 mixed) for one candidate:
+// chi-square (tail samples masked) or correlation (masked samples are zero,
+// so one loop serves both), cubic or quartic phase.
+template <int MODE, int S, bool SLOPE, bool QUART, typename V>
+__device__ __forceinline__ double lane_sum(const V (&sv)[S], const Anchor& an, double amp0, double ad, int valid,
+                                          bool cor, bool full) {
+    if constexpr (MODE == 1) {
+        if (cor) return (double)lane_chi2_mixed<S, false, SLOPE, true, QUART>(sv, an, amp0, ad, valid);
+        return full ? (double)lane_chi2_mixed<S, false, SLOPE, false, QUART>(sv, an, amp0, ad, valid)
+                    : (double)lane_chi2_mixed<S, true, SLOPE, false, QUART>(sv, an, amp0, ad, valid);
+    } else {
+        if (cor) return lane_chi2_f64<S, false, SLOPE, true, QUART>(sv, an, amp0, ad, valid);
+        return full ? lane_chi2_f64<S, false, SLOPE, false, QUART>(sv, an, amp0, ad, valid)
+                    : lane_chi2_f64<S, true, SLOPE, false, QUART>(sv, an, amp0, ad, valid);
+    }
+}
+
 // MODE: 0 = FP64 with per-sample cosine polynomial, 1 = mixed precision,
 // 2 = FP64 phasor recurrence.
 template <int S, int CPG, int MODE, bool SLOPE, typename V>
@@ -394,6 +427,7 @@ __device__ __forceinline__ void objective_unit(const BlockDesc* __restrict__ d, 
     const int ncand = min(CPG, d->P - cbase);
     const int tid = threadIdx.x;
     const bool cor = d->objective != 0;
+    const bool quart = d->quartic != 0;
     if (tid < ncand) cs[tid] = make_cand(d->trial + (size_t)(cbase + tid) * kStride, d->fs);
     const double m0 = (double)((int64_t)tile * (kThreads * S) + (int64_t)tid * S) - d->ref;
     __syncthreads();
@@ -422,25 +456,19 @@ __device__ __forceinline__ void objective_unit(const BlockDesc* __restrict__ d, 
         const Anchor an = make_anchor(cc, m0);
         const double amp0 = SLOPE ? __fma_rn(cc.Ad, m0, cc.A) : cc.A;
         double acc;
-        if (cor) {
-            // correlation objective: masked tail samples are zero, one loop serves both
-            if constexpr (MODE == 1)
-                acc = (double)lane_chi2_mixed<S, false, SLOPE, true>(sv, an, amp0, cc.Ad, valid);
-            else if constexpr (MODE == 2)
+        if constexpr (MODE == 2) {
+            // the anchor carries the quartic term; inside the chunk it is part of
+            // the dropped terms the host bounds
+            if (cor)
                 lane_rot<S, false, SLOPE, true, 1>(sv, &an, &amp0, &cc.Ad, valid, &acc);
-            else
-                acc = lane_chi2_f64<S, false, SLOPE, true>(sv, an, amp0, cc.Ad, valid);
-        } else if constexpr (MODE == 1) {
-            acc = full ? (double)lane_chi2_mixed<S, false, SLOPE>(sv, an, amp0, cc.Ad, valid)
-                       : (double)lane_chi2_mixed<S, true, SLOPE>(sv, an, amp0, cc.Ad, valid);
-        } else if constexpr (MODE == 2) {
-            if (full)
+            else if (full)
                 lane_rot<S, false, SLOPE, false, 1>(sv, &an, &amp0, &cc.Ad, valid, &acc);
             else
                 lane_rot<S, true, SLOPE, false, 1>(sv, &an, &amp0, &cc.Ad, valid, &acc);
+        } else if (quart) {
+            acc = lane_sum<MODE, S, SLOPE, true>(sv, an, amp0, cc.Ad, valid, cor, full);
         } else {
-            acc = full ? lane_chi2_f64<S, false, SLOPE>(sv, an, amp0, cc.Ad, valid)
-                       : lane_chi2_f64<S, true, SLOPE>(sv, an, amp0, cc.Ad, valid);
+            acc = lane_sum<MODE, S, SLOPE, false>(sv, an, amp0, cc.Ad, valid, cor, full);
         }
         red[c][tid] = acc;
     }
@@ -515,8 +543,8 @@ __device__ __forceinline__ void init_block(const BlockDesc* __restrict__ d) {
         double x[kStride];
 #pragma unroll
         for (int j = 0; j < kSlots; ++j) x[j] = d->lo[j];
-        x[6] = 0.0;
-        x[7] = 0.0;
+#pragma unroll
+        for (int j = kSlots; j < kStride; ++j) x[j] = 0.0;
         U4 w{0, 0, 0, 0};
         for (int a = 0; a < d->D; ++a) {
             if ((a & 3) == 0) w = draw4(d->seed, d->stream, (uint32_t)i, 0u, kTagInit, (uint32_t)(a >> 2));
@@ -704,8 +732,8 @@ __device__ __forceinline__ void de_step_body(const BlockDesc* __restrict__ d, do
     double y[kStride];
 #pragma unroll
     for (int j = 0; j < kSlots; ++j) y[j] = xs[i * kSlots + j];
-    y[6] = 0.0;
-    y[7] = 0.0;
+#pragma unroll
+    for (int j = kSlots; j < kStride; ++j) y[j] = 0.0;
     U4 u{0, 0, 0, 0};
     for (int a = 0; a < d->D; ++a) {
         if ((a & 3) == 0) u = draw4(d->seed, d->stream, (uint32_t)i, gn, kTagXover, (uint32_t)(a >> 2));

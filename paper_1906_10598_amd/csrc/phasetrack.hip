@@ -198,12 +198,20 @@ PersistKernel persistent_kernel(int dtype, Geometry g, int mode, bool slope) {
 // turns when (S - 1)^3 |f2| / (6 fs^3) <= 1e-12 and the chunk's second
 // difference 2 |b2| <= 1e-2 / (2 pi), with b2 = f1 / (2 fs^2) + f2 m / (2 fs^3)
 // over the block's sample offsets |m| <= n + |ref|.
-bool phasor_ok(int spl, double fs, double span, double f1max, double f2max) {
+// The phasor path drops the chunk-local terms b3 j^3 + b4 j^4 (j < S) and
+// needs a small second difference; with |m0| <= span, b3 = a3 + 4 a4 m0,
+// b2 = a2 + 3 a3 m0 + 6 a4 m0^2 (turns per sample^k).
+bool phasor_ok(int spl, double fs, double span, double f1max, double f2max, double f3max) {
     const double a3 = f2max / (6.0 * fs * fs * fs);
-    const double b2 = f1max / (2.0 * fs * fs) + 3.0 * a3 * span;
+    const double a4 = f3max / (24.0 * fs * fs * fs * fs);
+    const double b3 = a3 + 4.0 * a4 * span;
+    const double b2 = f1max / (2.0 * fs * fs) + 3.0 * a3 * span + 6.0 * a4 * span * span;
     const double s1 = spl - 1;
-    return s1 * s1 * s1 * a3 <= 1e-12 && 2.0 * b2 <= 1e-2 / (2.0 * M_PI);
+    return s1 * s1 * s1 * (b3 + s1 * a4) <= 1e-12 && 2.0 * b2 <= 1e-2 / (2.0 * M_PI);
 }
+
+double box_max(const pt_box& bx, int j) { return std::max(std::fabs(bx.lo[j]), std::fabs(bx.hi[j])); }
+bool box_quartic(const pt_box& bx) { return bx.lo[6] != 0.0 || bx.hi[6] != 0.0; }
 
 unsigned pow2_at_least(int v) {
     unsigned p = 256;
@@ -456,10 +464,8 @@ int prepare(pt_ctx* ctx, const pt_block* blocks, int nblk, const pt_de_settings*
         bool ok = true;
         for (int b = 0; b < nblk && ok; ++b) {
             const pt_box& bx = blocks[b].box;
-            const double f1 = std::max(std::fabs(bx.lo[3]), std::fabs(bx.hi[3]));
-            const double f2 = std::max(std::fabs(bx.lo[4]), std::fabs(bx.hi[4]));
             const double span = (double)blocks[b].n + std::fabs(block_ref(&blocks[b]));
-            ok = phasor_ok(pl->geo.spl, blocks[b].fs, span, f1, f2);
+            ok = phasor_ok(pl->geo.spl, blocks[b].fs, span, box_max(bx, 3), box_max(bx, 4), box_max(bx, 6));
         }
         if (ok) pl->mode = kModePhasor;
     }
@@ -556,6 +562,7 @@ int prepare(pt_ctx* ctx, const pt_block* blocks, int nblk, const pt_de_settings*
         d.sync = with_state ? static_cast<int*>(ctx->sync.p) + (size_t)b * kSyncInts : nullptr;
         d.gen_begin = 0;
         d.objective = de->objective;
+        d.quartic = box_quartic(B.box);
         hd[b] = d;
     }
     HIPCHK(hipMemcpyAsync(ctx->desc.p, hd, sizeof(BlockDesc) * nblk, hipMemcpyHostToDevice, s));
@@ -564,9 +571,11 @@ int prepare(pt_ctx* ctx, const pt_block* blocks, int nblk, const pt_de_settings*
 
 void derive(pt_fit* f) {
     const double two_pi = 2.0 * M_PI;
-    const double phi0 = f->coef[1], f0 = f->coef[2], f1 = f->coef[3], f2 = f->coef[4];
-    auto phase = [&](double t) { return phi0 + two_pi * (f0 * t + f1 * t * t / 2.0 + f2 * t * t * t / 6.0); };
-    auto freq = [&](double t) { return f0 + f1 * t + f2 * t * t / 2.0; };
+    const double phi0 = f->coef[1], f0 = f->coef[2], f1 = f->coef[3], f2 = f->coef[4], f3 = f->coef[6];
+    auto phase = [&](double t) {
+        return phi0 + two_pi * (f0 * t + f1 * t * t / 2.0 + f2 * t * t * t / 6.0 + f3 * t * t * t * t / 24.0);
+    };
+    auto freq = [&](double t) { return f0 + f1 * t + f2 * t * t / 2.0 + f3 * t * t * t / 6.0; };
     auto wrap = [&](double p) {
         double r = std::fmod(p, two_pi);
         return r < 0 ? r + two_pi : r;
@@ -780,6 +789,32 @@ static int eval_setup(pt_ctx* ctx, const pt_block* block, const double* pop, int
     if (precision != PT_PREC_FP64 && precision != PT_PREC_MIXED) return fail(PT_EINVAL, "precision %d", precision);
     if (objective != PT_OBJ_CHI2 && objective != PT_OBJ_COR) return fail(PT_EINVAL, "objective %d", objective);
     HIPCHK(hipSetDevice(ctx->device));
+    // The population decides the arithmetic (it may leave the box): the
+    // amplitude-slope and quartic terms are on when any row uses them, and
+    // the FP64 phasor path when every row satisfies its bound.
+    std::vector<double> hp((size_t)P * PT_NSLOT);
+    HIPCHK(hipMemcpyAsync(hp.data(), pop, hp.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    pt_block blk = *block;
+    double f1 = 0.0, f2 = 0.0, f3 = 0.0;
+    for (int j : {5, 6}) {
+        double lo = 0.0, hi = 0.0;
+        for (int p = 0; p < P; ++p) {
+            const double v = hp[(size_t)p * PT_NSLOT + j];
+            if (v != 0.0 || !std::isfinite(v)) {
+                lo = std::min(lo, v);
+                hi = std::max(hi, v);
+                if (!std::isfinite(v)) hi = 1.0;  // keep the term on; the result is not finite anyway
+            }
+        }
+        blk.box.lo[j] = std::isfinite(lo) ? lo : -1.0;
+        blk.box.hi[j] = std::isfinite(hi) ? hi : 1.0;
+    }
+    for (int p = 0; p < P; ++p) {
+        f1 = std::max(f1, std::fabs(hp[(size_t)p * PT_NSLOT + 3]));
+        f2 = std::max(f2, std::fabs(hp[(size_t)p * PT_NSLOT + 4]));
+        f3 = std::max(f3, std::fabs(hp[(size_t)p * PT_NSLOT + 6]));
+    }
     pt_de_settings de;
     std::memset(&de, 0, sizeof de);
     de.pop = P;
@@ -789,23 +824,15 @@ static int eval_setup(pt_ctx* ctx, const pt_block* block, const double* pop, int
     de.precision = precision;
     de.objective = objective;
     void* old_desc = ctx->desc.p;
-    if ((rc = prepare(ctx, block, 1, &de, s, pl, false))) return rc;
+    if ((rc = prepare(ctx, &blk, 1, &de, s, pl, false))) return rc;
     if (ctx->desc.p != old_desc) ctx->drop_graphs();
     const BlockDesc* hd = static_cast<const BlockDesc*>(ctx->hdesc.p);
     HIPCHK(hipMemcpy2DAsync(hd[0].trial, kStride * sizeof(double), pop, PT_NSLOT * sizeof(double),
                             PT_NSLOT * sizeof(double), P, hipMemcpyDeviceToDevice, s));
     if (!pl->mixed && ctx->fp64_method != PT_FP64_POLY) {
-        // the arithmetic follows the population itself (which may leave the box)
-        std::vector<double> hp((size_t)P * PT_NSLOT);
-        HIPCHK(hipMemcpyAsync(hp.data(), pop, hp.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        double f1 = 0.0, f2 = 0.0;
-        for (int p = 0; p < P; ++p) {
-            f1 = std::max(f1, std::fabs(hp[(size_t)p * PT_NSLOT + 3]));
-            f2 = std::max(f2, std::fabs(hp[(size_t)p * PT_NSLOT + 4]));
-        }
         const double span = (double)block->n + std::fabs(block_ref(block));
-        pl->mode = std::isfinite(f1) && std::isfinite(f2) && phasor_ok(pl->geo.spl, block->fs, span, f1, f2)
+        pl->mode = std::isfinite(f1) && std::isfinite(f2) && std::isfinite(f3) &&
+                           phasor_ok(pl->geo.spl, block->fs, span, f1, f2, f3)
                        ? kModePhasor
                        : kModePoly;
     }
@@ -893,8 +920,14 @@ int pt_last_history(pt_ctx* ctx, int index, double* hist_host, int n, int* count
 }
 
 // ------------------------------------------------------ derived observables
+// phi(t) [rad] and F(t) [Hz] of a fit (Eq. 3-1-1, with the quartic term of slot 6)
 static double fit_phase(const pt_fit* f, double t) {
-    return f->coef[1] + 2.0 * M_PI * (f->coef[2] * t + f->coef[3] * t * t / 2.0 + f->coef[4] * t * t * t / 6.0);
+    const double* c = f->coef;
+    return c[1] + 2.0 * M_PI * (c[2] * t + c[3] * t * t / 2.0 + c[4] * t * t * t / 6.0 + c[6] * t * t * t * t / 24.0);
+}
+static double fit_freq(const pt_fit* f, double t) {
+    const double* c = f->coef;
+    return c[2] + c[3] * t + c[4] * t * t / 2.0 + c[6] * t * t * t / 6.0;
 }
 
 int pt_phase(const pt_fit* fit, const double* t, int64_t n, double* phase, double* phase_mod2pi, double* freq_hz,
@@ -910,8 +943,8 @@ int pt_phase(const pt_fit* fit, const double* t, int64_t n, double* phase, doubl
             double r = std::fmod(p, two_pi);
             phase_mod2pi[k] = r < 0 ? r + two_pi : r;
         }
-        if (freq_hz) freq_hz[k] = fit->coef[2] + fit->coef[3] * tk + fit->coef[4] * tk * tk / 2.0;
-        if (fdot_hz_s) fdot_hz_s[k] = fit->coef[3] + fit->coef[4] * tk;
+        if (freq_hz) freq_hz[k] = fit_freq(fit, tk);
+        if (fdot_hz_s) fdot_hz_s[k] = fit->coef[3] + fit->coef[4] * tk + fit->coef[6] * tk * tk / 2.0;
     }
     return PT_OK;
 }
@@ -944,7 +977,7 @@ int pt_los_accel(const pt_fit* fit, double t, double f_carrier_hz, double M2, in
     if (!(f_carrier_hz > 0)) return fail(PT_EINVAL, "f_carrier must be > 0");
     if (three_way && !(M2 > 0)) return fail(PT_EINVAL, "M2 must be > 0 for three-way");
     const double c = 299792458.0;
-    const double phi2 = 2.0 * M_PI * (fit->coef[3] + fit->coef[4] * t);  // rad/s^2
+    const double phi2 = 2.0 * M_PI * (fit->coef[3] + fit->coef[4] * t + fit->coef[6] * t * t / 2.0);  // rad/s^2
     const double k = three_way ? 4.0 * M_PI * M2 * f_carrier_hz : 2.0 * M_PI * f_carrier_hz;
     *a_m_s2 = phi2 * c / k;
     return PT_OK;
@@ -956,9 +989,7 @@ int pt_continuity(const pt_fit* a, const pt_fit* b, double* dphi_rad, double* df
     const double d = fit_phase(a, ta) - fit_phase(b, tb);
     if (dphi_rad) *dphi_rad = std::remainder(d, 2.0 * M_PI);
     if (dfreq_hz) {
-        const double fa = a->coef[2] + a->coef[3] * ta + a->coef[4] * ta * ta / 2.0;
-        const double fb = b->coef[2] + b->coef[3] * tb + b->coef[4] * tb * tb / 2.0;
-        *dfreq_hz = fa - fb;
+        *dfreq_hz = fit_freq(a, ta) - fit_freq(b, tb);
     }
     return PT_OK;
 }
@@ -1070,6 +1101,8 @@ int pt_seed_box(const pt_seed* sd, int rule, double nsig, double T, int slope, p
     mid[3] = sd->f1;
     mid[5] = 0.0;
     half[5] = slope ? 0.2 * sd->A / T : 0.0;
+    mid[6] = 0.0;  // seeding gives no estimate of f3: the cubic model
+    half[6] = 0.0;
     if (rule == PT_RANGE_PAPER) {
         half[0] = 0.1 * sd->A;
         half[2] = 0.1 * std::fabs(sd->f0);
@@ -1181,7 +1214,7 @@ int pt_ctx_autotune(pt_ctx* ctx, int64_t n, int P, int precision, void* hip_stre
     std::vector<double> hp((size_t)P * PT_NSLOT);
     for (int p = 0; p < P; ++p) {
         double* x = &hp[(size_t)p * PT_NSLOT];
-        x[0] = 1.0; x[1] = 0.1 * p; x[2] = 1000.0 + 1e-3 * p; x[3] = 0.5; x[4] = 0.01; x[5] = 0.0;
+        x[0] = 1.0; x[1] = 0.1 * p; x[2] = 1000.0 + 1e-3 * p; x[3] = 0.5; x[4] = 0.01; x[5] = 0.0; x[6] = 0.0;
     }
     HIPCHK(hipMemcpy(ctx->eval_pop.p, hp.data(), hp.size() * 8, hipMemcpyHostToDevice));
     pt_block b;
@@ -1194,6 +1227,7 @@ int pt_ctx_autotune(pt_ctx* ctx, int64_t n, int P, int precision, void* hip_stre
     b.ref = NAN;
     for (int j = 0; j < PT_NSLOT; ++j) { b.box.lo[j] = 0; b.box.hi[j] = 1; }
     b.box.hi[5] = 0;
+    b.box.hi[6] = 0;
     const Geometry saved = ctx->forced;
     Geometry best{0, 0};
     double best_ms = 1e30;
@@ -1294,20 +1328,23 @@ struct pt_server {
 namespace {
 
 // Phase of the previous fit re-expanded about the new block's reference
-// time, dt seconds later: phi0 + 2 pi (f0 dt + f1 dt^2/2 + f2 dt^3/6),
-// f0 + f1 dt + f2 dt^2/2, f1 + f2 dt, f2; amplitude A + Adot dt.
+// time, dt seconds later: phi0 + 2 pi (f0 dt + f1 dt^2/2 + f2 dt^3/6 + f3 dt^4/24),
+// f0 + f1 dt + f2 dt^2/2 + f3 dt^3/6, f1 + f2 dt + f3 dt^2/2, f2 + f3 dt, f3;
+// amplitude A + Adot dt.
 void predict(const double* c, double dt, double* out) {
     const double two_pi = 2.0 * M_PI;
-    double turns = c[2] * dt + c[3] * dt * dt / 2.0 + c[4] * dt * dt * dt / 6.0;
+    const double d2 = dt * dt, d3 = d2 * dt;
+    double turns = c[2] * dt + c[3] * d2 / 2.0 + c[4] * d3 / 6.0 + c[6] * d3 * dt / 24.0;
     turns -= std::floor(turns);
     double ph = std::fmod(c[1] + two_pi * turns, two_pi);
     if (ph < 0) ph += two_pi;
     out[0] = c[0] + c[5] * dt;
     out[1] = ph;
-    out[2] = c[2] + c[3] * dt + c[4] * dt * dt / 2.0;
-    out[3] = c[3] + c[4] * dt;
-    out[4] = c[4];
+    out[2] = c[2] + c[3] * dt + c[4] * d2 / 2.0 + c[6] * d3 / 6.0;
+    out[3] = c[3] + c[4] * dt + c[6] * d2 / 2.0;
+    out[4] = c[4] + c[6] * dt;
     out[5] = c[5];
+    out[6] = c[6];
 }
 
 size_t slot_bytes(const pt_block& b, int P, int max_gens, int tile) {
@@ -1320,10 +1357,10 @@ size_t slot_bytes(const pt_block& b, int P, int max_gens, int tile) {
 int slot_mode(const pt_server* sv, const pt_block& b) {
     if (sv->cfg.de.precision == PT_PREC_MIXED) return kModeMixed;
     if (sv->ctx->fp64_method == PT_FP64_POLY) return kModePoly;
-    const double f1 = std::max(std::fabs(b.box.lo[3]), std::fabs(b.box.hi[3]));
-    const double f2 = std::max(std::fabs(b.box.lo[4]), std::fabs(b.box.hi[4]));
     const double span = (double)b.n + std::fabs(b.ref);
-    return phasor_ok(sv->geo.spl, b.fs, span, f1, f2) ? kModePhasor : kModePoly;
+    return phasor_ok(sv->geo.spl, b.fs, span, box_max(b.box, 3), box_max(b.box, 4), box_max(b.box, 6))
+               ? kModePhasor
+               : kModePoly;
 }
 
 // Warm box of a track's next block around the prediction from its last fit.
@@ -1343,8 +1380,8 @@ void warm_box(const pt_server* sv, const pt_server::Track& tr, const pt_block& g
     // Sec. 3.1.1 running range: frequency and rate over the new block's span
     const double* c = tr.last.coef;
     const double ta = tr.t_since, tb = tr.t_since + (double)b.n / b.fs;
-    const double fa = c[2] + c[3] * ta + c[4] * ta * ta / 2.0, fb = c[2] + c[3] * tb + c[4] * tb * tb / 2.0;
-    const double ra = c[3] + c[4] * ta, rb = c[3] + c[4] * tb;
+    const double fa = fit_freq(&tr.last, ta), fb = fit_freq(&tr.last, tb);
+    const double ra = c[3] + c[4] * ta + c[6] * ta * ta / 2.0, rb = c[3] + c[4] * tb + c[6] * tb * tb / 2.0;
     const double lo_v[2] = {std::min(fa, fb), std::min(ra, rb)}, hi_v[2] = {std::max(fa, fb), std::max(ra, rb)};
     for (int q = 0; q < 2; ++q) {
         const int j = 2 + q;

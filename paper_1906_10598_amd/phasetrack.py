@@ -15,7 +15,7 @@ import math
 import os
 from typing import Optional, Sequence
 
-NSLOT = 6
+NSLOT = 7  # A, phi0, f0, f1, f2, Adot, f3
 MAX_POP = 1024
 PT_OK, PT_EINVAL, PT_ENOMEM, PT_EDEVICE, PT_EBUSY, PT_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 PT_F32, PT_F64 = 0, 1
@@ -461,10 +461,11 @@ def pt_ctx_autotune(ctx, n: int, P: int, precision: int, stream=None):
 
 # ------------------------------------------------------------ conveniences
 def make_box(lo, hi) -> pt_box:
+    """Box from lo / hi sequences of up to NSLOT slots (missing slots fixed at 0)."""
     b = pt_box()
     for j in range(NSLOT):
-        b.lo[j] = float(lo[j])
-        b.hi[j] = float(hi[j])
+        b.lo[j] = float(lo[j]) if j < len(lo) else 0.0
+        b.hi[j] = float(hi[j]) if j < len(hi) else 0.0
     return b
 
 
@@ -545,9 +546,11 @@ class Context:
         """Objective (chi^2 or correlation) of each row of ``pop`` (torch FP64 tensor P x 6 on the GPU)."""
         import torch
 
+        if pop.dim() == 2 and pop.shape[1] < NSLOT:  # missing slots are 0
+            pop = torch.nn.functional.pad(pop, (0, NSLOT - pop.shape[1]))
         pop = pop.contiguous()
         if pop.dtype != torch.float64 or pop.dim() != 2 or pop.shape[1] != NSLOT or not pop.is_cuda:
-            raise ValueError("pop must be a CUDA float64 tensor of shape (P, 6)")
+            raise ValueError(f"pop must be a CUDA float64 tensor of shape (P, <= {NSLOT})")
         out = torch.empty(pop.shape[0], dtype=torch.float64, device=pop.device)
         pt_objective(self.handle, block, pop.data_ptr(), pop.shape[0], precision, out.data_ptr(),
                      current_stream(), objective)

@@ -9,7 +9,8 @@ The paper's recordings (Mars Express, Chang'E-4 relay; Sec. 2.1, Sec. 4) are
 not available, so these generators stand in for them with the paper's
 shapes: real narrow-band samples quantised to 16 bit (Table 3), blocks of
 hundreds of thousands of samples (Sec. 1.3, 400K per block), block lengths
-up to 20 s (Sec. 4.1.1), and a cubic Taylor phase (Eq. 2-2-1, n = 3).
+up to 20 s (Sec. 4.1.1), and a cubic Taylor phase (Eq. 2-2-1, n = 3), or a
+quartic one for perigee-like arcs (Sec. 3.2.1, n = 4).
 """
 from .signals import (  # noqa: F401
     NSLOT,
@@ -20,5 +21,7 @@ from .signals import (  # noqa: F401
     config1,
     config3,
     config4_stream,
+    config_quartic,
     shift_truth,
+    shift_truth4,
 )

@@ -34,7 +34,7 @@ from typing import List, Optional
 
 import numpy as np
 
-NSLOT = 6  # A, phi0 [rad], f0 [Hz], f1 [Hz/s], f2 [Hz/s^2], Adot [1/s]
+NSLOT = 7  # A, phi0 [rad], f0 [Hz], f1 [Hz/s], f2 [Hz/s^2], Adot [1/s], f3 [Hz/s^3]
 _SEED_BASE = 0x19061059
 
 
@@ -90,7 +90,18 @@ def shift_truth(phi0, f0, f1, f2, dt):
     return phi, f0n, f1n, float(F2)
 
 
-def block_from_phase(n, fs, amp, phi0, f0, f1, f2, sigma, rng, quantise, t0=0.0, full_scale=None):
+def shift_truth4(phi0, f0, f1, f2, f3, dt):
+    """shift_truth for a quartic phase (f3 t^4 / 24 added): returns
+    (phi0', f0', f1', f2', f3) about t = dt, exact rationals."""
+    F0, F1, F2, F3, D = Fraction(f0), Fraction(f1), Fraction(f2), Fraction(f3), Fraction(dt)
+    turns = F0 * D + F1 * D ** 2 / 2 + F2 * D ** 3 / 6 + F3 * D ** 4 / 24
+    frac = turns - math.floor(turns)
+    phi = math.fmod(phi0 + 2.0 * math.pi * float(frac), 2.0 * math.pi)
+    return (phi, float(F0 + F1 * D + F2 * D ** 2 / 2 + F3 * D ** 3 / 6), float(F1 + F2 * D + F3 * D ** 2 / 2),
+            float(F2 + F3 * D), float(F3))
+
+
+def block_from_phase(n, fs, amp, phi0, f0, f1, f2, sigma, rng, quantise, t0=0.0, full_scale=None, f3=0.0):
     """Samples amp * cos(phase(t0 + k/fs)) + noise for k < n (phase at absolute time).
 
     quantise: int16 codes q / 32767 as FP32, with the block's own peak as full
@@ -100,6 +111,8 @@ def block_from_phase(n, fs, amp, phi0, f0, f1, f2, sigma, rng, quantise, t0=0.0,
     t = t0 + k / fs
     # phase in turns with exact-integer removal of f0*t0 style large parts
     turns = f0 * t + f1 * t * t / 2.0 + f2 * t * t * t / 6.0
+    if f3:
+        turns = turns + f3 * t ** 4 / 24.0
     turns = turns - np.floor(turns)
     s = amp * np.cos(phi0 + 2.0 * np.pi * turns)
     if sigma > 0:
@@ -123,8 +136,8 @@ def config0(seed: int = 0) -> Block:
     s, _ = block_from_phase(n, fs, A, phi0, f0, f1, 0.0, sigma, rng, quantise=False)
     ref = n / 2.0
     p, g0, g1, g2 = shift_truth(phi0, f0, f1, 0.0, ref / fs)
-    truth = np.array([A, p, g0, g1, 0.0, 0.0])
-    half = np.array([0.2 * A, math.pi, 2.0, 1.0, 0.0, 0.0])
+    truth = np.array([A, p, g0, g1, 0.0, 0.0, 0.0])
+    half = np.array([0.2 * A, math.pi, 2.0, 1.0, 0.0, 0.0, 0.0])
     de = DESettings(pop=32, max_gens=200, F=0.5, CR=0.9, seed=(_SEED_BASE ^ 0xDE) + seed)
     return Block(np.ascontiguousarray(s, dtype=np.float64), fs, ref, truth, truth - half,
                  truth + half, de, sigma, stream=0, name="tiny-4096-fp64")
@@ -146,8 +159,8 @@ def _paper_block(n, fs, snr_db, rng, gens, seed, stream, name):
     ref = n / 2.0
     p, g0, g1, g2 = shift_truth(phi0, f0, f1, f2, ref / fs)
     a = A * scale
-    truth = np.array([a, p, g0, g1, g2, 0.0])
-    half = np.array([0.1 * a, math.pi, 0.5, 0.1, 0.01, 0.0])
+    truth = np.array([a, p, g0, g1, g2, 0.0, 0.0])
+    half = np.array([0.1 * a, math.pi, 0.5, 0.1, 0.01, 0.0, 0.0])
     de = DESettings(pop=40, max_gens=gens, F=0.5, CR=0.9, seed=(_SEED_BASE ^ 0xDE) + seed)
     return Block(s, fs, ref, truth, truth - half, truth + half, de, sigma * scale,
                  stream=stream, name=name, meta={"snr_db": snr_db})
@@ -203,8 +216,8 @@ def config4_stream(seed: int = 0, ntracks: int = 16, nblocks: int = 160,
         ref = n / 2.0
         p, g0, g1, g2 = shift_truth(tr["phi0"], tr["f0"], tr["f1"], tr["f2"], t0 + ref / fs)
         a = A * scale
-        truth = np.array([a, p, g0, g1, g2, 0.0])
-        half = np.array([0.1 * a, math.pi, 0.5, 0.1, 0.01, 0.0])
+        truth = np.array([a, p, g0, g1, g2, 0.0, 0.0])
+        half = np.array([0.1 * a, math.pi, 0.5, 0.1, 0.01, 0.0, 0.0])
         blk = Block(s, fs, ref, truth, truth - half, truth + half,
                     DESettings(pop=40, max_gens=3000, F=0.5, CR=0.9,
                                seed=(_SEED_BASE ^ 0xDE) + seed, rel_tol=1e-9, window=50),
@@ -214,3 +227,27 @@ def config4_stream(seed: int = 0, ntracks: int = 16, nblocks: int = 160,
         tr["t"] = t0 + n / fs
         tr["seq"] += 1
     return out
+
+
+def config_quartic(seed: int = 0, n: int = 1_000_000) -> Block:
+    """Perigee-like block (Sec. 3.2.1): 20 s at 50 kHz whose phase needs the
+    fourth Taylor order.  f0 ~ U(-15, 15) kHz, f1 ~ U(-5, 5) Hz/s,
+    f2 ~ U(-0.05, 0.05) Hz/s^2, |f3| ~ U(2e-4, 1e-3) Hz/s^3 with a random sign
+    (0.5 to 2.6 rad of quartic phase at the block ends), 0 dB, int16 with the
+    block's peak as full scale.  Box: the paper-scale half-widths plus
+    f3 +- 2e-4 Hz/s^3; DE P = 40, 2000 generations."""
+    rng = _rng(5, 0, seed)
+    fs, A = 50_000.0, 1.0
+    sigma = A / math.sqrt(2.0)
+    phi0, f0, f1, f2 = _paper_truth(rng)
+    f0 = float(np.clip(f0, -15000.0, 15000.0))
+    f3 = float(rng.uniform(2e-4, 1e-3) * rng.choice([-1.0, 1.0]))
+    s, scale = block_from_phase(n, fs, A, phi0, f0, f1, f2, sigma, rng, quantise=True, f3=f3)
+    ref = n / 2.0
+    p, g0, g1, g2, g3 = shift_truth4(phi0, f0, f1, f2, f3, ref / fs)
+    a = A * scale
+    truth = np.array([a, p, g0, g1, g2, 0.0, g3])
+    half = np.array([0.1 * a, math.pi, 0.5, 0.1, 0.01, 0.0, 2e-4])
+    de = DESettings(pop=40, max_gens=2000, F=0.5, CR=0.9, seed=(_SEED_BASE ^ 0xDE) + seed)
+    return Block(s, fs, ref, truth, truth - half, truth + half, de, sigma * scale,
+                 stream=0, name=f"quartic-{n}-fp32")

@@ -85,11 +85,14 @@ def random_population(rng, lo, hi, P, far=0):
     """P members uniform in the box, plus `far` members well outside it."""
     lo = np.asarray(lo, dtype=np.float64)
     hi = np.asarray(hi, dtype=np.float64)
-    pop = lo + rng.random((P, 6)) * (hi - lo)
+    ns = lo.size
+    pop = lo + rng.random((P, ns)) * (hi - lo)
     for k in range(min(far, P)):
         w = hi - lo
-        pop[k] = lo + (rng.random(6) * 5 - 2) * np.where(w > 0, w, 1.0)
-        pop[k, 5] = 0.0 if hi[5] == lo[5] else pop[k, 5]
+        pop[k] = lo + (rng.random(ns) * 5 - 2) * np.where(w > 0, w, 1.0)
+        for j in (5, 6):  # amplitude slope and quartic term stay off when their box is fixed
+            if j < ns and hi[j] == lo[j]:
+                pop[k, j] = lo[j]
     return pop
 
 

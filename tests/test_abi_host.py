@@ -202,3 +202,33 @@ def test_continuity_matches_oracle():
         wp, wf = oseed.border_continuity(da, db)
         assert abs(math.remainder(dphi - wp, 2 * math.pi)) < 1e-9 and abs(dfreq - wf) < 1e-9
         assert abs(math.remainder(dphi + jump + 2 * math.pi * fjump * b.t_left, 2 * math.pi)) < 1e-6
+
+
+def test_quartic_observables_match_oracle():
+    # slot 6 (f3, the fourth Taylor order of Sec. 3.2.1) in every derived observable
+    from oracle import seed as oseed
+
+    rng = np.random.default_rng(12)
+    for _ in range(20):
+        phi0, f0, f1, f2 = rng.uniform(0, 6), rng.uniform(-2e4, 2e4), rng.uniform(-5, 5), rng.uniform(-.05, .05)
+        f3 = rng.uniform(-1e-3, 1e-3)
+        c5 = oracle.derived.coefs_from_fit(phi0, f0, f1, f2, f3)
+        f = _fit_from_coefs(c5[:4], 20.0)
+        f.coef[6] = f3
+        t = rng.uniform(-10, 10, size=7)
+        ph, pm, fr, fd = ptk.pt_phase(f, t)
+        assert np.allclose(ph, oracle.derived.phase(c5, t), rtol=1e-13, atol=1e-8)
+        assert np.allclose(fr, oracle.derived.freq_hz(c5, t), rtol=1e-13, atol=1e-10)
+        assert np.allclose(fd, oracle.derived.phase_accel(c5, t) / (2 * math.pi), rtol=1e-12, atol=1e-13)
+        a = ptk.pt_los_accel(f, float(t[0]), 8.4e9)
+        assert a == pytest.approx(float(oracle.derived.los_accel(c5, t[0], 8.4e9)), rel=1e-12, abs=1e-15)
+        # continuity of one quartic split in two blocks
+        p, g0, g1, g2, g3 = synth.shift_truth4(phi0, f0, f1, f2, f3, 20.0)
+        g = _fit_from_coefs(oracle.derived.coefs_from_fit(p, g0, g1, g2), 20.0)
+        g.coef[6] = g3
+        dphi, dfreq = ptk.pt_continuity(f, g)
+        assert abs(dphi) < 1e-6 and abs(dfreq) < 1e-9
+        da = dict(phi0=phi0, f0=f0, f1=f1, f2=f2, f3=f3, t_left=f.t_left, t_right=f.t_right)
+        db = dict(phi0=p, f0=g0, f1=g1, f2=g2, f3=g3, t_left=g.t_left, t_right=g.t_right)
+        wp, wf = oseed.border_continuity(da, db)
+        assert abs(math.remainder(dphi - wp, 2 * math.pi)) < 1e-6 and abs(dfreq - wf) < 1e-9

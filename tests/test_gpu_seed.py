@@ -27,6 +27,7 @@ def _mirror(truth, f0_est):
     t = np.array(truth, dtype=np.float64)
     if t[2] * f0_est < 0:
         t[1:5] = -t[1:5]
+        t[6:] = -t[6:]
     return t
 
 

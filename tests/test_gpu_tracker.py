@@ -61,6 +61,7 @@ def _oriented(truth, f0):
     t = np.array(truth, dtype=np.float64)
     if t[2] * f0 < 0:
         t[1:5] = -t[1:5]
+        t[6:] = -t[6:]
     return t
 
 

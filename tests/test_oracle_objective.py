@@ -85,14 +85,15 @@ def test_linear_phase_dirichlet_closed_form(n, fs, ref):
         assert abs(got - want) <= tol + 1e-15 * want
 
 
-def _simpson_signal(n, fs, ref, A, phi0, f0, f1, f2):
+def _simpson_signal(n, fs, ref, A, phi0, f0, f1, f2, f3=0.0):
     """cos of phi0 + 2 pi * integral_0^t f(u) du, t = (k - ref)/fs, the
-    integral accumulated with Simpson's rule in exact rationals."""
-    F0, F1, F2 = Fraction(f0), Fraction(f1), Fraction(f2)
+    integral accumulated with Simpson's rule in exact rationals (exact for
+    the cubic frequency law f0 + f1 u + f2 u^2/2 + f3 u^3/6)."""
+    F0, F1, F2, F3 = Fraction(f0), Fraction(f1), Fraction(f2), Fraction(f3)
     h = 1 / Fraction(fs)
 
     def f(u):
-        return F0 + F1 * u + F2 * u * u / 2
+        return F0 + F1 * u + F2 * u * u / 2 + F3 * u * u * u / 6
 
     kref = int(ref)
     assert Fraction(ref) == kref
@@ -121,6 +122,35 @@ def test_integrated_frequency_law_vanishes_at_truth():
         y = list(x)
         y[j] *= scale
         assert oracle.chi2(s, fs, ref, y) > 1.0
+
+
+def test_quartic_frequency_law_vanishes_at_truth():
+    # the fourth Taylor order of Sec. 3.2.1: slot 6 is f3 with phase 2 pi f3 t^4 / 24
+    n, fs, ref = 2000, 500.0, 1000.0
+    A, phi0, f0, f1, f2, f3 = 0.8, 2.1, 37.25, 3.5, -1.75, 1.5
+    s = _simpson_signal(n, fs, ref, A, phi0, f0, f1, f2, f3)
+    x = [A, phi0, f0, f1, f2, 0.0, f3]
+    assert oracle.chi2(s, fs, ref, x) < 1e-20
+    for j, scale in [(6, 2.0), (6, 0.0), (6, -1.0), (4, 0.0)]:
+        y = list(x)
+        y[j] *= scale
+        assert oracle.chi2(s, fs, ref, y) > 1.0
+    # the correlation objective sees the same phase
+    xc = list(x)
+    assert oracle.cor(s, fs, ref, xc) < oracle.cor(s, fs, ref, x[:6] + [0.0])
+
+
+def test_quartic_reference_shift_invariance():
+    rng = np.random.default_rng(8)
+    n, fs = 3001, 1000.0
+    s = rng.normal(size=n)
+    phi0, f0, f1, f2, f3 = 0.4, 123.4, 2.0, -0.7, 0.3
+    x1 = [1.3, phi0, f0, f1, f2, 0.0, f3]
+    shifted = synth.shift_truth4(phi0, f0, f1, f2, f3, 0.9)
+    x2 = [1.3, shifted[0], shifted[1], shifted[2], shifted[3], 0.0, shifted[4]]
+    a = oracle.chi2(s, fs, 0.0, x1)
+    b = oracle.chi2(s, fs, 900.0, x2)
+    assert abs(a - b) <= 1e-9 * a
 
 
 def test_reference_shift_invariance():

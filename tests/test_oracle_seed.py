@@ -131,8 +131,8 @@ def _r(**kw):
 
 def test_seed_box_paper_rule_hand_worked():
     lo, hi = seed.seed_box(_r(), "paper", 10.0, 8.0, slope=True)
-    want_lo = [1.8, 0.0, 900.0, -4.4, -150 / math.pi, -0.05]
-    want_hi = [2.2, 2 * math.pi, 1100.0, -3.6, 150 / math.pi, 0.05]
+    want_lo = [1.8, 0.0, 900.0, -4.4, -150 / math.pi, -0.05, 0.0]
+    want_hi = [2.2, 2 * math.pi, 1100.0, -3.6, 150 / math.pi, 0.05, 0.0]
     assert np.allclose(lo, want_lo, rtol=0, atol=1e-12) and np.allclose(hi, want_hi, rtol=0, atol=1e-12)
     # f1 near zero: the printed 10 % would collapse the range; nsig standard errors floor it
     lo, hi = seed.seed_box(_r(f1=0.001), "paper", 10.0, 8.0)
@@ -142,8 +142,8 @@ def test_seed_box_paper_rule_hand_worked():
 
 def test_seed_box_sigma_rule_hand_worked():
     lo, hi = seed.seed_box(_r(), "sigma", 10.0, 8.0)
-    want_lo = [1.8, 0.0, 999.9, -4.03, -0.02, 0.0]
-    want_hi = [2.2, 2 * math.pi, 1000.1, -3.97, 0.06, 0.0]
+    want_lo = [1.8, 0.0, 999.9, -4.03, -0.02, 0.0, 0.0]
+    want_hi = [2.2, 2 * math.pi, 1000.1, -3.97, 0.06, 0.0, 0.0]
     assert np.allclose(lo, want_lo, rtol=0, atol=1e-12) and np.allclose(hi, want_hi, rtol=0, atol=1e-12)
     lo, hi = seed.seed_box(_r(sd_A=0.05), "sigma", 10.0, 8.0)
     assert math.isclose(hi[0] - lo[0], 1.0, rel_tol=1e-12)  # 10 sd_A beats 10 %
