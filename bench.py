@@ -189,6 +189,30 @@ def objective_comparison(ctx, ptk, synth, np, torch, nseeds):
     return res
 
 
+def quartic_fit(ctx, ptk, synth, np, torch):
+    """Perigee-like 20 s block (1e6 samples) with the fourth Taylor order
+    (Sec. 3.2.1): the quartic fit (f3 active) against the cubic one."""
+    b = synth.config_quartic(3)
+    dev = torch.from_numpy(b.samples).cuda()
+    de = ptk.make_settings(pop=b.de.pop, max_gens=b.de.max_gens, F=b.de.F, CR=b.de.CR, seed=b.de.seed)
+    blk = ptk.make_block(dev, b.fs, b.lo, b.hi, ref=b.ref, stream=b.stream)
+    ctx.fit_block(blk, de)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    q = ctx.fit_block(blk, de)
+    dt = time.perf_counter() - t0
+    arith = ARITH_NAME[ptk.pt_ctx_last_arithmetic(ctx.handle)]
+    lo, hi = b.lo.copy(), b.hi.copy()
+    lo[6] = hi[6] = 0.0
+    lo[4], hi[4] = b.truth[4] - 0.05, b.truth[4] + 0.05
+    c = ctx.fit_block(ptk.make_block(dev, b.fs, lo, hi, ref=b.ref, stream=b.stream), de)
+    noise = b.n * b.sigma ** 2
+    return {"workload": "1e6 samples at 50 kHz (20 s), quartic phase, 0 dB; P=40, 2000 generations",
+            "fit_ms": dt * 1e3, "candidate_samples_per_s": b.de.pop * (b.de.max_gens + 1) * b.n / dt,
+            "arithmetic": arith, "f3_truth": float(b.truth[6]), "f3_fit": q.coef[6],
+            "chi2_over_noise": {"quartic": q.objective / noise, "cubic": c.objective / noise}}
+
+
 def cpu_baseline(b, gens, nthreads):
     import numpy as np
 
@@ -226,6 +250,7 @@ def main():
     ap.add_argument("--serve-blocks", type=int, default=160)
     ap.add_argument("--no-objcmp", action="store_true", help="skip the chi-square vs correlation comparison")
     ap.add_argument("--objcmp-seeds", type=int, default=8)
+    ap.add_argument("--no-quartic", action="store_true", help="skip the quartic (perigee) fit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -390,6 +415,12 @@ def main():
         print(f"# objectives: chi2 {objcmp['chi2']['median_gens_to_converge']} gens, "
               f"cor {objcmp['cor']['median_gens_to_converge']} gens", file=sys.stderr, flush=True)
 
+    # ---- fourth Taylor order on a perigee-like block
+    quartic = None
+    if not args.no_quartic:
+        quartic = quartic_fit(ctx, ptk, synth, np, torch)
+        print(f"# quartic: {quartic['fit_ms']:.1f} ms per fit", file=sys.stderr, flush=True)
+
     # ---- CPU oracle baseline (bounded sample of the same fit)
     cpu = None
     if not args.no_cpu:
@@ -440,6 +471,7 @@ def main():
         "batch": batch,
         "serving": serving,
         "objective_comparison": objcmp,
+        "quartic": quartic,
         "cpu_baseline": cpu,
         "paper_context": {"gtx580_fit_s": 6.5, "evaluations": 80000, "block": "~400K samples"},
     }

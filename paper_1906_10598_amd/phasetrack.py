@@ -516,6 +516,16 @@ class Context:
     """Owning wrapper of a pt_ctx handle."""
 
     def __init__(self, device: int = 0):
+        # torch and this library share the process's HIP runtime; torch must
+        # bring up its device state first (when the library initialises the
+        # runtime first, torch afterwards reports no devices)
+        try:
+            import torch
+
+            if torch.cuda.is_available():
+                torch.cuda.init()
+        except ImportError:
+            pass
         self.handle = pt_ctx_create(device)
         self.device = device
 

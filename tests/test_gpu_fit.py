@@ -205,9 +205,9 @@ def test_amplitude_slope_fit_matches_oracle():
     rng = np.random.default_rng(17)
     n, fs = 20_000, 2_000.0
     t = (np.arange(n) - n / 2) / fs
-    x = np.array([0.8, 1.9, 311.25, 0.75, 0.0, 0.06])
+    x = np.array([0.8, 1.9, 311.25, 0.75, 0.0, 0.06, 0.0])
     s = (x[0] + x[5] * t) * np.cos(x[1] + 2 * np.pi * (x[2] * t + x[3] * t * t / 2)) + rng.normal(0, 0.2, n)
-    half = np.array([0.1, np.pi, 0.5, 0.5, 0.0, 0.1])
+    half = np.array([0.1, np.pi, 0.5, 0.5, 0.0, 0.1, 0.0])
     b = synth.Block(s, fs, n / 2, x, x - half, x + half,
                     synth.DESettings(pop=40, max_gens=400, seed=99), 0.2, stream=3, name="slope")
     dev = to_dev(s)

@@ -149,8 +149,8 @@ def _step_track(seed, jump_hz, nblocks=3, n=200_000):
         s, scale = synth.block_from_phase(n, FS, 1.0, phi0, f0, f1, f2, 1 / math.sqrt(2), rng, True, t0=tt)
         p, g0, g1, g2 = synth.shift_truth(phi0, f0, f1, f2, tt + n / 2 / FS)
         a = scale
-        truth = np.array([a, p, g0, g1, g2, 0.0])
-        half = np.array([0.1 * a, math.pi, 0.5, 0.1, 0.01, 0.0])
+        truth = np.array([a, p, g0, g1, g2, 0.0, 0.0])
+        half = np.array([0.1 * a, math.pi, 0.5, 0.1, 0.01, 0.0, 0.0])
         b = synth.Block(s, FS, n / 2, truth, truth - half, truth + half, None, scale / math.sqrt(2),
                         stream=k, name=f"step{k}")
         items.append({"track": 0, "seq": k, "block": b})
