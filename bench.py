@@ -34,7 +34,6 @@ PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector (published, packed)
 #     + square-accumulate FMA.
 FLOP_PER_PAIR = {0: 6 + 1 + 1 + 20 + 2 + 2, 1: 6 + 1 + 1 + 12 + 2 + 2, 2: 6 + 6 + 2 + 2}
 ARITH_NAME = {0: "fp64-per-sample", 1: "mixed", 2: "fp64-phasor"}
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_objective_fp64_paper400k.md")
 KERNEL_SRC = [os.path.join(ROOT, "paper_1906_10598_amd", "csrc", f) for f in ("kernels.h", "device.h")]
 
 
@@ -46,19 +45,27 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def read_traffic():
-    """HBM bytes per objective launch from the committed rocprofv3 summary,
-    or None when the kernel sources changed since the counters were taken."""
+def read_traffic(path, geometry):
+    """HBM bytes per objective launch from a committed rocprofv3 summary of the
+    same kernel (sources hash, workload and geometry), else None."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(path) as f:
             for line in f:
                 if line.startswith("traffic:"):
                     kv = dict(item.split("=", 1) for item in line.split()[1:])
-                    if kv.get("kernel_hash") == kernel_hash() and kv.get("workload") == "paper-400000-fp32":
+                    if (kv.get("kernel_hash") == kernel_hash() and kv.get("workload") == "paper-400000-fp32"
+                            and kv.get("geometry") == "%d,%d" % tuple(geometry)):
                         return float(kv["bytes_per_launch"])
     except (OSError, ValueError, KeyError):
         return None
     return None
+
+
+def traffic_of(name, geometry):
+    """Traffic of the FP64 ("fp64") or mixed objective kernel at `geometry`,
+    from profiles/k_objective_<name>_paper400k_<S>x<C>.md."""
+    return read_traffic(os.path.join(ROOT, "profiles", "k_objective_%s_paper400k_%dx%d.md" % (name, *geometry)),
+                        geometry)
 
 
 def pct(xs, q):
@@ -372,7 +379,7 @@ def main():
                       "achieved": ach, "peak": peak, "arithmetic": ARITH_NAME[arith],
                       "flop_per_candidate_sample": FLOP_PER_PAIR[arith]}
 
-    traffic = read_traffic()
+    traffic = traffic_of("fp64", tiles["fp64"])
 
     # ---- batched fits: 64 uneven blocks, own populations, shared launches
     batch = None
@@ -458,7 +465,8 @@ def main():
                   "geometry": {"samples_per_lane": tiles["mixed"][0], "cand_per_group": tiles["mixed"][1]},
                   "roofline": {"bound": "alu", "achieved": roof["mixed"]["achieved"], "peak": PEAK_FP32_TFLOPS,
                                "unit": "TFLOP/s", "frac": roof["mixed"]["achieved"] / PEAK_FP32_TFLOPS,
-                               "avg_launch_ms": roof["mixed"]["avg_launch_ms"]}},
+                               "avg_launch_ms": roof["mixed"]["avg_launch_ms"],
+                               "traffic": traffic_of("mixed", tiles["mixed"])}},
         "roofline": {"bound": "alu", "achieved": r64["achieved"], "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": r64["achieved"] / PEAK_FP64_TFLOPS, "traffic": traffic,
                      "kernel": "k_objective (FP64, %s)" % r64["arithmetic"], "avg_launch_ms": r64["avg_launch_ms"],

@@ -19,6 +19,7 @@ import csv
 import glob
 import hashlib
 import os
+import re
 import statistics
 import sys
 from collections import defaultdict
@@ -97,8 +98,12 @@ def summarise(root, kernel, command):
     if avg_ns:
         head.append(f"Average duration of the kernel: {avg_ns / 1e3:.3f} us\n")
     if traffic is not None:
+        geo = ""
+        m = re.search(r"k_objective<\w+, (\d+), (\d+)", kernel)
+        if m:
+            geo = f" geometry={m.group(1)},{m.group(2)}"
         head.append(f"traffic: bytes_per_launch={traffic:.0f} kernel_hash={kernel_hash()} "
-                    f"workload=paper-400000-fp32\n")
+                    f"workload=paper-400000-fp32{geo}\n")
     return "\n".join(head + out) + "\n"
 
 
