@@ -437,11 +437,13 @@ int pt_ctx_last_launch(pt_ctx* ctx, int* mode);
 
 /* ---- FP64 objective arithmetic ----
  * PT_FP64_AUTO (default): inside each lane's chunk of S samples the phasor
- *   exp(2 pi i Phi) advances by two complex multiplies per sample from an
- *   exact FP64 anchor (cubic term inside the chunk dropped), whenever that
- *   is exact to 1e-12 turns for the block and box: (S - 1)^3 |f2|max /
- *   (6 fs^3) <= 1e-12 and the chunk's second phase difference is below
- *   1e-2 / (2 pi) turns; otherwise the per-sample path.
+ *   exp(2 pi i Phi) follows from an exact FP64 anchor by a three-term
+ *   recurrence for the linear phase and a first-order correction for the
+ *   quadratic one (six operations per sample), wherever that is accurate to
+ *   2e-11 per sample for the whole box: the dropped cubic and quartic terms
+ *   below 1e-12 turns, the quadratic correction's error below 1e-11, and
+ *   the carrier at least S * 2.2e-4 / (2 pi) of fs away from 0 and fs / 2
+ *   (the recurrence's conditioning); otherwise the per-sample path.
  * PT_FP64_POLY: always the per-sample path (exact reduction of the phase in
  *   turns, degree-10 cosine polynomial). */
 enum { PT_FP64_AUTO = 0, PT_FP64_POLY = 1 };

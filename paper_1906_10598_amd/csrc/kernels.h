@@ -223,16 +223,24 @@ __device__ __forceinline__ double lane_chi2_f64(const double (&sv)[S], const Anc
 }
 
 // ---------------------------------------------------------------------------
-// FP64 phasor lane accumulation.  Within one lane chunk the phase is the
-// quadratic b0 + b1 j + b2 j^2 (turns); the host selects this path only when
-// the dropped cubic term, (S - 1)^3 |b3|, is below 1e-12 turns and the
-// second difference 2 b2 is below 1e-2 / (2 pi) turns for every candidate.
-// z_j = exp(2 pi i Phi(j)) then follows the recurrence z_{j+1} = z_j w_j,
-// w_{j+1} = w_j v with w_0 = exp(2 pi i (b1 + b2)) and v = exp(2 pi i 2 b2):
-// two complex multiplies (8 FMA/MUL) per sample instead of a reduction and
-// a degree-10 cosine.  z_0 and w_0 come from the sine / cosine polynomials
-// of the reduced turns; v from its Taylor series (|angle| <= 1e-2, error
-// below 1e-20).  The recurrence's rounding grows as ~2 S ulp (S <= 32).
+// FP64 phasor lane accumulation.  Within one lane chunk the phase is
+// Phi(j) = b0 + b1 j + b2 j^2 + (b3 j^3 + b4 j^4) turns, j < S.  The host
+// selects this path only where, for every candidate of the box,
+//   (1) the dropped terms (S - 1)^3 |b3| + (S - 1)^4 |b4| stay below 1e-12 turns,
+//   (2) theta = 2 pi b2 (S - 1)^2 satisfies theta^2 / 2 <= 1e-11, and
+//   (3) the local frequency b1 stays at least S * 2.2e-4 / (2 pi) turns away
+//       from 0 and 1/2 (|sin 2 pi b1| >= S * 2.2e-4).
+// Then exp(2 pi i Phi(j)) = u_j g_j with u_j = exp(2 pi i (b0 + b1 j)) and
+// g_j = exp(i theta_j), theta_j = 2 pi b2 j^2:
+//   - both parts of u_j follow the real three-term (Chebyshev) recurrence
+//     u_{j+1} = 2 cos(2 pi b1) u_j - u_{j-1}, one FMA each; its rounding
+//     grows by at most j ulp / |sin 2 pi b1|, held below 1e-12 by (3);
+//   - cos(2 pi Phi(j)) = Re(u_j) cos theta_j - Im(u_j) sin theta_j, taken as
+//     Re(u_j) - Im(u_j) theta_j, whose error theta^2 / 2 is bounded by (2).
+// Six FP64 operations per sample and candidate (two recurrence FMAs, theta,
+// the correction FMA, residual, square-accumulate) instead of a reduction
+// and a degree-10 cosine; u_0 and exp(2 pi i b1) come from the sine / cosine
+// polynomials of exactly reduced turns.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void sincos_turns64(double r, double& c, double& sn) {
     const double u = r * r;
@@ -254,17 +262,19 @@ template <int S, bool TAIL, bool SLOPE, bool COR, int NC>
 __device__ __forceinline__ void lane_rot(const double (&sv)[S], const Anchor* an, const double* amp0,
                                          const double* ad, int valid, double* out) {
     static_assert(kSinDeg64 == kCosDeg64, "sine and cosine tables have one degree");
-    double zr[NC], zi[NC], wr[NC], wi[NC], vr[NC], vi[NC], acc0[NC], acc1[NC];
+    double pr[NC], pi[NC], cr[NC], ci[NC], c2[NC], th[NC], acc0[NC], acc1[NC];
 #pragma unroll
     for (int q = 0; q < NC; ++q) {
-        sincos_turns64(an[q].b0, zr[q], zi[q]);  // b0 is already reduced to [-1/2, 1/2]
-        double d = an[q].b1 + an[q].b2;
-        d -= rint(d);
-        sincos_turns64(d, wr[q], wi[q]);
-        const double x = 12.566370614359172954 * an[q].b2;  // 2 pi (2 b2) radians
-        const double x2 = x * x;
-        vr[q] = __fma_rn(x2, __fma_rn(x2, __fma_rn(x2, -1.0 / 720.0, 1.0 / 24.0), -0.5), 1.0);
-        vi[q] = x * __fma_rn(x2, __fma_rn(x2, __fma_rn(x2, -1.0 / 5040.0, 1.0 / 120.0), -1.0 / 6.0), 1.0);
+        double wr, wi;
+        sincos_turns64(an[q].b0, cr[q], ci[q]);  // u_0; b0 is already reduced to [-1/2, 1/2]
+        double e = an[q].b1;
+        e -= rint(e);
+        sincos_turns64(e, wr, wi);  // exp(2 pi i b1)
+        c2[q] = 2.0 * wr;
+        // u_{-1} = u_0 exp(-2 pi i b1) starts the recurrence
+        pr[q] = __fma_rn(cr[q], wr, ci[q] * wi);
+        pi[q] = __fma_rn(ci[q], wr, -(cr[q] * wi));
+        th[q] = 6.283185307179586477 * an[q].b2;  // radians per j^2
         acc0[q] = 0.0;
         acc1[q] = 0.0;
     }
@@ -272,29 +282,27 @@ __device__ __forceinline__ void lane_rot(const double (&sv)[S], const Anchor* an
     for (int j = 0; j < S; ++j) {
 #pragma unroll
         for (int q = 0; q < NC; ++q) {
+            if (j > 0) {
+                const double nr = __fma_rn(c2[q], cr[q], -pr[q]);
+                const double ni = __fma_rn(c2[q], ci[q], -pi[q]);
+                pr[q] = cr[q];
+                pi[q] = ci[q];
+                cr[q] = nr;
+                ci[q] = ni;
+            }
+            // (Im(u) theta) j^2 with j^2 an immediate, so no per-sample product is hoisted into registers
+            const double zr = j == 0 ? cr[q] : __fma_rn(-(ci[q] * th[q]), (double)(j * j), cr[q]);
             double& acc = (j & 1) ? acc1[q] : acc0[q];
             if constexpr (COR) {
-                const double m = SLOPE ? __fma_rn(ad[q], (double)j, amp0[q]) * zr[q] : zr[q];
+                const double m = SLOPE ? __fma_rn(ad[q], (double)j, amp0[q]) * zr : zr;
                 acc = __fma_rn(sv[j], m, acc);
             } else {
                 const double amp = SLOPE ? __fma_rn(ad[q], (double)j, amp0[q]) : amp0[q];
-                const double rho = __fma_rn(-amp, zr[q], sv[j]);
+                const double rho = __fma_rn(-amp, zr, sv[j]);
                 if (TAIL) {
                     if (j < valid) acc = __fma_rn(rho, rho, acc);
                 } else {
                     acc = (j < 2) ? rho * rho : __fma_rn(rho, rho, acc);
-                }
-            }
-            if (j + 1 < S) {
-                const double nzr = __fma_rn(zr[q], wr[q], -(zi[q] * wi[q]));
-                const double nzi = __fma_rn(zr[q], wi[q], zi[q] * wr[q]);
-                zr[q] = nzr;
-                zi[q] = nzi;
-                if (j + 2 < S) {
-                    const double nwr = __fma_rn(wr[q], vr[q], -(wi[q] * vi[q]));
-                    const double nwi = __fma_rn(wr[q], vi[q], wi[q] * vr[q]);
-                    wr[q] = nwr;
-                    wi[q] = nwi;
                 }
             }
         }
@@ -433,7 +441,12 @@ __device__ __forceinline__ void objective_unit(const BlockDesc* __restrict__ d, 
     __syncthreads();
 
     int c0 = 0;
-    if constexpr (MODE == 2) {
+#ifndef PT_ROT_PAIR
+// 0: one candidate at a time -- 109 VGPRs, four waves per SIMD -- measured
+// faster on MI355X than pairs (187 VGPRs, two waves per SIMD)
+#define PT_ROT_PAIR 0
+#endif
+    if constexpr (MODE == 2 && PT_ROT_PAIR) {
         // phasor path: candidates in pairs (two independent recurrences per lane)
         for (; c0 + 1 < ncand; c0 += 2) {
             const Cand ca = cs[c0], cb = cs[c0 + 1];

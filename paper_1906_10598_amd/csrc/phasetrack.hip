@@ -198,16 +198,33 @@ PersistKernel persistent_kernel(int dtype, Geometry g, int mode, bool slope) {
 // turns when (S - 1)^3 |f2| / (6 fs^3) <= 1e-12 and the chunk's second
 // difference 2 |b2| <= 1e-2 / (2 pi), with b2 = f1 / (2 fs^2) + f2 m / (2 fs^3)
 // over the block's sample offsets |m| <= n + |ref|.
-// The phasor path drops the chunk-local terms b3 j^3 + b4 j^4 (j < S) and
-// needs a small second difference; with |m0| <= span, b3 = a3 + 4 a4 m0,
-// b2 = a2 + 3 a3 m0 + 6 a4 m0^2 (turns per sample^k).
-bool phasor_ok(int spl, double fs, double span, double f1max, double f2max, double f3max) {
+// Validity of the FP64 phasor path (see lane_rot) for every candidate with
+// f0 in [f0lo, f0hi], |f1| <= f1max, |f2| <= f2max, |f3| <= f3max and lane
+// anchors |m0| <= span samples from the reference (turns per sample^k:
+// b3 = a3 + 4 a4 m0, b2 = a2 + 3 a3 m0 + 6 a4 m0^2, b1 = f(t) / fs):
+//   (1) (S - 1)^3 |b3| + (S - 1)^4 |b4| <= 1e-12 turns (dropped terms);
+//   (2) theta^2 / 2 <= 1e-11 with theta = 2 pi |b2| (S - 1)^2 (first-order
+//       quadratic correction);
+//   (3) |sin 2 pi b1| >= S * 2.2e-4 over the block's frequency range
+//       (conditioning of the three-term recurrence).
+bool phasor_ok(int spl, double fs, double span, double f0lo, double f0hi, double f1max, double f2max,
+               double f3max) {
     const double a3 = f2max / (6.0 * fs * fs * fs);
     const double a4 = f3max / (24.0 * fs * fs * fs * fs);
     const double b3 = a3 + 4.0 * a4 * span;
     const double b2 = f1max / (2.0 * fs * fs) + 3.0 * a3 * span + 6.0 * a4 * span * span;
     const double s1 = spl - 1;
-    return s1 * s1 * s1 * (b3 + s1 * a4) <= 1e-12 && 2.0 * b2 <= 1e-2 / (2.0 * M_PI);
+    if (!(s1 * s1 * s1 * (b3 + s1 * a4) <= 1e-12)) return false;
+    const double th = 2.0 * M_PI * b2 * s1 * s1;
+    if (!(0.5 * th * th <= 1e-11)) return false;
+    const double tmax = span / fs;
+    const double dev = f1max * tmax + f2max * tmax * tmax / 2.0 + f3max * tmax * tmax * tmax / 6.0;
+    const double xlo = (f0lo - dev) / fs, xhi = (f0hi + dev) / fs;  // turns per sample
+    if (!(std::isfinite(xlo) && std::isfinite(xhi)) || xhi - xlo > 1e6) return false;
+    const double delta = std::asin(std::min(1.0, spl * 2.2e-4)) / (2.0 * M_PI);
+    // no multiple of 1/2 within delta of [xlo, xhi]
+    const double k0 = std::ceil(2.0 * (xlo - delta));
+    return !(k0 / 2.0 <= xhi + delta);
 }
 
 double box_max(const pt_box& bx, int j) { return std::max(std::fabs(bx.lo[j]), std::fabs(bx.hi[j])); }
@@ -465,7 +482,8 @@ int prepare(pt_ctx* ctx, const pt_block* blocks, int nblk, const pt_de_settings*
         for (int b = 0; b < nblk && ok; ++b) {
             const pt_box& bx = blocks[b].box;
             const double span = (double)blocks[b].n + std::fabs(block_ref(&blocks[b]));
-            ok = phasor_ok(pl->geo.spl, blocks[b].fs, span, box_max(bx, 3), box_max(bx, 4), box_max(bx, 6));
+            ok = phasor_ok(pl->geo.spl, blocks[b].fs, span, bx.lo[2], bx.hi[2], box_max(bx, 3), box_max(bx, 4),
+                           box_max(bx, 6));
         }
         if (ok) pl->mode = kModePhasor;
     }
@@ -796,7 +814,7 @@ static int eval_setup(pt_ctx* ctx, const pt_block* block, const double* pop, int
     HIPCHK(hipMemcpyAsync(hp.data(), pop, hp.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     pt_block blk = *block;
-    double f1 = 0.0, f2 = 0.0, f3 = 0.0;
+    double f1 = 0.0, f2 = 0.0, f3 = 0.0, f0lo = INFINITY, f0hi = -INFINITY;
     for (int j : {5, 6}) {
         double lo = 0.0, hi = 0.0;
         for (int p = 0; p < P; ++p) {
@@ -811,6 +829,8 @@ static int eval_setup(pt_ctx* ctx, const pt_block* block, const double* pop, int
         blk.box.hi[j] = std::isfinite(hi) ? hi : 1.0;
     }
     for (int p = 0; p < P; ++p) {
+        f0lo = std::min(f0lo, hp[(size_t)p * PT_NSLOT + 2]);
+        f0hi = std::max(f0hi, hp[(size_t)p * PT_NSLOT + 2]);
         f1 = std::max(f1, std::fabs(hp[(size_t)p * PT_NSLOT + 3]));
         f2 = std::max(f2, std::fabs(hp[(size_t)p * PT_NSLOT + 4]));
         f3 = std::max(f3, std::fabs(hp[(size_t)p * PT_NSLOT + 6]));
@@ -832,7 +852,7 @@ static int eval_setup(pt_ctx* ctx, const pt_block* block, const double* pop, int
     if (!pl->mixed && ctx->fp64_method != PT_FP64_POLY) {
         const double span = (double)block->n + std::fabs(block_ref(block));
         pl->mode = std::isfinite(f1) && std::isfinite(f2) && std::isfinite(f3) &&
-                           phasor_ok(pl->geo.spl, block->fs, span, f1, f2, f3)
+                           phasor_ok(pl->geo.spl, block->fs, span, f0lo, f0hi, f1, f2, f3)
                        ? kModePhasor
                        : kModePoly;
     }
@@ -1358,7 +1378,8 @@ int slot_mode(const pt_server* sv, const pt_block& b) {
     if (sv->cfg.de.precision == PT_PREC_MIXED) return kModeMixed;
     if (sv->ctx->fp64_method == PT_FP64_POLY) return kModePoly;
     const double span = (double)b.n + std::fabs(b.ref);
-    return phasor_ok(sv->geo.spl, b.fs, span, box_max(b.box, 3), box_max(b.box, 4), box_max(b.box, 6))
+    return phasor_ok(sv->geo.spl, b.fs, span, b.box.lo[2], b.box.hi[2], box_max(b.box, 3), box_max(b.box, 4),
+                     box_max(b.box, 6))
                ? kModePhasor
                : kModePoly;
 }

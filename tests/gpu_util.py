@@ -48,11 +48,13 @@ def phase_rounding_bound(s, pop, fs, ref):
     return 8 * phi_max * 2.0 ** -53, np.abs(pop[:, 0])
 
 
-# Per-sample phase error [rad] of the FP64 arithmetics beyond the phase
-# rounding: the per-sample cosine path ~1e-16 turns; the phasor path drops the
-# cubic term inside a lane's chunk only where that term stays below 1e-12
-# turns, plus its recurrence rounding.
-MODEL_PHASE_ERR = {ptk.PT_ARITH_FP64_POLY: 1e-13, ptk.PT_ARITH_FP64_PHASOR: 2 * math.pi * 1e-12 + 1e-13}
+# Per-sample error of the model cosine [relative to A, or rad of phase] of the
+# FP64 arithmetics beyond the phase rounding: the per-sample cosine path
+# ~1e-16 turns; the phasor path is used only where its dropped terms stay
+# below 1e-12 turns, its quadratic correction below 1e-11 and its recurrence
+# rounding below 1e-12.
+MODEL_PHASE_ERR = {ptk.PT_ARITH_FP64_POLY: 1e-13,
+                   ptk.PT_ARITH_FP64_PHASOR: 2 * math.pi * 1e-12 + 1e-11 + 1e-12 + 1e-13}
 
 
 def model_phase_err(c=None):
