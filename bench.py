@@ -249,6 +249,8 @@ def main():
                     help="profiling mode: one fit, then --reps back-to-back objective launches; "
                          "also one 256 MiB device copy as the traffic-counter calibration")
     ap.add_argument("--reps", type=int, default=200)
+    ap.add_argument("--launch", default="auto", choices=["auto", "graph", "persistent"],
+                    help="launch strategy of the fits (pt_ctx_set_launch_mode)")
     ap.add_argument("--fit-only", action="store_true",
                     help="profiling mode: --warmup + --steps fits of the paper-scale block (FP64, default "
                          "launch form), then one JSON line with the fit times")
@@ -313,10 +315,12 @@ def main():
         return lambda k: ptk.make_settings(pop=P, max_gens=G, F=b.de.F, CR=b.de.CR, seed=b.de.seed + k,
                                            precision=prec)
 
+    ptk.pt_ctx_set_launch_mode(ctx.handle, {"auto": ptk.PT_LAUNCH_AUTO, "graph": ptk.PT_LAUNCH_GRAPH,
+                                            "persistent": ptk.PT_LAUNCH_PERSISTENT}[args.launch])
     if args.fit_only:
         run_fits(ctx, blk, de(ptk.PT_PREC_FP64), args.warmup, "warmup")
         el, lat, _ = run_fits(ctx, blk, de(ptk.PT_PREC_FP64), args.steps, "fp64")
-        print(json.dumps({"fit_only": True, "fits": args.steps, "ms_per_fit": el / args.steps * 1e3,
+        print(json.dumps({"fit_only": True, "launch": args.launch, "fits": args.steps, "ms_per_fit": el / args.steps * 1e3,
                           "p50_ms": pct(lat, 50), "geometry": tiles["fp64"],
                           "arithmetic": ARITH_NAME[ptk.pt_ctx_last_arithmetic(ctx.handle)],
                           "kernel_hash": kernel_hash()}), flush=True)

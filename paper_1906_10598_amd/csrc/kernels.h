@@ -59,6 +59,17 @@ __device__ __forceinline__ double xld(const double* p) {
     return *p;
 #endif
 }
+// Load of a word another launch wrote (COH = false: plain, cacheable; kernel
+// boundaries order it) or that another workgroup of this launch may write
+// (COH = true: xld).
+template <bool COH>
+__device__ __forceinline__ double ld(const double* p) {
+    if constexpr (COH)
+        return xld(p);
+    else
+        return *p;
+}
+
 __device__ __forceinline__ void xst(double* p, double v) {
 #if PT_SYNC_VARIANT >= 2
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -97,16 +108,17 @@ struct Cand {
     double a0, a1, a2, a3, a4, A, Ad;  // Ad = Adot / fs: amplitude slope per sample
 };
 
+template <bool COH>
 __device__ __forceinline__ Cand make_cand(const double* x, double fs) {
     Cand c;
-    const double t = xld(x + 1) * 0.15915494309189533577;  // phi0 / (2 pi)
+    const double t = ld<COH>(x + 1) * 0.15915494309189533577;  // phi0 / (2 pi)
     c.a0 = t - rint(t);
-    c.a1 = xld(x + 2) / fs;
-    c.a2 = xld(x + 3) / (2.0 * fs * fs);
-    c.a3 = xld(x + 4) / (6.0 * fs * fs * fs);
-    c.A = xld(x + 0);
-    c.Ad = xld(x + 5) / fs;
-    c.a4 = xld(x + 6) / (24.0 * fs * fs * fs * fs);
+    c.a1 = ld<COH>(x + 2) / fs;
+    c.a2 = ld<COH>(x + 3) / (2.0 * fs * fs);
+    c.a3 = ld<COH>(x + 4) / (6.0 * fs * fs * fs);
+    c.A = ld<COH>(x + 0);
+    c.Ad = ld<COH>(x + 5) / fs;
+    c.a4 = ld<COH>(x + 6) / (24.0 * fs * fs * fs * fs);
     return c;
 }
 
@@ -426,8 +438,9 @@ __device__ __forceinline__ double lane_sum(const V (&sv)[S], const Anchor& an, d
 }
 
 // MODE: 0 = FP64 with per-sample cosine polynomial, 1 = mixed precision,
-// 2 = FP64 phasor recurrence.
-template <int S, int CPG, int MODE, bool SLOPE, typename V>
+// 2 = FP64 phasor recurrence.  COH: the trial rows may be written inside the
+// launch (persistent kernel).
+template <int S, int CPG, int MODE, bool SLOPE, bool COH = false, typename V>
 __device__ __forceinline__ void objective_unit(const BlockDesc* __restrict__ d, int tile, int group,
                                                const V (&sv)[S], bool full, int valid, Cand* cs,
                                                double (*red)[kThreads]) {
@@ -436,7 +449,7 @@ __device__ __forceinline__ void objective_unit(const BlockDesc* __restrict__ d, 
     const int tid = threadIdx.x;
     const bool cor = d->objective != 0;
     const bool quart = d->quartic != 0;
-    if (tid < ncand) cs[tid] = make_cand(d->trial + (size_t)(cbase + tid) * kStride, d->fs);
+    if (tid < ncand) cs[tid] = make_cand<COH>(d->trial + (size_t)(cbase + tid) * kStride, d->fs);
     const double m0 = (double)((int64_t)tile * (kThreads * S) + (int64_t)tid * S) - d->ref;
     __syncthreads();
 
@@ -505,6 +518,7 @@ __device__ __forceinline__ void objective_unit(const BlockDesc* __restrict__ d, 
 // bit-identical sums.  red: NT doubles of LDS.  Returns the objective of
 // candidate threadIdx.x (meaningful for threadIdx.x < P) after a barrier.
 // ---------------------------------------------------------------------------
+template <bool COH>
 __device__ __forceinline__ double reduce_partials(const BlockDesc* __restrict__ d, double* red) {
     const int P = d->P, T = d->ntiles, NT = blockDim.x, t = threadIdx.x;
     const int k = NT >= P ? NT / P : 1;
@@ -519,7 +533,7 @@ __device__ __forceinline__ double reduce_partials(const BlockDesc* __restrict__ 
         for (int base = 0; base < cnt; base += kB) {
             double v[kB];
 #pragma unroll
-            for (int q = 0; q < kB; ++q) v[q] = base + q < cnt ? xld(pr + (size_t)(base + q) * k) : 0.0;
+            for (int q = 0; q < kB; ++q) v[q] = base + q < cnt ? ld<COH>(pr + (size_t)(base + q) * k) : 0.0;
 #pragma unroll
             for (int q = 0; q < kB; ++q)
                 if (base + q < cnt) s += v[q];
@@ -541,7 +555,7 @@ __device__ __forceinline__ double reduce_partials(const BlockDesc* __restrict__ 
 __global__ void k_reduce_out(const BlockDesc* __restrict__ descs, double* __restrict__ out) {
     extern __shared__ double red[];
     const BlockDesc* d = descs;
-    const double v = reduce_partials(d, red);
+    const double v = reduce_partials<false>(d, red);
     if ((int)threadIdx.x < d->P) out[threadIdx.x] = v;
 }
 
@@ -610,6 +624,9 @@ __device__ __forceinline__ bool better(double fa, int ia, double fb, int ib) {
 // Member rows and the state are fetched before the reduction so their
 // latency overlaps it.  Dynamic LDS: P * kSlots + 2 NT doubles + NT ints.
 // ---------------------------------------------------------------------------
+// ROWS_COH: population rows and DE state may be written inside the launch
+// (persistent kernel); PART_COH: the partial sums may (fused or persistent).
+template <bool ROWS_COH, bool PART_COH>
 __device__ __forceinline__ void de_step_body(const BlockDesc* __restrict__ d, double* lds) {
     DeState* st = d->st;
     const int P = d->P, NT = blockDim.x, i = threadIdx.x;
@@ -626,10 +643,10 @@ __device__ __forceinline__ void de_step_body(const BlockDesc* __restrict__ d, do
         const double* b = d->pop + (size_t)i * kStride;
 #pragma unroll
         for (int j = 0; j < kSlots; ++j) {
-            tr[j] = xld(a + j);
-            po[j] = xld(b + j);
+            tr[j] = ld<ROWS_COH>(a + j);
+            po[j] = ld<ROWS_COH>(b + j);
         }
-        fo = xld(d->fpop + i);
+        fo = ld<ROWS_COH>(d->fpop + i);
     }
     if (i == 0) {
         // Atomic (vector, agent-scope) loads: inside the persistent kernel these
@@ -642,7 +659,7 @@ __device__ __forceinline__ void de_step_body(const BlockDesc* __restrict__ d, do
                     ? __hip_atomic_load(d->hist + (g0 - d->window), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
                     : 0.0;
     }
-    const double ft = reduce_partials(d, red);  // contains a barrier
+    const double ft = reduce_partials<PART_COH>(d, red);  // contains a barrier
     if (s_done) return;
     const int g = s_gen;
 
@@ -765,7 +782,7 @@ __device__ __forceinline__ void de_step_body(const BlockDesc* __restrict__ d, do
 
 __global__ __launch_bounds__(1024) void k_de_step(const BlockDesc* __restrict__ descs) {
     extern __shared__ double lds[];
-    de_step_body(descs + blockIdx.x, lds);
+    de_step_body<false, false>(descs + blockIdx.x, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -865,6 +882,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 4))
     int* sync = d->sync;
     const int xcd = bid & 7;
     __syncthreads();  // every wave's partial stores are issued
+    // (one counter per block instead of per XCD range: fits 30 % slower on MI355X,
+    // the same-address atomics from all XCDs serialise)
     if (threadIdx.x == 0) {
         const int nx = units_in_range(d, xcd, Ux, total_units);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, PT_REL_SCOPE);
@@ -885,7 +904,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 4))
     __syncthreads();
     if (!s_last) return;
     extern __shared__ double de_lds[];
-    de_step_body(d, de_lds);
+    de_step_body<false, true>(d, de_lds);
     __syncthreads();
     if (threadIdx.x < 8) __hip_atomic_store(sync + threadIdx.x * kSyncLine, 0, __ATOMIC_RELAXED,
                                             __HIP_MEMORY_SCOPE_AGENT);
@@ -940,7 +959,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 4))
             if (s_done) continue;
             any = true;
             if (!resident) load_lane<V, T, S>(d, tile, sv, full, valid);
-            objective_unit<S, CPG, MODE, SLOPE>(d, tile, group, sv, full, valid, cs, red);
+            objective_unit<S, CPG, MODE, SLOPE, true>(d, tile, group, sv, full, valid, cs, red);
             // The workgroup barrier makes every wave's partial stores visible
             // at the XCD's L2; one release fence then publishes them device-wide
             // before the arrival is counted.  Arrivals are counted per XCD
@@ -968,7 +987,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 4))
             }
             __syncthreads();
             if (s_last) {
-                de_step_body(d, lds);
+                de_step_body<true, true>(d, lds);
                 __syncthreads();
                 if (threadIdx.x == 0) {
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, PT_REL_SCOPE);
