@@ -251,6 +251,8 @@ def main():
     ap.add_argument("--reps", type=int, default=200)
     ap.add_argument("--launch", default="auto", choices=["auto", "graph", "persistent"],
                     help="launch strategy of the fits (pt_ctx_set_launch_mode)")
+    ap.add_argument("--fusion", default="lead", choices=["lead", "last", "off"],
+                    help="where a graph-launched fit runs its DE step (pt_ctx_set_step_fusion)")
     ap.add_argument("--fit-only", action="store_true",
                     help="profiling mode: --warmup + --steps fits of the paper-scale block (FP64, default "
                          "launch form), then one JSON line with the fit times")
@@ -294,10 +296,10 @@ def main():
         prec = ptk.PT_PREC_FP64 if args.kernel_only == "fp64" else ptk.PT_PREC_MIXED
         # two-launch generations here, so every k_objective launch of this run is
         # the bare objective the roofline times
-        ptk.pt_ctx_set_step_fusion(ctx.handle, False)
+        ptk.pt_ctx_set_step_fusion(ctx.handle, ptk.PT_FUSION_OFF)
         ctx.fit_block(blk, ptk.make_settings(pop=P, max_gens=G, F=b.de.F, CR=b.de.CR, seed=b.de.seed,
                                              precision=prec))
-        ptk.pt_ctx_set_step_fusion(ctx.handle, True)
+        ptk.pt_ctx_set_step_fusion(ctx.handle, ptk.PT_FUSION_LEAD)
         pop, _ = ptk.pt_last_population(ctx.handle, 0, P)
         popd = torch.from_numpy(pop).cuda()
         avg_ms = ptk.pt_time_objective(ctx.handle, blk, popd.data_ptr(), P, prec, args.reps, stream)
@@ -317,10 +319,13 @@ def main():
 
     ptk.pt_ctx_set_launch_mode(ctx.handle, {"auto": ptk.PT_LAUNCH_AUTO, "graph": ptk.PT_LAUNCH_GRAPH,
                                             "persistent": ptk.PT_LAUNCH_PERSISTENT}[args.launch])
+    ptk.pt_ctx_set_step_fusion(ctx.handle, {"lead": ptk.PT_FUSION_LEAD, "last": ptk.PT_FUSION_LAST,
+                                            "off": ptk.PT_FUSION_OFF}[args.fusion])
     if args.fit_only:
         run_fits(ctx, blk, de(ptk.PT_PREC_FP64), args.warmup, "warmup")
         el, lat, _ = run_fits(ctx, blk, de(ptk.PT_PREC_FP64), args.steps, "fp64")
-        print(json.dumps({"fit_only": True, "launch": args.launch, "fits": args.steps, "ms_per_fit": el / args.steps * 1e3,
+        print(json.dumps({"fit_only": True, "launch": args.launch, "fusion": args.fusion, "fits": args.steps,
+                          "ms_per_fit": el / args.steps * 1e3,
                           "p50_ms": pct(lat, 50), "geometry": tiles["fp64"],
                           "arithmetic": ARITH_NAME[ptk.pt_ctx_last_arithmetic(ctx.handle)],
                           "kernel_hash": kernel_hash()}), flush=True)

@@ -451,11 +451,23 @@ enum { PT_FP64_AUTO = 0, PT_FP64_POLY = 1 };
 int pt_ctx_set_fp64_method(pt_ctx* ctx, int method);
 
 /* ---- step fusion ----
- * 1 (default): for P <= 256 each generation is one launch -- the DE step of
- *   a block runs in the objective workgroup that finishes the block's last
- *   work unit (arrival counters, no waiting).  0: objective and DE step as
- *   two launches.  Both give bit-identical fits. */
-int pt_ctx_set_step_fusion(pt_ctx* ctx, int on);
+ * How a fit's generations map onto launches (graph-replayed fits; the DE
+ * step is that of Table 4, DE/rand/1/bin, in every form):
+ * PT_FUSION_LEAD (default, P <= 256): one launch per generation.  Every
+ *   objective workgroup first repeats the previous generation's DE step for
+ *   itself (objectives of all P trials from the tile partials, selection,
+ *   best member, stop rule) and draws the trials of its own candidates; the
+ *   workgroup of the block's first work unit stores the step.  Nothing waits
+ *   and nothing is read in the launch that writes it (two buffer slots
+ *   alternate by launch parity).  One extra launch runs the last step.
+ * PT_FUSION_LAST (P <= 256): one launch per generation; the DE step runs
+ *   once, in the objective workgroup that finishes the block's last work
+ *   unit (arrival counters, no waiting).
+ * PT_FUSION_OFF: objective and DE step as two launches.
+ * All three give bit-identical fits.  Returns PT_EINVAL for another value. */
+enum { PT_FUSION_OFF = 0, PT_FUSION_LEAD = 1, PT_FUSION_LAST = 2 };
+
+int pt_ctx_set_step_fusion(pt_ctx* ctx, int mode);
 
 /* Objective arithmetic of the context's most recent fit or objective
  * evaluation: per-sample FP64 cosine, mixed precision, or FP64 phasor. */

@@ -25,13 +25,18 @@ constexpr int kMaxCpg = 8;       // largest candidates-per-workgroup instantiate
 
 // Per-block DE state, written only by the DE kernels.
 struct DeState {
-    int gen;       // generation of the population in `trial` (0 = initial)
+    int gen;       // generation of the population in `trial` (0 = initial); leading-step form:
+                   // the generation the launch reading this slot evaluates; at a stop, the last
+                   // generation selected
     int done;      // nonzero once the stop rule has fired
     int flags;     // PT_FLAG_* bits
     int best;      // index of the best member
     double best_f;
     int arrive;    // persistent kernel: work units finished, all generations
     int ready;     // persistent kernel: DE steps completed (trial of `ready` is set)
+    int slot;      // population slot (0: pop / fpop, 1: pop2 / fpop2) of the selected population
+    int pad;
+    double old;    // leading-step form: best-so-far value the window rule of the next step compares with
 };
 
 // Everything a kernel needs to know about one block of a launch.
@@ -66,6 +71,16 @@ struct BlockDesc {
     int objective;     // 0 = chi-square (Eq. 2-2-4), 1 = correlation (Eq. 2-2-5)
     int quartic;       // nonzero: the phase has the fourth-order term f3 (slot 6)
     int pad2;
+    // Leading-step launches (k_objective with fused >= 2) alternate between two
+    // copies of the DE buffers: launch parity p reads the state of slot p and
+    // the rows, objectives and partials of slot p ^ 1, and writes the others.
+    // Slot 0 is pop / trial / fpop / partials / st, slot 1 these; null when
+    // the fit does not use that form.
+    double* pop2;
+    double* trial2;
+    double* fpop2;
+    double* partials2;
+    DeState* st2;
 };
 
 // Persistent-kernel synchronisation words of one block, one 128-byte line each:

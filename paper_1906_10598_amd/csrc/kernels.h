@@ -52,11 +52,25 @@ namespace pt {
 #define PT_REL_SCOPE "agent"
 #endif
 
+// Every buffer a kernel reaches through a descriptor is device (global)
+// memory; accessing it through global-space pointers gives global_load /
+// global_store instead of flat accesses, which also count against the LDS
+// counter, so a wait for an LDS or scalar access would wait for them too.
+#define PT_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ T gld(const T* p) {
+    return *(const PT_GLOBAL T*)p;
+}
+template <typename T>
+__device__ __forceinline__ void gst(T* p, T v) {
+    *(PT_GLOBAL T*)p = v;
+}
+
 __device__ __forceinline__ double xld(const double* p) {
 #if PT_SYNC_VARIANT >= 1
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load((const PT_GLOBAL double*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 #else
-    return *p;
+    return gld(p);
 #endif
 }
 // Load of a word another launch wrote (COH = false: plain, cacheable; kernel
@@ -67,21 +81,21 @@ __device__ __forceinline__ double ld(const double* p) {
     if constexpr (COH)
         return xld(p);
     else
-        return *p;
+        return gld(p);
 }
 
 __device__ __forceinline__ void xst(double* p, double v) {
 #if PT_SYNC_VARIANT >= 2
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store((PT_GLOBAL double*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 #else
-    *p = v;
+    gst(p, v);
 #endif
 }
 __device__ __forceinline__ void xsti(int* p, int v) {
 #if PT_SYNC_VARIANT >= 2
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store((PT_GLOBAL int*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 #else
-    *p = v;
+    gst(p, v);
 #endif
 }
 
@@ -108,17 +122,41 @@ struct Cand {
     double a0, a1, a2, a3, a4, A, Ad;  // Ad = Adot / fs: amplitude slope per sample
 };
 
+// Turn-domain value of population slot j (coefficient x): A; phi0 / 2 pi
+// reduced to [-1/2, 1/2]; f0 / fs; f1 / (2 fs^2); f2 / (6 fs^3); Adot / fs;
+// f3 / (24 fs^4).  One division serves every slot (slots 0 and 1 divide by
+// 1); no contraction, so every caller rounds alike.
+__device__ __forceinline__ double cand_value(int j, double x, double fs) {
+#pragma clang fp contract(off)
+    double den = 1.0;
+    if (j == 2 || j == 5) den = fs;
+    if (j == 3) den = 2.0 * fs * fs;
+    if (j == 4) den = 6.0 * fs * fs * fs;
+    if (j == 6) den = 24.0 * fs * fs * fs * fs;
+    double q = x / den;
+    if (j == 1) {
+        const double t = x * 0.15915494309189533577;
+        q = t - rint(t);
+    }
+    return q;
+}
+// Cand member written by slot j
+__device__ __forceinline__ double& cand_member(Cand& c, int j) {
+    double* m = &c.a0;  // a0, a1, a2, a3, a4, A, Ad
+    constexpr unsigned kIdx = 5u | (0u << 3) | (1u << 6) | (2u << 9) | (3u << 12) | (6u << 15) | (4u << 18);
+    return m[(kIdx >> (3 * j)) & 7u];
+}
+
 template <bool COH>
 __device__ __forceinline__ Cand make_cand(const double* x, double fs) {
     Cand c;
-    const double t = ld<COH>(x + 1) * 0.15915494309189533577;  // phi0 / (2 pi)
-    c.a0 = t - rint(t);
-    c.a1 = ld<COH>(x + 2) / fs;
-    c.a2 = ld<COH>(x + 3) / (2.0 * fs * fs);
-    c.a3 = ld<COH>(x + 4) / (6.0 * fs * fs * fs);
-    c.A = ld<COH>(x + 0);
-    c.Ad = ld<COH>(x + 5) / fs;
-    c.a4 = ld<COH>(x + 6) / (24.0 * fs * fs * fs * fs);
+    c.A = cand_value(0, ld<COH>(x + 0), fs);
+    c.a0 = cand_value(1, ld<COH>(x + 1), fs);
+    c.a1 = cand_value(2, ld<COH>(x + 2), fs);
+    c.a2 = cand_value(3, ld<COH>(x + 3), fs);
+    c.a3 = cand_value(4, ld<COH>(x + 4), fs);
+    c.Ad = cand_value(5, ld<COH>(x + 5), fs);
+    c.a4 = cand_value(6, ld<COH>(x + 6), fs);
     return c;
 }
 
@@ -400,24 +438,65 @@ __device__ __forceinline__ float lane_chi2_mixed(const float (&sv)[S], const Anc
 // MODE: arithmetic (see objective_unit); SLOPE: amplitude slope active.  sv holds the
 // lane's samples (loaded by load_lane); cs / red are LDS scratch.
 // ---------------------------------------------------------------------------
+// The loads are branch-free: every lane reads S / G 16-byte groups (G
+// samples each) at start indices clamped to [0, n - G] (n >= 8 >= G), so
+// every address is in range and no load waits for another at a branch.
+// Only a lane reaching past the last sample sees clamped data; finish_lane
+// shifts its group into place and zeroes what lies past the end.
+template <typename T, int S>
+__device__ __forceinline__ void load_lane_raw(const BlockDesc* __restrict__ d, int tile, T (&w)[S]) {
+    constexpr int G = 16 / (int)sizeof(T);
+    static_assert(S % G == 0, "samples per lane must be a multiple of a 16-byte group");
+    typedef T group_t __attribute__((ext_vector_type(G), aligned(sizeof(T))));
+    const int64_t n = d->n;
+    const int64_t n0 = (int64_t)tile * (kThreads * S) + (int64_t)threadIdx.x * S;
+    const T* __restrict__ sp = static_cast<const T*>(d->samples);
+#pragma unroll
+    for (int g = 0; g < S / G; ++g) {
+        const int64_t b = min(n0 + G * g, n - G);
+        const group_t x = *(const PT_GLOBAL group_t*)(sp + b);
+#pragma unroll
+        for (int e = 0; e < G; ++e) w[G * g + e] = x[e];
+    }
+}
+
+// sv from the raw groups; full: the whole tile lies inside the block;
+// valid: samples of this lane inside the block (S when full).
 template <typename V, typename T, int S>
-__device__ __forceinline__ void load_lane(const BlockDesc* __restrict__ d, int tile, V (&sv)[S], bool& full,
-                                          int& valid) {
+__device__ __forceinline__ void finish_lane(const BlockDesc* __restrict__ d, int tile, const T (&w)[S],
+                                            V (&sv)[S], bool& full, int& valid) {
+    constexpr int G = 16 / (int)sizeof(T);
     const int64_t n = d->n;
     const int64_t tile0 = (int64_t)tile * (kThreads * S);
     const int64_t n0 = tile0 + (int64_t)threadIdx.x * S;
     full = tile0 + kThreads * S <= n;
-    const T* __restrict__ sp = static_cast<const T*>(d->samples);
-    valid = S;
-    if (full) {
 #pragma unroll
-        for (int j = 0; j < S; ++j) sv[j] = (V)sp[n0 + j];
-    } else {
+    for (int j = 0; j < S; ++j) sv[j] = (V)w[j];
+    valid = S;
+    if (!full) {
         const int64_t rem = n - n0;
         valid = rem <= 0 ? 0 : (rem >= S ? S : (int)rem);
 #pragma unroll
-        for (int j = 0; j < S; ++j) sv[j] = j < valid ? (V)sp[n0 + j] : (V)0;
+        for (int g = 0; g < S / G; ++g) {
+            const int64_t s0 = n0 + G * g;
+            const int64_t sh = s0 - min(s0, n - G);  // where the group's first sample landed
+#pragma unroll
+            for (int e = 0; e < G; ++e) {
+                T x = w[G * g + e];
+#pragma unroll
+                for (int t = 1; e + t < G; ++t) x = sh == t ? w[G * g + e + t] : x;
+                sv[G * g + e] = s0 + e < n ? (V)x : (V)0;
+            }
+        }
     }
+}
+
+template <typename V, typename T, int S>
+__device__ __forceinline__ void load_lane(const BlockDesc* __restrict__ d, int tile, V (&sv)[S], bool& full,
+                                          int& valid) {
+    T w[S];
+    load_lane_raw<T, S>(d, tile, w);
+    finish_lane<V, T, S>(d, tile, w, sv, full, valid);
 }
 
 // Lane sum of the per-sample paths (MODE 0 FP64, 1 mixed) for one candidate:
@@ -439,19 +518,23 @@ __device__ __forceinline__ double lane_sum(const V (&sv)[S], const Anchor& an, d
 
 // MODE: 0 = FP64 with per-sample cosine polynomial, 1 = mixed precision,
 // 2 = FP64 phasor recurrence.  COH: the trial rows may be written inside the
-// launch (persistent kernel).
+// launch (persistent kernel).  trows: the population rows to evaluate, or
+// null when the caller has already put the group's candidates into cs (and
+// passed a barrier); part: the partial sums to write.
 template <int S, int CPG, int MODE, bool SLOPE, bool COH = false, typename V>
 __device__ __forceinline__ void objective_unit(const BlockDesc* __restrict__ d, int tile, int group,
                                                const V (&sv)[S], bool full, int valid, Cand* cs,
-                                               double (*red)[kThreads]) {
+                                               double (*red)[kThreads], const double* trows, double* part) {
     const int cbase = group * CPG;
     const int ncand = min(CPG, d->P - cbase);
     const int tid = threadIdx.x;
     const bool cor = d->objective != 0;
     const bool quart = d->quartic != 0;
-    if (tid < ncand) cs[tid] = make_cand<COH>(d->trial + (size_t)(cbase + tid) * kStride, d->fs);
     const double m0 = (double)((int64_t)tile * (kThreads * S) + (int64_t)tid * S) - d->ref;
-    __syncthreads();
+    if (trows != nullptr) {
+        if (tid < ncand) cs[tid] = make_cand<COH>(trows + (size_t)(cbase + tid) * kStride, d->fs);
+        __syncthreads();
+    }
 
     int c0 = 0;
 #ifndef PT_ROT_PAIR
@@ -504,7 +587,7 @@ __device__ __forceinline__ void objective_unit(const BlockDesc* __restrict__ d, 
     for (int c = wave; c < ncand; c += kThreads / 64) {
         double v = ((red[c][lane] + red[c][lane + 64]) + red[c][lane + 128]) + red[c][lane + 192];
         v = wave_sum(v);
-        if (lane == 0) xst(d->partials + (size_t)(cbase + c) * d->ntiles + tile, v);
+        if (lane == 0) xst(part + (size_t)(cbase + c) * d->ntiles + tile, v);
     }
 }
 
@@ -518,18 +601,18 @@ __device__ __forceinline__ void objective_unit(const BlockDesc* __restrict__ d, 
 // bit-identical sums.  red: NT doubles of LDS.  Returns the objective of
 // candidate threadIdx.x (meaningful for threadIdx.x < P) after a barrier.
 // ---------------------------------------------------------------------------
-template <bool COH>
-__device__ __forceinline__ double reduce_partials(const BlockDesc* __restrict__ d, double* red) {
+template <bool COH, int kB = 32>
+__device__ __forceinline__ double reduce_partials(const BlockDesc* __restrict__ d, const double* partials,
+                                                  double* red) {
     const int P = d->P, T = d->ntiles, NT = blockDim.x, t = threadIdx.x;
     const int k = NT >= P ? NT / P : 1;
     if (t < P * k) {
         const int c = t / k, part = t - c * k;
-        const double* pr = d->partials + (size_t)c * T + part;
+        const double* pr = partials + (size_t)c * T + part;
         const int cnt = part < T ? (T - part + k - 1) / k : 0;  // tiles part, part + k, ... < T
         double s = 0.0;
-        // batches of 32 loads in flight (one memory round trip per batch), then
+        // batches of kB loads in flight (one memory round trip per batch), then
         // added one by one in tile order
-        constexpr int kB = 32;
         for (int base = 0; base < cnt; base += kB) {
             double v[kB];
 #pragma unroll
@@ -555,7 +638,7 @@ __device__ __forceinline__ double reduce_partials(const BlockDesc* __restrict__ 
 __global__ void k_reduce_out(const BlockDesc* __restrict__ descs, double* __restrict__ out) {
     extern __shared__ double red[];
     const BlockDesc* d = descs;
-    const double v = reduce_partials<false>(d, red);
+    const double v = reduce_partials<false>(d, d->partials, red);
     if ((int)threadIdx.x < d->P) out[threadIdx.x] = v;
 }
 
@@ -596,7 +679,15 @@ __device__ __forceinline__ void init_block(const BlockDesc* __restrict__ d) {
         s.best_f = __builtin_inf();
         s.arrive = 0;
         s.ready = 0;
+        s.slot = 0;
+        s.pad = 0;
+        s.old = 0.0;
         *d->st = s;
+        if (d->st2 != nullptr) {
+            // leading-step form: launch 1 runs the DE step of generation 0
+            s.gen = 1;
+            *d->st2 = s;
+        }
     }
     if (d->sync != nullptr)
         for (int k = i; k < kSyncInts; k += blockDim.x) d->sync[k] = 0;  // gen_begin is 0 here
@@ -610,6 +701,108 @@ __global__ void k_de_init(const BlockDesc* __restrict__ descs, int* __restrict__
 // (f, index) pair order of the argmin: smaller objective, then smaller index.
 __device__ __forceinline__ bool better(double fa, int ia, double fb, int ib) {
     return ib >= 0 && (ia < 0 || fb < fa || (fb == fa && ib < ia));
+}
+
+// Random decisions of member i's trial for generation gn (DE/rand/1/bin,
+// Table 4): r1, r2, r3 distinct and != i, and the active coordinates the
+// binomial crossover takes from the mutant (u < CR, or the forced jrand) as a
+// bit mask over act[].  Every number comes from the fit's Philox stream at
+// (i, gn); none depends on the population, so the draws can be made before
+// the selection they feed.
+struct Draws {
+    int r1, r2, r3;
+    unsigned cross;
+};
+
+__device__ __forceinline__ Draws trial_draws(const BlockDesc* __restrict__ d, int i, uint32_t gn) {
+    const int P = d->P;
+    const U4 w = draw4(d->seed, d->stream, (uint32_t)i, gn, kTagMut, 0u);
+    Draws r;
+    int r1 = index_from(w.x, P - 1);
+    if (r1 >= i) ++r1;
+    const int lo2 = min(i, r1), hi2 = max(i, r1);
+    int r2 = index_from(w.y, P - 2);
+    if (r2 >= lo2) ++r2;
+    if (r2 >= hi2) ++r2;
+    int e0 = i, e1 = r1, e2 = r2, t;
+    if (e0 > e1) { t = e0; e0 = e1; e1 = t; }
+    if (e1 > e2) { t = e1; e1 = e2; e2 = t; }
+    if (e0 > e1) { t = e0; e0 = e1; e1 = t; }
+    int r3 = index_from(w.z, P - 3);
+    if (r3 >= e0) ++r3;
+    if (r3 >= e1) ++r3;
+    if (r3 >= e2) ++r3;
+    const int jr = index_from(w.w, d->D);
+    unsigned cross = 0;
+    U4 u{0, 0, 0, 0};
+    for (int a = 0; a < d->D; ++a) {
+        if ((a & 3) == 0) u = draw4(d->seed, d->stream, (uint32_t)i, gn, kTagXover, (uint32_t)(a >> 2));
+        if (unit_from(word(u, a & 3)) < d->CR || a == jr) cross |= 1u << a;
+    }
+    r.r1 = r1;
+    r.r2 = r2;
+    r.r3 = r3;
+    r.cross = cross;
+    return r;
+}
+
+// Trial vector y of member i from the selected population xs (P x kSlots,
+// LDS) and its draws: v = x_r1 + F (x_r2 - x_r3) with the half-way bound
+// rule on the crossed coordinates, x_i elsewhere.
+__device__ __forceinline__ void apply_trial(const BlockDesc* __restrict__ d, const double* xs, int i,
+                                            const Draws& r, double (&y)[kStride]) {
+#pragma unroll
+    for (int j = 0; j < kSlots; ++j) y[j] = xs[i * kSlots + j];
+#pragma unroll
+    for (int j = kSlots; j < kStride; ++j) y[j] = 0.0;
+    for (int a = 0; a < d->D; ++a) {
+        if (!((r.cross >> a) & 1u)) continue;
+        const int j = d->act[a];
+        const double x1 = xs[r.r1 * kSlots + j];
+        double v = __fma_rn(d->F, xs[r.r2 * kSlots + j] - xs[r.r3 * kSlots + j], x1);
+        if (v < d->lo[j]) v = (d->lo[j] + x1) * 0.5;
+        if (v > d->hi[j]) v = (d->hi[j] + x1) * 0.5;
+        y[j] = v;
+    }
+}
+
+// Best member of the selected population: argmin of fsel (thread i holds
+// member i's value, -1 index past P), lowest index on ties; every thread
+// gets the result.  fr / ix: NT doubles / ints of LDS.
+__device__ __forceinline__ void argmin_members(int P, double fsel, double* fr, int* ix, int& best, double& bf) {
+    const int NT = blockDim.x, i = threadIdx.x;
+    if (P <= 64) {
+        // wave 0: the smallest value, then the lowest lane holding it (the
+        // lowest index on ties; a member whose objective is NaN is never best
+        // unless all are)
+        if (i < 64) {
+            const double f = i < P ? fsel : __builtin_inf();
+            double m = f;
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) m = fmin(m, __shfl_xor(m, off, 64));
+            const unsigned long long hit = __ballot(i < P && f == m);
+            const int id = hit ? __ffsll(hit) - 1 : 0;
+            const double fb = __shfl(f, id, 64);
+            if (i == 0) {
+                fr[0] = fb;
+                ix[0] = id;
+            }
+        }
+        __syncthreads();
+    } else {
+        fr[i] = fsel;
+        ix[i] = i < P ? i : -1;
+        __syncthreads();
+        for (int off = NT >> 1; off > 0; off >>= 1) {
+            if (i < off && better(fr[i], ix[i], fr[i + off], ix[i + off])) {
+                fr[i] = fr[i + off];
+                ix[i] = ix[i + off];
+            }
+            __syncthreads();
+        }
+    }
+    best = ix[0];
+    bf = fr[0];
 }
 
 // ---------------------------------------------------------------------------
@@ -659,7 +852,7 @@ __device__ __forceinline__ void de_step_body(const BlockDesc* __restrict__ d, do
                     ? __hip_atomic_load(d->hist + (g0 - d->window), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
                     : 0.0;
     }
-    const double ft = reduce_partials<PART_COH>(d, red);  // contains a barrier
+    const double ft = reduce_partials<PART_COH>(d, d->partials, red);  // contains a barrier
     if (s_done) return;
     const int g = s_gen;
 
@@ -678,39 +871,7 @@ __device__ __forceinline__ void de_step_body(const BlockDesc* __restrict__ d, do
     // argmin, lowest index on ties
     int best;
     double bf;
-    if (P <= 64) {
-        if (i < 64) {
-            double f = fsel;
-            int id = i < P ? i : -1;
-#pragma unroll
-            for (int off = 32; off >= 1; off >>= 1) {
-                const double fo2 = __shfl_xor(f, off, 64);
-                const int io2 = __shfl_xor(id, off, 64);
-                if (better(f, id, fo2, io2)) {
-                    f = fo2;
-                    id = io2;
-                }
-            }
-            if (i == 0) {
-                fr[0] = f;
-                ix[0] = id;
-            }
-        }
-        __syncthreads();
-    } else {
-        fr[i] = fsel;
-        ix[i] = i < P ? i : -1;
-        __syncthreads();
-        for (int off = NT >> 1; off > 0; off >>= 1) {
-            if (i < off && better(fr[i], ix[i], fr[i + off], ix[i + off])) {
-                fr[i] = fr[i + off];
-                ix[i] = ix[i + off];
-            }
-            __syncthreads();
-        }
-    }
-    best = ix[0];
-    bf = fr[0];
+    argmin_members(P, fsel, fr, ix, best, bf);
 
     int flags = 0;
     if (i == 0) {
@@ -740,41 +901,8 @@ __device__ __forceinline__ void de_step_body(const BlockDesc* __restrict__ d, do
     }
     if (s_stop || i >= P) return;
 
-    // trial vector of member i for generation g + 1
-    const uint32_t gn = (uint32_t)(g + 1);
-    const U4 w = draw4(d->seed, d->stream, (uint32_t)i, gn, kTagMut, 0u);
-    int r1 = index_from(w.x, P - 1);
-    if (r1 >= i) ++r1;
-    const int lo2 = min(i, r1), hi2 = max(i, r1);
-    int r2 = index_from(w.y, P - 2);
-    if (r2 >= lo2) ++r2;
-    if (r2 >= hi2) ++r2;
-    int e0 = i, e1 = r1, e2 = r2, t;
-    if (e0 > e1) { t = e0; e0 = e1; e1 = t; }
-    if (e1 > e2) { t = e1; e1 = e2; e2 = t; }
-    if (e0 > e1) { t = e0; e0 = e1; e1 = t; }
-    int r3 = index_from(w.z, P - 3);
-    if (r3 >= e0) ++r3;
-    if (r3 >= e1) ++r3;
-    if (r3 >= e2) ++r3;
-    const int jr = index_from(w.w, d->D);
-
     double y[kStride];
-#pragma unroll
-    for (int j = 0; j < kSlots; ++j) y[j] = xs[i * kSlots + j];
-#pragma unroll
-    for (int j = kSlots; j < kStride; ++j) y[j] = 0.0;
-    U4 u{0, 0, 0, 0};
-    for (int a = 0; a < d->D; ++a) {
-        if ((a & 3) == 0) u = draw4(d->seed, d->stream, (uint32_t)i, gn, kTagXover, (uint32_t)(a >> 2));
-        const double U = unit_from(word(u, a & 3));
-        const int j = d->act[a];
-        const double x1 = xs[r1 * kSlots + j];
-        double v = __fma_rn(d->F, xs[r2 * kSlots + j] - xs[r3 * kSlots + j], x1);
-        if (v < d->lo[j]) v = (d->lo[j] + x1) * 0.5;
-        if (v > d->hi[j]) v = (d->hi[j] + x1) * 0.5;
-        if (U < d->CR || a == jr) y[j] = v;
-    }
+    apply_trial(d, xs, i, trial_draws(d, i, (uint32_t)(g + 1)), y);
     double* trow = d->trial + (size_t)i * kStride;
 #pragma unroll
     for (int j = 0; j < kStride; ++j) xst(trow + j, y[j]);
@@ -783,6 +911,244 @@ __device__ __forceinline__ void de_step_body(const BlockDesc* __restrict__ d, do
 __global__ __launch_bounds__(1024) void k_de_step(const BlockDesc* __restrict__ descs) {
     extern __shared__ double lds[];
     de_step_body<false, false>(descs + blockIdx.x, lds);
+}
+
+// ---------------------------------------------------------------------------
+// Leading DE step (fits with P <= 256, blockDim = 256).  Launch L of a fit
+// (L a kernel argument) evaluates the trial population of generation L.
+// Before that, every objective workgroup of the launch repeats the DE step
+// of generation L - 1 for itself -- the objectives of all P trials from
+// their tile partials, and the selection -- and draws the trials of its own
+// candidate group (BOOK = false).  One more workgroup per block (BOOK =
+// true) runs the same step with the rest of it: the best member, the
+// best-so-far history and the stop rule, and it stores the selected
+// population, its objectives and the state the next launch reads.
+// Objective workgroups do not wait for the stop rule: after a stop they
+// evaluate one generation that nothing reads.  No workgroup waits for
+// another and none reads what another writes in the same launch: launch
+// parity p reads the state of slot p and the rows, objectives and partials
+// of slot p ^ 1 (all written by the previous launch) and writes the
+// opposite slots (BlockDesc).  Reduction order, selection, argmin and random
+// draws are those of de_step_body, so fits are bit-identical to the other
+// launch forms.  The random draws of the group's trials depend on L only,
+// so they are made while the step's loads are in flight.  A fit takes
+// max_gens + 2 launches: the last one runs only the DE step of generation
+// max_gens, which stops the fit.  After a stop, each further launch copies
+// the final state to the other slot, so every later launch sees it.
+//
+// Returns false when there is nothing to evaluate (BOOK, or the fit has
+// stopped); otherwise the group's candidates are in cs, past a barrier.
+// lds: the DE step's dynamic LDS plus P * kSlots doubles (2 P kSlots + 2 *
+// 256 doubles + 256 ints).
+// ---------------------------------------------------------------------------
+template <int CPG, bool BOOK, typename RT, int RS>
+__device__ __forceinline__ bool de_lead(const BlockDesc* __restrict__ d, int L, int tile, int group, Cand* cs,
+                                        double* lds, const RT (&raw)[RS]) {
+    const int p = L & 1;
+    const int P = d->P, NT = blockDim.x, i = threadIdx.x;
+    double* xs = lds;                              // P x kSlots: trial rows, then the selected rows
+    double* red = xs + (size_t)P * kSlots;         // NT
+    double* fr = red + NT;                         // NT
+    int* ix = reinterpret_cast<int*>(fr + NT);     // NT
+    double* xp = reinterpret_cast<double*>(ix + NT);  // P x kSlots: population rows
+    __shared__ int s_done, s_stop;
+    __shared__ double s_old;
+    const DeState* st_in = p ? d->st2 : d->st;
+    DeState* st_out = p ? d->st : d->st2;
+    const double* rows_in = p ? d->pop : d->pop2;  // slot p ^ 1
+    const double* trial_in = p ? d->trial : d->trial2;
+    const double* fpop_in = p ? d->fpop : d->fpop2;
+    const double* part_in = p ? d->partials : d->partials2;
+    double* rows_out = p ? d->pop2 : d->pop;       // slot p
+    double* trial_out = p ? d->trial2 : d->trial;
+    double* fpop_out = p ? d->fpop2 : d->fpop;
+    const int cbase = group * CPG;
+    const int ncand = min(CPG, P - cbase);
+
+    // 1. every load of the step, issued together: the tile partials (k threads
+    //    per member summing tiles part, part + k, ... as reduce_partials does),
+    //    the population rows and objectives, the state
+    // loads per thread in one batch: 17 covers P = 40 up to 102 tiles (400 000
+    // samples at 16 per lane) in one memory round trip; 24 would cost the
+    // kernel its fourth wave per SIMD (143 VGPRs instead of 115)
+    constexpr int kB = 17;
+    const int T = d->ntiles;
+    const int k = NT >= P ? NT / P : 1;
+    const int pm = i / k, part = i - pm * k;
+    const int cnt = (i < P * k && part < T) ? (T - part + k - 1) / k : 0;
+    const double* pr = part_in + (size_t)pm * T + part;
+    double v[kB];
+    // (no load sits in a branch: out-of-range ones read a valid address and
+    // are discarded, so none waits for another)
+#pragma unroll
+    for (int q = 0; q < kB; ++q) {
+        const double x = gld(q < cnt ? pr + (size_t)q * k : part_in);
+        v[q] = q < cnt ? x : 0.0;
+    }
+    // rows: element e = member * kSlots + slot, kR per thread (P <= 73 in one round)
+    constexpr int kR = 2;
+    const int ne = P * kSlots;
+    double rt[kR], rp[kR];
+#pragma unroll
+    for (int r = 0; r < kR; ++r) {
+        const int e = min(i + r * NT, ne - 1);
+        const int mem = e / kSlots;
+        const size_t off = (size_t)mem * kStride + (e - mem * kSlots);
+        rt[r] = gld(trial_in + off);
+        rp[r] = gld(rows_in + off);
+    }
+    const double fo = gld(fpop_in + min(i, P - 1));
+    const int st_done = gld(&st_in->done);
+    const double st_old = gld(&st_in->old);
+
+    // 2. while they are in flight: the random draws of this thread's trial
+    //    coordinate (candidate c = i / 8 of the group, slot j = i % 8)
+    const int c = i >> 3, j = i & 7;
+    const bool tw = !BOOK && L > 0 && c < ncand;
+    Draws dr{0, 0, 0, 0u};
+    if (tw) dr = trial_draws(d, cbase + c, (uint32_t)L);
+
+    // 3. objectives of all P trials, in reduce_partials' order
+    double sp = 0.0;
+#pragma unroll
+    for (int q = 0; q < kB; ++q)
+        if (q < cnt) sp += v[q];
+    for (int base = kB; base < cnt; base += kB) {
+#pragma unroll
+        for (int q = 0; q < kB; ++q) {
+            const double x = gld(base + q < cnt ? pr + (size_t)(base + q) * k : part_in);
+            v[q] = base + q < cnt ? x : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < kB; ++q)
+            if (base + q < cnt) sp += v[q];
+    }
+    // the lane's samples (loaded before the step) must have arrived here, so
+    // their loads are issued with the step's and not after it
+#pragma unroll
+    for (int q = 0; q < RS; ++q) asm volatile("" ::"v"(raw[q]));
+    if (i < P * k) red[i] = sp;
+#pragma unroll
+    for (int r = 0; r < kR; ++r) {
+        const int e = i + r * NT;
+        if (e < ne) {
+            xs[e] = rt[r];
+            xp[e] = rp[r];
+        }
+    }
+    for (int e = i + kR * NT; e < ne; e += NT) {  // P > 73
+        const int mem = e / kSlots;
+        const size_t off = (size_t)mem * kStride + (e - mem * kSlots);
+        xs[e] = gld(trial_in + off);
+        xp[e] = gld(rows_in + off);
+    }
+    if (i == 0) {
+        s_done = st_done;
+        s_old = st_old;
+    }
+    __syncthreads();
+    double ft = 0.0;
+    if (i < P) {
+        for (int q = 0; q < k; ++q) ft += red[i * k + q];
+        // correlation objective, Eq. (2-2-5): F = 1 / (arctan(C) + pi/2)
+        if (d->objective != 0) ft = 1.0 / (atan(ft) + 1.5707963267948966192);
+    }
+    if (s_done) {
+        if (BOOK && i == 0) {
+            const DeState s = *st_in;
+            xsti(&st_out->gen, s.gen);
+            xsti(&st_out->done, s.done);
+            xsti(&st_out->flags, s.flags);
+            xsti(&st_out->best, s.best);
+            xst(&st_out->best_f, s.best_f);
+            xsti(&st_out->slot, s.slot);
+        }
+        return false;
+    }
+    if (L == 0) {
+        // generation 0: the initial population as stored (slot 0); no step
+        if (BOOK) return false;
+        if (i < ncand) cs[i] = make_cand<false>(trial_out + (size_t)(cbase + i) * kStride, d->fs);
+        __syncthreads();
+        return true;
+    }
+    const int g = L - 1;
+
+    // 4. selection (generation 0 accepts the initial population)
+    double fsel = __builtin_inf();
+    if (i < P) {
+        const bool take = g == 0 || ft <= fo;
+        if (!take) {
+#pragma unroll
+            for (int q = 0; q < kSlots; ++q) xs[i * kSlots + q] = xp[i * kSlots + q];
+        }
+        fsel = take ? ft : fo;
+    }
+    if constexpr (!BOOK) {
+        __syncthreads();  // selected rows complete
+        // 5. the group's trials, one coordinate per thread (apply_trial's
+        //    arithmetic), straight into the candidates' turn-domain form
+        if (tw) {
+            const int m = cbase + c;
+            double y = 0.0;
+            if (j < kSlots) {
+                y = xs[m * kSlots + j];
+                int a = -1;
+                for (int q = 0; q < d->D; ++q)
+                    if (d->act[q] == j) a = q;
+                if (a >= 0 && ((dr.cross >> a) & 1u)) {
+                    const double x1 = xs[dr.r1 * kSlots + j];
+                    double vm = __fma_rn(d->F, xs[dr.r2 * kSlots + j] - xs[dr.r3 * kSlots + j], x1);
+                    if (vm < d->lo[j]) vm = (d->lo[j] + x1) * 0.5;
+                    if (vm > d->hi[j]) vm = (d->hi[j] + x1) * 0.5;
+                    y = vm;
+                }
+                cand_member(cs[c], j) = cand_value(j, y, d->fs);
+            }
+            if (tile == 0) gst(trial_out + (size_t)m * kStride + j, y);
+        }
+        __syncthreads();
+        return true;
+    }
+
+    // bookkeeping: best member, stop rule, stores
+    int best;
+    double bf;
+    argmin_members(P, fsel, fr, ix, best, bf);  // contains a barrier
+    if (i == 0) {
+        int flags = 0;
+        if (bf <= d->vtr) flags |= 4;  // PT_FLAG_VTR
+        if (d->rel_tol > 0.0 && d->window > 0 && g >= d->window && s_old - bf <= d->rel_tol * bf)
+            flags |= 1;  // PT_FLAG_CONVERGED
+        if (!flags && g >= d->max_gens) flags |= 2;  // PT_FLAG_MAXGEN
+        s_stop = flags;
+    }
+    __syncthreads();
+    const int flags = s_stop;
+    if (i < P) {
+        double* r = rows_out + (size_t)i * kStride;
+#pragma unroll
+        for (int q = 0; q < kSlots; ++q) gst(r + q, xs[i * kSlots + q]);
+#pragma unroll
+        for (int q = kSlots; q < kStride; ++q) gst(r + q, 0.0);
+        gst(fpop_out + i, fsel);
+    }
+    if (i == 0) {
+        xst(d->hist + g, bf);
+        // the window rule of the next step compares with hist[g + 1 - window]
+        double old = 0.0;
+        if (!flags && d->rel_tol > 0.0 && d->window > 0 && g + 1 >= d->window)
+            old = d->window == 1 ? bf : gld(d->hist + (g + 1 - d->window));
+        // the next launch evaluates generation g + 2 after the step of g + 1
+        xsti(&st_out->gen, flags ? g : g + 2);
+        xsti(&st_out->done, flags != 0);
+        xsti(&st_out->flags, flags);
+        xsti(&st_out->best, best);
+        xst(&st_out->best_f, bf);
+        xsti(&st_out->slot, p);
+        xst(&st_out->old, old);
+    }
+    return false;
 }
 
 // ---------------------------------------------------------------------------
@@ -838,7 +1204,8 @@ __device__ __forceinline__ int units_in_range(const BlockDesc* d, int x, int Ux,
     return max(0, min(ue, re) - max(ub, rb));
 }
 
-// Objective kernel: one work unit per workgroup.  Units are remapped so
+// Objective kernel: one work unit per workgroup (fused = 0; 1 and >= 2 add
+// the DE step, see below).  Units are remapped so
 // that the candidate groups of a tile run on one XCD (workgroup ids are dealt
 // round-robin to the 8 XCDs, so XCD x runs units [x Ux, (x + 1) Ux), Ux =
 // gridDim / 8).
@@ -852,8 +1219,16 @@ __device__ __forceinline__ int units_in_range(const BlockDesc* d, int x, int Ux,
 // two-launch form) and clears the counters for the next launch.  No
 // workgroup waits for another.  Partial sums are coherent stores and loads
 // (xst / xld), so the fences only order each wave's accesses around its
-// counter update.  Dynamic LDS: the DE step's (P * kSlots + 2 * 256 doubles
-// + 256 ints).
+// counter update.
+//
+// fused = 2 + L (fits with P <= 256): launch L of the leading-step form
+// (de_lead): every objective workgroup first runs the DE step of generation
+// L - 1 for itself, then evaluates its candidates of generation L; the grid
+// has one more unit per block (after the objective units) that keeps the
+// block's DE state.
+//
+// Dynamic LDS for fused != 0: the DE step's (P * kSlots + 2 * 256 doubles +
+// 256 ints), and P * kSlots doubles more for fused >= 2.
 template <typename T, int S, int CPG, int MODE, bool SLOPE>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_objective(
     const BlockDesc* __restrict__ descs, int nblk, int total_units, int fused) {
@@ -861,22 +1236,44 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 4))
     const int bid = blockIdx.x;
     const int Ux = nwg >> 3;
     const int unit = (bid & 7) * Ux + (bid >> 3);
-    if (unit >= total_units) return;
+    __shared__ Cand cs[CPG];
+    extern __shared__ double de_lds[];
+    if (unit >= total_units) {
+        // leading-step form: unit total_units + b keeps block b's DE state
+        if (fused >= 2 && unit < total_units + nblk) {
+            const float none[1] = {0.0f};
+            de_lead<CPG, true>(descs + (unit - total_units), fused - 2, 0, 0, cs, de_lds, none);
+        }
+        return;
+    }
     const BlockDesc* __restrict__ d = descs + find_block(descs, nblk, unit);
-    if (d->st != nullptr && d->st->done) return;
+    // (the leading-step form reads its stop state inside de_lead, which must
+    // also run after a stop to copy the state forward)
+    if (fused < 2 && d->st != nullptr && d->st->done) return;
     const int local = unit - d->unit_begin;
     const int tile = local / d->ngroups;
     const int group = local - tile * d->ngroups;
 
-    __shared__ Cand cs[CPG];
     __shared__ double red[CPG][kThreads];
     __shared__ int s_last;
     using V = typename std::conditional<MODE == 1, float, double>::type;
     V sv[S];
     bool full;
     int valid;
+    if (fused >= 2) {
+        // the samples' loads overlap the DE step's; they stay in their stored
+        // type until then (fewer registers across the step)
+        T raw[S];
+        load_lane_raw<T, S>(d, tile, raw);
+        const int L = fused - 2;  // the launch's index within the fit
+        if (!de_lead<CPG, false>(d, L, tile, group, cs, de_lds, raw)) return;
+        finish_lane<V, T, S>(d, tile, raw, sv, full, valid);
+        objective_unit<S, CPG, MODE, SLOPE>(d, tile, group, sv, full, valid, cs, red, nullptr,
+                                            (L & 1) ? d->partials2 : d->partials);
+        return;
+    }
     load_lane<V, T, S>(d, tile, sv, full, valid);
-    objective_unit<S, CPG, MODE, SLOPE>(d, tile, group, sv, full, valid, cs, red);
+    objective_unit<S, CPG, MODE, SLOPE>(d, tile, group, sv, full, valid, cs, red, d->trial, d->partials);
     if (!fused) return;
 
     int* sync = d->sync;
@@ -903,7 +1300,6 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 4))
     }
     __syncthreads();
     if (!s_last) return;
-    extern __shared__ double de_lds[];
     de_step_body<false, true>(d, de_lds);
     __syncthreads();
     if (threadIdx.x < 8) __hip_atomic_store(sync + threadIdx.x * kSyncLine, 0, __ATOMIC_RELAXED,
@@ -959,7 +1355,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 4))
             if (s_done) continue;
             any = true;
             if (!resident) load_lane<V, T, S>(d, tile, sv, full, valid);
-            objective_unit<S, CPG, MODE, SLOPE, true>(d, tile, group, sv, full, valid, cs, red);
+            objective_unit<S, CPG, MODE, SLOPE, true>(d, tile, group, sv, full, valid, cs, red, d->trial,
+                                                      d->partials);
             // The workgroup barrier makes every wave's partial stores visible
             // at the XCD's L2; one release fence then publishes them device-wide
             // before the arrival is counted.  Arrivals are counted per XCD
@@ -1032,10 +1429,18 @@ struct FitRecord {
 
 __global__ void k_finalize(const BlockDesc* __restrict__ descs, FitRecord* __restrict__ out) {
     const BlockDesc* d = descs + blockIdx.x;
+    // leading-step form: the final state is the slot whose stop flag is set
+    DeState s = *d->st;
+    if (d->st2 != nullptr && !s.done) s = *d->st2;
+    const double* pop = s.slot ? d->pop2 : d->pop;
+    if (s.slot) {
+        // leave the final population in slot 0, where the host reads it
+        for (int k = threadIdx.x; k < d->P * kStride; k += blockDim.x) d->pop[k] = pop[k];
+        for (int k = threadIdx.x; k < d->P; k += blockDim.x) d->fpop[k] = d->fpop2[k];
+    }
     if (threadIdx.x != 0) return;
-    const DeState s = *d->st;
     FitRecord r;
-    const double* xb = d->pop + (size_t)s.best * kStride;
+    const double* xb = pop + (size_t)s.best * kStride;
     int flags = s.flags;
     for (int j = 0; j < kSlots; ++j) r.x[j] = xb[j];
     for (int a = 0; a < d->D; ++a) {

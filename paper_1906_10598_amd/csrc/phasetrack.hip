@@ -46,6 +46,9 @@ int fail(int code, const char* fmt, ...) {
     } while (0)
 
 constexpr int kChunk = 50;  // generations per captured graph
+// the leading-step form takes a launch's buffer slot from its parity, so every
+// graph must start at an even launch
+static_assert(kChunk % 2 == 0, "graph chunks must hold an even number of launches");
 
 struct DevBuf {
     void* p = nullptr;
@@ -247,11 +250,12 @@ struct Plan {
     Geometry geo{16, 4};
     int total_units = 0;
     int grid = 0;          // objective workgroups (multiple of 8)
+    int grid_lead = 0;     // leading-step form: objective units plus one per block (multiple of 8)
     unsigned de_threads = 64;
     size_t de_lds = 0;
     int max_gens = 0;
     bool window = false;
-    bool fused = false;    // DE step inside the objective launch (k_objective, fused != 0)
+    int fused = 0;         // DE step inside the objective launch: 0 no, 1 last workgroup, 2 leading step
 };
 
 }  // namespace
@@ -293,11 +297,12 @@ struct pt_ctx {
         int nblk, grid, total_units, spl, cpg, dtype, mixed, slope;
         unsigned de_threads;
         size_t de_lds;
-        int iters, fused;
+        int iters, fused, base;
         bool operator<(const GraphKey& o) const {
             return std::tie(desc, nblk, grid, total_units, spl, cpg, dtype, mixed, slope, de_threads, de_lds, iters,
-                            fused) < std::tie(o.desc, o.nblk, o.grid, o.total_units, o.spl, o.cpg, o.dtype,
-                                              o.mixed, o.slope, o.de_threads, o.de_lds, o.iters, o.fused);
+                            fused, base) < std::tie(o.desc, o.nblk, o.grid, o.total_units, o.spl, o.cpg, o.dtype,
+                                                    o.mixed, o.slope, o.de_threads, o.de_lds, o.iters, o.fused,
+                                                    o.base);
         }
     };
     std::map<GraphKey, hipGraphExec_t> graphs;
@@ -401,8 +406,9 @@ int collect_timing(pt_ctx* ctx) {
     return PT_OK;
 }
 
-// Enqueue one generation: objective over all units, then the DE step.
-int enqueue_generation(pt_ctx* ctx, const Plan& pl, ObjKernel obj, hipStream_t s, bool timed) {
+// Enqueue one generation: objective over all units, then the DE step.  L:
+// the launch's index within the fit (the leading-step form's kernel argument).
+int enqueue_generation(pt_ctx* ctx, const Plan& pl, ObjKernel obj, hipStream_t s, bool timed, int L) {
     const BlockDesc* d = static_cast<const BlockDesc*>(ctx->desc.p);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (timed) {
@@ -412,8 +418,11 @@ int enqueue_generation(pt_ctx* ctx, const Plan& pl, ObjKernel obj, hipStream_t s
         HIPCHK(hipEventRecord(e0, s));
     }
     if (pl.fused && !timed) {
-        // the DE step runs in each block's last objective workgroup
-        hipLaunchKernelGGL(obj, dim3(pl.grid), dim3(kThreads), pl.de_lds, s, d, pl.nblk, pl.total_units, 1);
+        // the DE step runs in each block's last objective workgroup (1), or
+        // ahead of the objective in every workgroup (2 + launch index)
+        const int f = pl.fused == 2 ? 2 + L : 1;
+        const int grid = pl.fused == 2 ? pl.grid_lead : pl.grid;
+        hipLaunchKernelGGL(obj, dim3(grid), dim3(kThreads), pl.de_lds, s, d, pl.nblk, pl.total_units, f);
         HIPCHK(hipGetLastError());
         return PT_OK;
     }
@@ -428,9 +437,13 @@ int enqueue_generation(pt_ctx* ctx, const Plan& pl, ObjKernel obj, hipStream_t s
     return PT_OK;
 }
 
-int get_graph(pt_ctx* ctx, const Plan& pl, ObjKernel obj, int iters, hipGraphExec_t* out) {
+// Graph of `iters` generations starting at launch `base` (the leading-step
+// form passes the launch index, so its graphs are kept per base; the others
+// share base 0).
+int get_graph(pt_ctx* ctx, const Plan& pl, ObjKernel obj, int iters, int base, hipGraphExec_t* out) {
+    if (pl.fused != 2) base = 0;
     pt_ctx::GraphKey key{ctx->desc.p, pl.nblk, pl.grid, pl.total_units, pl.geo.spl, pl.geo.cpg, pl.dtype,
-                         pl.mode, (int)pl.slope, pl.de_threads, pl.de_lds, iters, (int)pl.fused};
+                         pl.mode, (int)pl.slope, pl.de_threads, pl.de_lds, iters, (int)pl.fused, base};
     auto it = ctx->graphs.find(key);
     if (it != ctx->graphs.end()) {
         *out = it->second;
@@ -439,7 +452,7 @@ int get_graph(pt_ctx* ctx, const Plan& pl, ObjKernel obj, int iters, hipGraphExe
     hipStream_t cs = ctx->cap_stream;
     HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     int rc = PT_OK;
-    for (int k = 0; k < iters && rc == PT_OK; ++k) rc = enqueue_generation(ctx, pl, obj, cs, false);
+    for (int k = 0; k < iters && rc == PT_OK; ++k) rc = enqueue_generation(ctx, pl, obj, cs, false, base + k);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(cs, &g);
     if (rc != PT_OK) {
@@ -504,22 +517,27 @@ int prepare(pt_ctx* ctx, const pt_block* blocks, int nblk, const pt_de_settings*
     if (units > (int64_t)1 << 30) return fail(PT_EINVAL, "batch too large (%lld work units)", (long long)units);
     pl->total_units = (int)units;
     pl->grid = (int)((units + 7) / 8 * 8);
+    pl->grid_lead = (int)((units + nblk + 7) / 8 * 8);
     pl->de_threads = pow2_at_least(P);  // >= 256 and >= P: also fixes the partial-sum order
     pl->de_lds = (size_t)P * kSlots * 8 + (size_t)pl->de_threads * (8 + 8 + 4);
-    pl->fused = with_state && ctx->step_fusion && pl->de_threads == (unsigned)kThreads;
+    pl->fused = (with_state && ctx->step_fusion && pl->de_threads == (unsigned)kThreads)
+                    ? (ctx->step_fusion == PT_FUSION_LAST ? 1 : 2)
+                    : 0;
+    if (pl->fused == 2) pl->de_lds += (size_t)P * kSlots * 8;  // the leading step stages both row sets
 
+    // two slots of the DE buffers (the leading-step form alternates between them)
     const size_t rows = (size_t)nblk * P * kStride * sizeof(double);
     int rc;
-    if ((rc = ctx->desc.ensure(sizeof(BlockDesc) * nblk)) || (rc = ctx->pop.ensure(rows)) ||
-        (rc = ctx->trial.ensure(rows)) || (rc = ctx->fpop.ensure((size_t)nblk * P * sizeof(double))) ||
-        (rc = ctx->partials.ensure(part_elems * sizeof(double))) ||
+    if ((rc = ctx->desc.ensure(sizeof(BlockDesc) * nblk)) || (rc = ctx->pop.ensure(2 * rows)) ||
+        (rc = ctx->trial.ensure(2 * rows)) || (rc = ctx->fpop.ensure(2 * (size_t)nblk * P * sizeof(double))) ||
+        (rc = ctx->partials.ensure(2 * part_elems * sizeof(double))) ||
         (rc = ctx->hist.ensure((size_t)nblk * (de->max_gens + 1) * sizeof(double))) ||
-        (rc = ctx->state.ensure((size_t)nblk * sizeof(DeState))) ||
+        (rc = ctx->state.ensure(2 * (size_t)nblk * sizeof(DeState))) ||
         (rc = ctx->sync.ensure((size_t)nblk * kSyncInts * sizeof(int))) ||
         (rc = ctx->rec.ensure((size_t)nblk * sizeof(FitRecord))) ||
         (rc = ctx->hdesc.ensure(sizeof(BlockDesc) * nblk)) ||
         (rc = ctx->hrec.ensure((size_t)nblk * sizeof(FitRecord))) ||
-        (rc = ctx->hstate.ensure((size_t)nblk * sizeof(DeState))))
+        (rc = ctx->hstate.ensure(2 * (size_t)nblk * sizeof(DeState))))
         return rc;
     if (stage_bytes && (rc = ctx->staging.ensure(stage_bytes))) return rc;
 
@@ -577,6 +595,13 @@ int prepare(pt_ctx* ctx, const pt_block* blocks, int nblk, const pt_de_settings*
         part_off += (size_t)P * ntiles[b];
         d.hist = hist + (size_t)b * (de->max_gens + 1);
         d.st = with_state ? st + b : nullptr;
+        if (pl->fused == 2) {
+            d.pop2 = d.pop + (size_t)nblk * P * kStride;
+            d.trial2 = d.trial + (size_t)nblk * P * kStride;
+            d.fpop2 = d.fpop + (size_t)nblk * P;
+            d.partials2 = d.partials + part_elems;
+            d.st2 = d.st + nblk;
+        }
         d.sync = with_state ? static_cast<int*>(ctx->sync.p) + (size_t)b * kSyncInts : nullptr;
         d.gen_begin = 0;
         d.objective = de->objective;
@@ -647,7 +672,10 @@ int run_fit(pt_ctx* ctx, const pt_block* blocks, int nblk, const pt_de_settings*
     hipLaunchKernelGGL(k_de_init, dim3(nblk), dim3(pl.de_threads), 0, s, d, err);
     HIPCHK(hipGetLastError());
 
-    const int iters = de->max_gens + 1;  // evaluation of gen 0 plus max_gens generations
+    // evaluation of gen 0 plus max_gens generations; the leading-step form adds
+    // one launch for the DE step of the last generation
+    const bool lead = pl.fused == 2 && !ctx->timing;
+    const int iters = de->max_gens + 1 + (lead ? 1 : 0);
     if (persistent) {
         int nb = nblk, tu = pl.total_units, steps = de->max_gens + 1;
         uint64_t ticks = ctx->spin_ticks;
@@ -667,25 +695,27 @@ int run_fit(pt_ctx* ctx, const pt_block* blocks, int nblk, const pt_de_settings*
         // nothing else to enqueue
     } else if (ctx->timing) {
         for (int k = 0; k < iters; ++k)
-            if ((rc = enqueue_generation(ctx, pl, obj, s, true))) return rc;
+            if ((rc = enqueue_generation(ctx, pl, obj, s, true, k))) return rc;
     } else {
         hipGraphExec_t ex = nullptr;
         const int full = iters / kChunk, rem = iters % kChunk;
-        if (full && (rc = get_graph(ctx, pl, obj, kChunk, &ex))) return rc;
         DeState* hst = static_cast<DeState*>(ctx->hstate.p);
-        for (int c = 0; c < full; ++c) {
+        bool all = false;
+        for (int c = 0; c < full && !all; ++c) {
+            if ((c == 0 || lead) && (rc = get_graph(ctx, pl, obj, kChunk, c * kChunk, &ex))) return rc;
             HIPCHK(hipGraphLaunch(ex, s));
             if (pl.window && c + 1 < full) {
-                // stop replaying once every block has met its stop rule
-                HIPCHK(hipMemcpyAsync(hst, ctx->state.p, sizeof(DeState) * nblk, hipMemcpyDeviceToHost, s));
+                // stop launching once every block has met its stop rule (the
+                // leading-step form's launches must otherwise run in sequence)
+                const int ns = lead ? 2 * nblk : nblk;  // leading-step form: either slot may hold the stop
+                HIPCHK(hipMemcpyAsync(hst, ctx->state.p, sizeof(DeState) * ns, hipMemcpyDeviceToHost, s));
                 HIPCHK(hipStreamSynchronize(s));
-                bool all = true;
-                for (int b = 0; b < nblk && all; ++b) all = hst[b].done != 0;
-                if (all) break;
+                all = true;
+                for (int b = 0; b < nblk && all; ++b) all = hst[b].done != 0 || (lead && hst[nblk + b].done != 0);
             }
         }
-        for (int k = 0; k < rem; ++k)
-            if ((rc = enqueue_generation(ctx, pl, obj, s, false))) return rc;
+        for (int k = 0; k < rem && !all; ++k)
+            if ((rc = enqueue_generation(ctx, pl, obj, s, false, full * kChunk + k))) return rc;
     }
     hipLaunchKernelGGL(k_finalize, dim3(nblk), dim3(64), 0, s, d, static_cast<FitRecord*>(ctx->rec.p));
     HIPCHK(hipGetLastError());
@@ -1165,10 +1195,11 @@ int pt_ctx_last_launch(pt_ctx* ctx, int* mode) {
     return PT_OK;
 }
 
-int pt_ctx_set_step_fusion(pt_ctx* ctx, int on) {
+int pt_ctx_set_step_fusion(pt_ctx* ctx, int mode) {
     if (!ctx) return fail(PT_EINVAL, "ctx is null");
-    if (on != 0 && on != 1) return fail(PT_EINVAL, "step fusion %d", on);
-    ctx->step_fusion = on;
+    if (mode != PT_FUSION_OFF && mode != PT_FUSION_LEAD && mode != PT_FUSION_LAST)
+        return fail(PT_EINVAL, "step fusion %d", mode);
+    ctx->step_fusion = mode;
     return PT_OK;
 }
 

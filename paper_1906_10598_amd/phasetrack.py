@@ -28,6 +28,7 @@ PT_LAUNCH_AUTO, PT_LAUNCH_GRAPH, PT_LAUNCH_PERSISTENT = 0, 1, 2
 PT_FP64_AUTO, PT_FP64_POLY = 0, 1
 PT_OBJ_CHI2, PT_OBJ_COR = 0, 1
 PT_ARITH_FP64_POLY, PT_ARITH_MIXED, PT_ARITH_FP64_PHASOR = 0, 1, 2
+PT_FUSION_OFF, PT_FUSION_LEAD, PT_FUSION_LAST = 0, 1, 2
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libphasetrack.so")
 
@@ -422,8 +423,10 @@ def pt_ctx_last_launch(ctx) -> int:
     return m.value
 
 
-def pt_ctx_set_step_fusion(ctx, on: bool):
-    _check(lib().pt_ctx_set_step_fusion(ctx, int(on)), "pt_ctx_set_step_fusion")
+def pt_ctx_set_step_fusion(ctx, mode: int):
+    """PT_FUSION_LEAD (default), PT_FUSION_LAST or PT_FUSION_OFF (True / False
+    stand for PT_FUSION_LEAD / PT_FUSION_OFF)."""
+    _check(lib().pt_ctx_set_step_fusion(ctx, int(mode)), "pt_ctx_set_step_fusion")
 
 
 def pt_ctx_last_arithmetic(ctx) -> int:

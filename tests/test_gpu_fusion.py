@@ -1,12 +1,17 @@
-"""Step fusion: one launch per generation (the DE step in each block's last
-objective workgroup) against objective + DE step as two launches.
+"""Step fusion: one launch per generation against objective + DE step as two
+launches.  Two one-launch forms: the leading step (every workgroup repeats
+the previous generation's DE step before its objective work; two buffer
+slots alternate by launch parity) and the last-workgroup step (the DE step
+in each block's last objective workgroup).
 
-The fused launch runs the same objective arithmetic, the same partial-sum
+Every form runs the same objective arithmetic, the same partial-sum
 reduction (same thread count and order) and the same DE step, so fits must
-be bit-identical: coefficients, objectives, flags, final populations and
-the best-so-far history.  Covered: the tiny block in both precisions, the
-paper-scale block, a batch of uneven blocks sharing each launch, and the
-window stop rule with blocks stopping at different generations.
+be bit-identical: coefficients, objectives, flags, generations, final
+populations and the best-so-far history.  Covered: the tiny block in both
+precisions, the paper-scale block, a batch of uneven blocks sharing each
+launch, the window stop rule with blocks stopping at different generations
+(in both launch parities), a stop at generation 0 (value to reach) and a
+fit with no generation after the initial one.
 """
 import numpy as np
 import pytest
@@ -18,15 +23,18 @@ from paper_1906_10598_amd import phasetrack as ptk
 pytestmark = pytest.mark.gpu
 
 
-def _fit(fused, pbs, de):
+FORMS = [ptk.PT_FUSION_LEAD, ptk.PT_FUSION_LAST]
+
+
+def _fit(mode, pbs, de):
     c = ctx()
-    ptk.pt_ctx_set_step_fusion(c.handle, fused)
+    ptk.pt_ctx_set_step_fusion(c.handle, mode)
     try:
         fits = c.fit_batch(pbs, de) if len(pbs) > 1 else [c.fit_block(pbs[0], de)]
         pops = [ptk.pt_last_population(c.handle, k, de.pop) for k in range(len(pbs))]
         hists = [ptk.pt_last_history(c.handle, k, f.generations + 1) for k, f in enumerate(fits)]
     finally:
-        ptk.pt_ctx_set_step_fusion(c.handle, True)
+        ptk.pt_ctx_set_step_fusion(c.handle, ptk.PT_FUSION_LEAD)
     return fits, pops, hists
 
 
@@ -39,26 +47,60 @@ def _same(a, b, label):
     print(f"[{label}] {len(a[0])} block(s) bit-identical; generations {[f.generations for f in a[0]]}", flush=True)
 
 
+@pytest.mark.parametrize("mode", FORMS)
 @pytest.mark.parametrize("prec", [ptk.PT_PREC_FP64, ptk.PT_PREC_MIXED])
-def test_tiny_block(prec):
+def test_tiny_block(prec, mode):
     b = synth.config0(1)
     dev = to_dev(b.samples)
     de = settings_of(b, precision=prec)
-    _same(_fit(True, [block_of(b, dev)], de), _fit(False, [block_of(b, dev)], de), f"fused tiny {prec}")
+    _same(_fit(mode, [block_of(b, dev)], de), _fit(ptk.PT_FUSION_OFF, [block_of(b, dev)], de),
+          f"fusion {mode} tiny {prec}")
 
 
-def test_paper_block():
+@pytest.mark.parametrize("mode", FORMS)
+def test_paper_block(mode):
     b = synth.config1(0)
     dev = to_dev(b.samples)
     de = settings_of(b)
-    _same(_fit(True, [block_of(b, dev)], de), _fit(False, [block_of(b, dev)], de), "fused paper")
+    _same(_fit(mode, [block_of(b, dev)], de), _fit(ptk.PT_FUSION_OFF, [block_of(b, dev)], de),
+          f"fusion {mode} paper")
 
 
-def test_batch_with_window_rule():
+@pytest.mark.parametrize("mode", FORMS)
+def test_batch_with_window_rule(mode):
     blocks = synth.config3(1, nblocks=12, gens=400)
     devs = [to_dev(x.samples) for x in blocks]
     pbs = [block_of(x, d) for x, d in zip(blocks, devs)]
     de = settings_of(blocks[0], gens=400, rel_tol=1e-9, window=30)
-    a, b = _fit(True, pbs, de), _fit(False, pbs, de)
-    assert len({f.generations for f in a[0]}) > 1  # blocks stopped at different generations
-    _same(a, b, "fused batch")
+    a, b = _fit(mode, pbs, de), _fit(ptk.PT_FUSION_OFF, pbs, de)
+    gens = {f.generations for f in a[0]}
+    assert len(gens) > 1  # blocks stopped at different generations
+    assert len({g % 2 for g in gens}) == 2  # ... in both launch parities
+    _same(a, b, f"fusion {mode} batch")
+
+
+@pytest.mark.parametrize("mode", FORMS)
+@pytest.mark.parametrize("window", [1, 2])
+def test_short_windows(mode, window):
+    # window 1 and 2: the rule compares with the step just stored / the one before
+    b = synth.config0(2)
+    dev = to_dev(b.samples)
+    de = settings_of(b, gens=300, rel_tol=1e-3, window=window)
+    a, o = _fit(mode, [block_of(b, dev)], de), _fit(ptk.PT_FUSION_OFF, [block_of(b, dev)], de)
+    assert a[0][0].flags & ptk.PT_FLAG_CONVERGED
+    _same(a, o, f"fusion {mode} window {window}")
+
+
+@pytest.mark.parametrize("mode", FORMS)
+def test_stop_at_generation_zero_and_no_generations(mode):
+    b = synth.config0(3)
+    dev = to_dev(b.samples)
+    for de in (settings_of(b, vtr=1e9), settings_of(b, gens=0), settings_of(b, gens=1)):
+        a, o = _fit(mode, [block_of(b, dev)], de), _fit(ptk.PT_FUSION_OFF, [block_of(b, dev)], de)
+        assert a[0][0].generations == o[0][0].generations <= 1
+        _same(a, o, f"fusion {mode} gens {de.max_gens} vtr {de.vtr}")
+
+
+def test_invalid_fusion_mode():
+    with pytest.raises(ptk.PtError):
+        ptk.pt_ctx_set_step_fusion(ctx().handle, 3)
