@@ -45,16 +45,17 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def read_traffic(path, geometry):
+def read_traffic(path, geometry, form="objective"):
     """HBM bytes per objective launch from a committed rocprofv3 summary of the
-    same kernel (sources hash, workload and geometry), else None."""
+    same kernel (sources hash, workload, geometry and launch form), else None."""
     try:
         with open(path) as f:
             for line in f:
                 if line.startswith("traffic:"):
                     kv = dict(item.split("=", 1) for item in line.split()[1:])
                     if (kv.get("kernel_hash") == kernel_hash() and kv.get("workload") == "paper-400000-fp32"
-                            and kv.get("geometry") == "%d,%d" % tuple(geometry)):
+                            and kv.get("geometry") == "%d,%d" % tuple(geometry)
+                            and kv.get("form", "objective") == form):
                         return float(kv["bytes_per_launch"])
     except (OSError, ValueError, KeyError):
         return None
@@ -68,6 +69,13 @@ def traffic_of(name, geometry):
                         geometry)
 
 
+def fit_traffic_of(geometry):
+    """Traffic per launch of the objective kernel in the FP64 fit's launch form
+    (leading DE step), from profiles/fit_lead_paper400k_<S>x<C>.md."""
+    return read_traffic(os.path.join(ROOT, "profiles", "fit_lead_paper400k_%dx%d.md" % tuple(geometry)),
+                        geometry, form="fit-lead")
+
+
 def pct(xs, q):
     xs = sorted(xs)
     if not xs:
@@ -77,18 +85,28 @@ def pct(xs, q):
     return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
 
 
-def run_fits(ctx, blk, de_fn, n, label):
+def run_fits(ctx, blk, de_fn, n, label, events=None):
+    """n fits; wall seconds, per-fit latencies [ms], fits.  events: a list that
+    receives the GPU time [ms] between HIP events recorded on the fits' stream
+    (torch's current stream) around the whole region."""
     import torch
 
     lat = []
     fits = []
     torch.cuda.synchronize()
+    if events is not None:
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
     t0 = time.perf_counter()
     for k in range(n):
         t1 = time.perf_counter()
         fits.append(ctx.fit_block(blk, de_fn(k)))
         lat.append((time.perf_counter() - t1) * 1e3)
+    if events is not None:
+        e1.record()
     torch.cuda.synchronize()
+    if events is not None:
+        events.append(e0.elapsed_time(e1))
     return time.perf_counter() - t0, lat, fits
 
 
@@ -251,7 +269,7 @@ def main():
     ap.add_argument("--reps", type=int, default=200)
     ap.add_argument("--launch", default="auto", choices=["auto", "graph", "persistent"],
                     help="launch strategy of the fits (pt_ctx_set_launch_mode)")
-    ap.add_argument("--fusion", default="lead", choices=["lead", "last", "off"],
+    ap.add_argument("--fusion", default="auto", choices=["auto", "lead", "last", "off"],
                     help="where a graph-launched fit runs its DE step (pt_ctx_set_step_fusion)")
     ap.add_argument("--fit-only", action="store_true",
                     help="profiling mode: --warmup + --steps fits of the paper-scale block (FP64, default "
@@ -282,6 +300,11 @@ def main():
     blk = ptk.make_block(dev, b.fs, b.lo, b.hi, ref=b.ref, stream=b.stream)
     stream = ptk.current_stream()
 
+    # launch form of the fits (the autotuner times fits in this form)
+    ptk.pt_ctx_set_launch_mode(ctx.handle, {"auto": ptk.PT_LAUNCH_AUTO, "graph": ptk.PT_LAUNCH_GRAPH,
+                                            "persistent": ptk.PT_LAUNCH_PERSISTENT}[args.launch])
+    ptk.pt_ctx_set_step_fusion(ctx.handle, {"auto": ptk.PT_FUSION_AUTO, "lead": ptk.PT_FUSION_LEAD,
+                                            "last": ptk.PT_FUSION_LAST, "off": ptk.PT_FUSION_OFF}[args.fusion])
     tiles = {}
     if args.tile:
         spl, cpg = (int(v) for v in args.tile.split(","))
@@ -299,15 +322,18 @@ def main():
         ptk.pt_ctx_set_step_fusion(ctx.handle, ptk.PT_FUSION_OFF)
         ctx.fit_block(blk, ptk.make_settings(pop=P, max_gens=G, F=b.de.F, CR=b.de.CR, seed=b.de.seed,
                                              precision=prec))
-        ptk.pt_ctx_set_step_fusion(ctx.handle, ptk.PT_FUSION_LEAD)
+        ptk.pt_ctx_set_step_fusion(ctx.handle, ptk.PT_FUSION_AUTO)
         pop, _ = ptk.pt_last_population(ctx.handle, 0, P)
         popd = torch.from_numpy(pop).cuda()
+        torch.cuda.synchronize()
         avg_ms = ptk.pt_time_objective(ctx.handle, blk, popd.data_ptr(), P, prec, args.reps, stream)
+        arith_k = ARITH_NAME[ptk.pt_ctx_last_arithmetic(ctx.handle)]
         src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
         torch.mul(src, 2.0, out=dst)  # calibration: reads 256 MiB, writes 256 MiB
         torch.cuda.synchronize()
         print(json.dumps({"kernel_only": args.kernel_only, "avg_launch_ms": avg_ms, "reps": args.reps,
+                          "arithmetic": arith_k,
                           "geometry": tiles[args.kernel_only], "kernel_hash": kernel_hash(),
                           "calibration_copy_bytes": 2 * src.numel() * 4}), flush=True)
         ctx.close()
@@ -317,13 +343,13 @@ def main():
         return lambda k: ptk.make_settings(pop=P, max_gens=G, F=b.de.F, CR=b.de.CR, seed=b.de.seed + k,
                                            precision=prec)
 
-    ptk.pt_ctx_set_launch_mode(ctx.handle, {"auto": ptk.PT_LAUNCH_AUTO, "graph": ptk.PT_LAUNCH_GRAPH,
-                                            "persistent": ptk.PT_LAUNCH_PERSISTENT}[args.launch])
-    ptk.pt_ctx_set_step_fusion(ctx.handle, {"lead": ptk.PT_FUSION_LEAD, "last": ptk.PT_FUSION_LAST,
-                                            "off": ptk.PT_FUSION_OFF}[args.fusion])
     if args.fit_only:
         run_fits(ctx, blk, de(ptk.PT_PREC_FP64), args.warmup, "warmup")
         el, lat, _ = run_fits(ctx, blk, de(ptk.PT_PREC_FP64), args.steps, "fp64")
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.mul(src, 2.0, out=dst)  # traffic-counter calibration: reads 256 MiB, writes 256 MiB
+        torch.cuda.synchronize()
         print(json.dumps({"fit_only": True, "launch": args.launch, "fusion": args.fusion, "fits": args.steps,
                           "ms_per_fit": el / args.steps * 1e3,
                           "p50_ms": pct(lat, 50), "geometry": tiles["fp64"],
@@ -334,7 +360,9 @@ def main():
 
     # ---- plain FP64: warmup + timed steps
     run_fits(ctx, blk, de(ptk.PT_PREC_FP64), args.warmup, "warmup")
-    elapsed, lat_steps, fits64 = run_fits(ctx, blk, de(ptk.PT_PREC_FP64), args.steps, "fp64")
+    ev = []
+    elapsed, lat_steps, fits64 = run_fits(ctx, blk, de(ptk.PT_PREC_FP64), args.steps, "fp64", events=ev)
+    launches_per_fit = ptk.pt_ctx_fit_launches(ctx.handle)
     value = pairs_per_fit * args.steps / elapsed
     arith64 = ARITH_NAME[ptk.pt_ctx_last_arithmetic(ctx.handle)]
     print(f"# fp64: {args.steps} fits in {elapsed:.3f} s", file=sys.stderr, flush=True)
@@ -389,6 +417,12 @@ def main():
                       "flop_per_candidate_sample": ALG_FLOP}
 
     traffic = traffic_of("fp64", tiles["fp64"])
+    # the kernel as the timed fits launch it: HIP events around the timed region,
+    # divided by the launches it held (every launch but each fit's last one
+    # evaluates the population: ALG_FLOP * P * N)
+    fit_launch_ms = ev[0] / (args.steps * launches_per_fit)
+    fit_flop = ALG_FLOP * pairs_per_fit * args.steps
+    fit_ach = fit_flop / (ev[0] * 1e-3) / 1e12
 
     # ---- batched fits: 64 uneven blocks, own populations, shared launches
     batch = None
@@ -476,12 +510,17 @@ def main():
                                "unit": "TFLOP/s", "frac": roof["mixed"]["achieved"] / PEAK_FP32_TFLOPS,
                                "avg_launch_ms": roof["mixed"]["avg_launch_ms"],
                                "traffic": traffic_of("mixed", tiles["mixed"])}},
-        "roofline": {"bound": "alu", "achieved": r64["achieved"], "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": r64["achieved"] / PEAK_FP64_TFLOPS, "traffic": traffic,
-                     "kernel": "k_objective (FP64, %s)" % r64["arithmetic"], "avg_launch_ms": r64["avg_launch_ms"],
-                     "in_fit_event_ms": r64["in_fit_event_ms"], "launches_per_fit": r64["launches"],
-                     "flop_per_candidate_sample": r64["flop_per_candidate_sample"],
-                     "kernel_hash": kernel_hash(),
+        "roofline": {"bound": "alu", "achieved": fit_ach, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": fit_ach / PEAK_FP64_TFLOPS, "traffic": fit_traffic_of(tiles["fp64"]),
+                     "kernel": "k_objective (FP64, %s) as launched in the timed fits: one launch per "
+                               "generation with the leading DE step" % arith64,
+                     "avg_launch_ms": fit_launch_ms, "launches_per_fit": launches_per_fit,
+                     "event_ms_timed_region": ev[0],
+                     "flop_per_candidate_sample": ALG_FLOP, "kernel_hash": kernel_hash(),
+                     "objective_only": {"kernel": "k_objective (FP64, %s), objective alone" % r64["arithmetic"],
+                                        "avg_launch_ms": r64["avg_launch_ms"], "achieved": r64["achieved"],
+                                        "frac": r64["achieved"] / PEAK_FP64_TFLOPS, "traffic": traffic,
+                                        "in_fit_event_ms": r64["in_fit_event_ms"]},
                      "fp64_per_sample_path": {k: roof["fp64_per_sample"][k] for k in
                                               ("avg_launch_ms", "achieved", "flop_per_candidate_sample")} |
                                              {"frac": roof["fp64_per_sample"]["achieved"] / PEAK_FP64_TFLOPS}},

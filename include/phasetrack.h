@@ -453,7 +453,12 @@ int pt_ctx_set_fp64_method(pt_ctx* ctx, int method);
 /* ---- step fusion ----
  * How a fit's generations map onto launches (graph-replayed fits; the DE
  * step is that of Table 4, DE/rand/1/bin, in every form):
- * PT_FUSION_LEAD (default, P <= 256): one launch per generation.  Every
+ * PT_FUSION_AUTO (default): PT_FUSION_LEAD when the launch's work units fit
+ *   in one round of resident workgroups (at most four per compute unit: a
+ *   latency-bound fit, such as one paper-scale block), else PT_FUSION_LAST
+ *   (a throughput-bound batch, where the leading step's repeated work costs
+ *   more than the last workgroup's wait).
+ * PT_FUSION_LEAD (P <= 256): one launch per generation.  Every
  *   objective workgroup first repeats the previous generation's DE step for
  *   itself (objectives of all P trials from the tile partials, selection,
  *   best member, stop rule) and draws the trials of its own candidates; the
@@ -465,7 +470,7 @@ int pt_ctx_set_fp64_method(pt_ctx* ctx, int method);
  *   unit (arrival counters, no waiting).
  * PT_FUSION_OFF: objective and DE step as two launches.
  * All three give bit-identical fits.  Returns PT_EINVAL for another value. */
-enum { PT_FUSION_OFF = 0, PT_FUSION_LEAD = 1, PT_FUSION_LAST = 2 };
+enum { PT_FUSION_OFF = 0, PT_FUSION_LEAD = 1, PT_FUSION_LAST = 2, PT_FUSION_AUTO = 3 };
 
 int pt_ctx_set_step_fusion(pt_ctx* ctx, int mode);
 
@@ -474,6 +479,12 @@ int pt_ctx_set_step_fusion(pt_ctx* ctx, int mode);
 enum { PT_ARITH_FP64_POLY = 0, PT_ARITH_MIXED = 1, PT_ARITH_FP64_PHASOR = 2 };
 
 int pt_ctx_last_arithmetic(pt_ctx* ctx, int* arith);
+
+/* Objective-kernel launches of the context's most recent fit (all blocks of
+ * a batch share them): one per generation including generation 0, plus one
+ * for the last DE step in the leading-step form; 1 for a persistent launch.
+ * A fit that stopped early by the window rule may have run fewer. */
+int pt_ctx_last_fit_launches(pt_ctx* ctx, int64_t* launches);
 
 /* ---- instrumentation ---- */
 
@@ -505,8 +516,11 @@ int pt_ctx_get_tile(pt_ctx* ctx, int64_t n, int P, int precision, int* samples_p
 int pt_ctx_set_tile(pt_ctx* ctx, int samples_per_lane, int cand_per_group);
 
 /* Time every supported geometry on a block of n samples and population P
- * (synthetic data on the device) and remember the fastest for that size
- * class and precision.  best_spl / best_cpg may be NULL. */
+ * (synthetic data on the device, a box of the paper's widths around one
+ * carrier): short fits of 100 generations in the context's current launch
+ * form and step fusion.  Remembers the fastest for that size class and
+ * precision; replaces the context's last-fit record (pt_last_population).
+ * best_spl / best_cpg may be NULL. */
 int pt_ctx_autotune(pt_ctx* ctx, int64_t n, int P, int precision, void* hip_stream,
                     int* best_spl, int* best_cpg);
 

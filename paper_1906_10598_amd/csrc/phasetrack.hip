@@ -281,7 +281,8 @@ struct pt_ctx {
     int fp64_method = PT_FP64_AUTO;
     int last_launch = PT_LAUNCH_GRAPH;
     int last_arith = PT_ARITH_FP64_POLY;
-    int step_fusion = 1;
+    int64_t last_fit_launches = 0;
+    int step_fusion = PT_FUSION_AUTO;
     uint64_t spin_ticks = 0;
     DevBuf errflag;
     // initial-range estimation
@@ -520,8 +521,12 @@ int prepare(pt_ctx* ctx, const pt_block* blocks, int nblk, const pt_de_settings*
     pl->grid_lead = (int)((units + nblk + 7) / 8 * 8);
     pl->de_threads = pow2_at_least(P);  // >= 256 and >= P: also fixes the partial-sum order
     pl->de_lds = (size_t)P * kSlots * 8 + (size_t)pl->de_threads * (8 + 8 + 4);
-    pl->fused = (with_state && ctx->step_fusion && pl->de_threads == (unsigned)kThreads)
-                    ? (ctx->step_fusion == PT_FUSION_LAST ? 1 : 2)
+    // leading step (2) for launches that fit in one round of resident
+    // workgroups (four per compute unit), last-workgroup step (1) for larger ones
+    int fusion = ctx->step_fusion;
+    if (fusion == PT_FUSION_AUTO) fusion = units <= 4LL * ctx->ncu ? PT_FUSION_LEAD : PT_FUSION_LAST;
+    pl->fused = (with_state && fusion != PT_FUSION_OFF && pl->de_threads == (unsigned)kThreads)
+                    ? (fusion == PT_FUSION_LAST ? 1 : 2)
                     : 0;
     if (pl->fused == 2) pl->de_lds += (size_t)P * kSlots * 8;  // the leading step stages both row sets
 
@@ -691,6 +696,7 @@ int run_fit(pt_ctx* ctx, const pt_block* blocks, int nblk, const pt_de_settings*
     }
     ctx->last_launch = persistent ? PT_LAUNCH_PERSISTENT : PT_LAUNCH_GRAPH;
     ctx->last_arith = pl.mode;
+    ctx->last_fit_launches = persistent ? 1 : iters;
     if (persistent) {
         // nothing else to enqueue
     } else if (ctx->timing) {
@@ -828,6 +834,17 @@ int pt_fit_batch(pt_ctx* ctx, const pt_block* blocks, int nblk, const pt_de_sett
 // Shared set-up of the bare objective entry points: descriptor of one block
 // without DE state, the caller's P x 6 rows copied into the stride-8 trial
 // rows, and the objective kernel of the chosen geometry.
+static_assert(kSlots == PT_NSLOT, "device rows hold the C-ABI's slots");
+
+// Rows of a caller's population (P x kSlots, packed) into the kStride layout
+// of a trial buffer; the pad slot is zero.
+__global__ void k_pack_rows(const double* __restrict__ src, double* __restrict__ dst, int P) {
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < P * kStride; e += gridDim.x * blockDim.x) {
+        const int r = e / kStride, c = e - r * kStride;
+        dst[e] = c < kSlots ? src[(size_t)r * kSlots + c] : 0.0;
+    }
+}
+
 static int eval_setup(pt_ctx* ctx, const pt_block* block, const double* pop, int P, int precision, int objective,
                       hipStream_t s, Plan* pl, ObjKernel* obj) {
     int rc = check_block(block, 0);
@@ -877,8 +894,10 @@ static int eval_setup(pt_ctx* ctx, const pt_block* block, const double* pop, int
     if ((rc = prepare(ctx, &blk, 1, &de, s, pl, false))) return rc;
     if (ctx->desc.p != old_desc) ctx->drop_graphs();
     const BlockDesc* hd = static_cast<const BlockDesc*>(ctx->hdesc.p);
-    HIPCHK(hipMemcpy2DAsync(hd[0].trial, kStride * sizeof(double), pop, PT_NSLOT * sizeof(double),
-                            PT_NSLOT * sizeof(double), P, hipMemcpyDeviceToDevice, s));
+    // (a kernel, not a strided 2-D copy: those have returned wrong data under
+    // the profiler on this runtime)
+    hipLaunchKernelGGL(k_pack_rows, dim3(1), dim3(256), 0, s, pop, hd[0].trial, P);
+    HIPCHK(hipGetLastError());
     if (!pl->mixed && ctx->fp64_method != PT_FP64_POLY) {
         const double span = (double)block->n + std::fabs(block_ref(block));
         pl->mode = std::isfinite(f1) && std::isfinite(f2) && std::isfinite(f3) &&
@@ -944,9 +963,13 @@ int pt_last_population(pt_ctx* ctx, int index, double* pop_host, double* fpop_ho
     HIPCHK(hipSetDevice(ctx->device));
     HIPCHK(hipDeviceSynchronize());
     if (pop_host) {
+        // whole rows, then the slots (a strided 2-D copy to host memory has
+        // returned wrong data under the profiler on this runtime)
         const double* src = static_cast<const double*>(ctx->pop.p) + (size_t)index * P * kStride;
-        HIPCHK(hipMemcpy2D(pop_host, PT_NSLOT * sizeof(double), src, kStride * sizeof(double),
-                           PT_NSLOT * sizeof(double), P, hipMemcpyDeviceToHost));
+        std::vector<double> rows((size_t)P * kStride);
+        HIPCHK(hipMemcpy(rows.data(), src, rows.size() * sizeof(double), hipMemcpyDeviceToHost));
+        for (int p = 0; p < P; ++p)
+            for (int j = 0; j < PT_NSLOT; ++j) pop_host[(size_t)p * PT_NSLOT + j] = rows[(size_t)p * kStride + j];
     }
     if (fpop_host) {
         const double* src = static_cast<const double*>(ctx->fpop.p) + (size_t)index * P;
@@ -1197,9 +1220,15 @@ int pt_ctx_last_launch(pt_ctx* ctx, int* mode) {
 
 int pt_ctx_set_step_fusion(pt_ctx* ctx, int mode) {
     if (!ctx) return fail(PT_EINVAL, "ctx is null");
-    if (mode != PT_FUSION_OFF && mode != PT_FUSION_LEAD && mode != PT_FUSION_LAST)
+    if (mode != PT_FUSION_OFF && mode != PT_FUSION_LEAD && mode != PT_FUSION_LAST && mode != PT_FUSION_AUTO)
         return fail(PT_EINVAL, "step fusion %d", mode);
     ctx->step_fusion = mode;
+    return PT_OK;
+}
+
+int pt_ctx_last_fit_launches(pt_ctx* ctx, int64_t* launches) {
+    if (!ctx || !launches) return fail(PT_EINVAL, "ctx / launches is null");
+    *launches = ctx->last_fit_launches;
     return PT_OK;
 }
 
@@ -1249,25 +1278,17 @@ int pt_ctx_autotune(pt_ctx* ctx, int64_t n, int P, int precision, void* hip_stre
     if (n < 8 || n > ((int64_t)1 << 31) || P < 4 || P > PT_MAX_POP) return fail(PT_EINVAL, "n or P out of range");
     if (precision != PT_PREC_FP64 && precision != PT_PREC_MIXED) return fail(PT_EINVAL, "precision %d", precision);
     HIPCHK(hipSetDevice(ctx->device));
-    hipStream_t s = static_cast<hipStream_t>(hip_stream);
-    // synthetic FP32 block and population (values only matter for timing)
+    // synthetic FP32 block (values only matter for timing)
     int rc;
     if ((rc = ctx->scratch.ensure((size_t)n * 4))) return rc;
-    if ((rc = ctx->eval_pop.ensure((size_t)P * PT_NSLOT * 8 + (size_t)P * 8))) return rc;
     std::vector<float> hs((size_t)std::min<int64_t>(n, 1 << 20));
     for (size_t k = 0; k < hs.size(); ++k) hs[k] = (float)std::cos(0.37 * (double)k);
     for (int64_t off = 0; off < n; off += (int64_t)hs.size()) {
         const size_t cnt = (size_t)std::min<int64_t>((int64_t)hs.size(), n - off);
         HIPCHK(hipMemcpy(static_cast<float*>(ctx->scratch.p) + off, hs.data(), cnt * 4, hipMemcpyHostToDevice));
     }
-    // a population near one carrier, as in a fit (the FP64 path then uses the
-    // arithmetic it uses in a fit of a paper-scale box)
-    std::vector<double> hp((size_t)P * PT_NSLOT);
-    for (int p = 0; p < P; ++p) {
-        double* x = &hp[(size_t)p * PT_NSLOT];
-        x[0] = 1.0; x[1] = 0.1 * p; x[2] = 1000.0 + 1e-3 * p; x[3] = 0.5; x[4] = 0.01; x[5] = 0.0; x[6] = 0.0;
-    }
-    HIPCHK(hipMemcpy(ctx->eval_pop.p, hp.data(), hp.size() * 8, hipMemcpyHostToDevice));
+    // a box around one carrier with the paper's widths (so the FP64 path uses
+    // the arithmetic it uses in a fit of a paper-scale box)
     pt_block b;
     std::memset(&b, 0, sizeof b);
     b.samples = ctx->scratch.p;
@@ -1276,27 +1297,44 @@ int pt_ctx_autotune(pt_ctx* ctx, int64_t n, int P, int precision, void* hip_stre
     b.on_device = 1;
     b.fs = 50000.0;
     b.ref = NAN;
-    for (int j = 0; j < PT_NSLOT; ++j) { b.box.lo[j] = 0; b.box.hi[j] = 1; }
-    b.box.hi[5] = 0;
-    b.box.hi[6] = 0;
+    const double lo[PT_NSLOT] = {0.8, 0.0, 1000.0, 0.4, -0.01, 0.0, 0.0};
+    const double hi[PT_NSLOT] = {1.2, 6.28, 1001.0, 0.6, 0.01, 0.0, 0.0};
+    for (int j = 0; j < PT_NSLOT; ++j) {
+        b.box.lo[j] = lo[j];
+        b.box.hi[j] = hi[j];
+    }
+    pt_de_settings de;
+    std::memset(&de, 0, sizeof de);
+    de.pop = P;
+    de.max_gens = 100;
+    de.F = 0.5;
+    de.CR = 0.9;
+    de.seed = 1;
+    de.vtr = -INFINITY;
+    de.precision = precision;
+    de.objective = PT_OBJ_CHI2;
     const Geometry saved = ctx->forced;
     Geometry best{0, 0};
     double best_ms = 1e30;
-    // two passes of 100 back-to-back launches per geometry; the faster pass counts
+    // per geometry: one untimed fit of 100 generations in the context's launch
+    // form (builds its graphs), then two timed ones; the faster counts
     std::map<std::pair<int, int>, double> t;
-    for (int pass = 0; pass < 2 && !rc; ++pass)
-        for (int spl : kSpl) {
-            for (int cpg : kCpg) {
-                ctx->forced = {spl, cpg};
-                double ms = 0.0;
-                rc = pt_time_objective(ctx, &b, static_cast<const double*>(ctx->eval_pop.p), P, precision, 100, s,
-                                       &ms);
-                if (rc) break;
-                auto key = std::make_pair(spl, cpg);
-                t[key] = pass ? std::min(t[key], ms) : ms;
+    pt_fit fit;
+    for (int spl : kSpl) {
+        for (int cpg : kCpg) {
+            ctx->forced = {spl, cpg};
+            double ms = 1e30;
+            for (int rep = 0; rep < 3 && !rc; ++rep) {
+                const auto t0 = std::chrono::steady_clock::now();
+                rc = run_fit(ctx, &b, 1, &de, hip_stream, &fit);
+                const auto t1 = std::chrono::steady_clock::now();
+                if (rep) ms = std::min(ms, std::chrono::duration<double, std::milli>(t1 - t0).count());
             }
             if (rc) break;
+            t[std::make_pair(spl, cpg)] = ms;
         }
+        if (rc) break;
+    }
     for (int spl : kSpl) {
         for (int cpg : kCpg) {
             if (rc) break;

@@ -28,7 +28,7 @@ PT_LAUNCH_AUTO, PT_LAUNCH_GRAPH, PT_LAUNCH_PERSISTENT = 0, 1, 2
 PT_FP64_AUTO, PT_FP64_POLY = 0, 1
 PT_OBJ_CHI2, PT_OBJ_COR = 0, 1
 PT_ARITH_FP64_POLY, PT_ARITH_MIXED, PT_ARITH_FP64_PHASOR = 0, 1, 2
-PT_FUSION_OFF, PT_FUSION_LEAD, PT_FUSION_LAST = 0, 1, 2
+PT_FUSION_OFF, PT_FUSION_LEAD, PT_FUSION_LAST, PT_FUSION_AUTO = 0, 1, 2, 3
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libphasetrack.so")
 
@@ -202,6 +202,7 @@ def _signatures(L):
         "pt_ctx_set_step_fusion": ([_CTX, i32], i32),
         "pt_ctx_set_timing": ([_CTX, i32], i32),
         "pt_ctx_kernel_stats": ([_CTX, ctypes.POINTER(i64), _DP], i32),
+        "pt_ctx_last_fit_launches": ([_CTX, ctypes.POINTER(i64)], i32),
         "pt_ctx_get_tile": ([_CTX, i64, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)], i32),
         "pt_ctx_set_tile": ([_CTX, i32, i32], i32),
         "pt_ctx_autotune": ([_CTX, i64, i32, i32, _VP, ctypes.POINTER(i32), ctypes.POINTER(i32)], i32),
@@ -417,6 +418,12 @@ def pt_ctx_set_fp64_method(ctx, method: int):
     _check(lib().pt_ctx_set_fp64_method(ctx, method), "pt_ctx_set_fp64_method")
 
 
+def pt_ctx_fit_launches(ctx) -> int:
+    n = ctypes.c_int64()
+    _check(lib().pt_ctx_last_fit_launches(ctx, ctypes.byref(n)), "pt_ctx_last_fit_launches")
+    return n.value
+
+
 def pt_ctx_last_launch(ctx) -> int:
     m = ctypes.c_int()
     _check(lib().pt_ctx_last_launch(ctx, ctypes.byref(m)), "pt_ctx_last_launch")
@@ -424,8 +431,7 @@ def pt_ctx_last_launch(ctx) -> int:
 
 
 def pt_ctx_set_step_fusion(ctx, mode: int):
-    """PT_FUSION_LEAD (default), PT_FUSION_LAST or PT_FUSION_OFF (True / False
-    stand for PT_FUSION_LEAD / PT_FUSION_OFF)."""
+    """PT_FUSION_AUTO (default), PT_FUSION_LEAD, PT_FUSION_LAST or PT_FUSION_OFF."""
     _check(lib().pt_ctx_set_step_fusion(ctx, int(mode)), "pt_ctx_set_step_fusion")
 
 

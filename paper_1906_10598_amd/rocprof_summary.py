@@ -13,7 +13,11 @@ of known size: 256 MiB read, 256 MiB written) and the VALU counters.  The
 summary carries a `traffic:` line that bench.py reads (bytes per launch and
 the hash of the kernel sources they were taken with).
 
-Usage: python -m paper_1906_10598_amd.rocprof_summary DIR OUT.md KERNEL_SUBSTRING "COMMAND TEXT"
+Usage: python -m paper_1906_10598_amd.rocprof_summary DIR OUT.md KERNEL_SUBSTRING "COMMAND TEXT" [FORM]
+
+FORM names the launch form the counters were taken in: "objective" (default,
+bench.py --kernel-only: the objective alone) or "fit-lead" (bench.py
+--fit-only: the fit's launches with the leading DE step).
 """
 import csv
 import glob
@@ -43,7 +47,7 @@ def _counters(path):
     return d
 
 
-def summarise(root, kernel, command):
+def summarise(root, kernel, command, form="objective"):
     out = []
     stats = os.path.join(root, "trace", "run_kernel_stats.csv")
     avg_ns = None
@@ -103,13 +107,14 @@ def summarise(root, kernel, command):
         if m:
             geo = f" geometry={m.group(1)},{m.group(2)}"
         head.append(f"traffic: bytes_per_launch={traffic:.0f} kernel_hash={kernel_hash()} "
-                    f"workload=paper-400000-fp32{geo}\n")
+                    f"workload=paper-400000-fp32{geo} form={form}\n")
     return "\n".join(head + out) + "\n"
 
 
 def main():
     root, out_path, kernel, command = sys.argv[1:5]
-    text = summarise(root, kernel, command)
+    form = sys.argv[5] if len(sys.argv) > 5 else "objective"
+    text = summarise(root, kernel, command, form)
     with open(out_path, "w") as fh:
         fh.write(text)
     print(text)

@@ -2,7 +2,8 @@
 launches.  Two one-launch forms: the leading step (every workgroup repeats
 the previous generation's DE step before its objective work; two buffer
 slots alternate by launch parity) and the last-workgroup step (the DE step
-in each block's last objective workgroup).
+in each block's last objective workgroup); the automatic choice picks one
+of them by launch size.
 
 Every form runs the same objective arithmetic, the same partial-sum
 reduction (same thread count and order) and the same DE step, so fits must
@@ -23,7 +24,7 @@ from paper_1906_10598_amd import phasetrack as ptk
 pytestmark = pytest.mark.gpu
 
 
-FORMS = [ptk.PT_FUSION_LEAD, ptk.PT_FUSION_LAST]
+FORMS = [ptk.PT_FUSION_LEAD, ptk.PT_FUSION_LAST, ptk.PT_FUSION_AUTO]
 
 
 def _fit(mode, pbs, de):
@@ -34,7 +35,7 @@ def _fit(mode, pbs, de):
         pops = [ptk.pt_last_population(c.handle, k, de.pop) for k in range(len(pbs))]
         hists = [ptk.pt_last_history(c.handle, k, f.generations + 1) for k, f in enumerate(fits)]
     finally:
-        ptk.pt_ctx_set_step_fusion(c.handle, ptk.PT_FUSION_LEAD)
+        ptk.pt_ctx_set_step_fusion(c.handle, ptk.PT_FUSION_AUTO)
     return fits, pops, hists
 
 
@@ -103,4 +104,4 @@ def test_stop_at_generation_zero_and_no_generations(mode):
 
 def test_invalid_fusion_mode():
     with pytest.raises(ptk.PtError):
-        ptk.pt_ctx_set_step_fusion(ctx().handle, 3)
+        ptk.pt_ctx_set_step_fusion(ctx().handle, 4)
