@@ -443,7 +443,11 @@ int pt_ctx_last_launch(pt_ctx* ctx, int* mode);
  *   2e-11 per sample for the whole box: the dropped cubic and quartic terms
  *   below 1e-12 turns, the quadratic correction's error below 1e-11, and
  *   the carrier at least S * 2.2e-4 / (2 pi) of fs away from 0 and fs / 2
- *   (the recurrence's conditioning); otherwise the per-sample path.
+ *   (the recurrence's conditioning); otherwise the per-sample path.  The
+ *   choice is made per block: in a graph-launched batch the blocks that
+ *   qualify and those that do not run as two objective launches per
+ *   generation (a persistent launch uses the per-sample path for all when
+ *   any block needs it).
  * PT_FP64_POLY: always the per-sample path (exact reduction of the phase in
  *   turns, degree-10 cosine polynomial). */
 enum { PT_FP64_AUTO = 0, PT_FP64_POLY = 1 };
@@ -475,7 +479,8 @@ enum { PT_FUSION_OFF = 0, PT_FUSION_LEAD = 1, PT_FUSION_LAST = 2, PT_FUSION_AUTO
 int pt_ctx_set_step_fusion(pt_ctx* ctx, int mode);
 
 /* Objective arithmetic of the context's most recent fit or objective
- * evaluation: per-sample FP64 cosine, mixed precision, or FP64 phasor. */
+ * evaluation: per-sample FP64 cosine, mixed precision, or FP64 phasor (also
+ * for a batch whose blocks used both FP64 arithmetics). */
 enum { PT_ARITH_FP64_POLY = 0, PT_ARITH_MIXED = 1, PT_ARITH_FP64_PHASOR = 2 };
 
 int pt_ctx_last_arithmetic(pt_ctx* ctx, int* arith);

@@ -256,6 +256,18 @@ struct Plan {
     int max_gens = 0;
     bool window = false;
     int fused = 0;         // DE step inside the objective launch: 0 no, 1 last workgroup, 2 leading step
+    // Objective launches of one generation in the graph form: blocks whose
+    // boxes allow the FP64 phasor arithmetic and those that do not run as
+    // separate launches, each over its own copy of its blocks' descriptors
+    // (units numbered from 0); otherwise one launch over the main table.
+    struct Launch {
+        int desc_off;      // first descriptor of the launch in the context's table
+        int nblk;
+        int mode;
+        int total_units, grid, grid_lead;
+        ObjKernel obj;
+    };
+    std::vector<Launch> launches;
 };
 
 }  // namespace
@@ -299,11 +311,12 @@ struct pt_ctx {
         unsigned de_threads;
         size_t de_lds;
         int iters, fused, base;
+        std::vector<int> launches;  // (descriptor offset, blocks, arithmetic, units) per objective launch
         bool operator<(const GraphKey& o) const {
             return std::tie(desc, nblk, grid, total_units, spl, cpg, dtype, mixed, slope, de_threads, de_lds, iters,
-                            fused, base) < std::tie(o.desc, o.nblk, o.grid, o.total_units, o.spl, o.cpg, o.dtype,
-                                                    o.mixed, o.slope, o.de_threads, o.de_lds, o.iters, o.fused,
-                                                    o.base);
+                            fused, base, launches) < std::tie(o.desc, o.nblk, o.grid, o.total_units, o.spl, o.cpg,
+                                                              o.dtype, o.mixed, o.slope, o.de_threads, o.de_lds,
+                                                              o.iters, o.fused, o.base, o.launches);
         }
     };
     std::map<GraphKey, hipGraphExec_t> graphs;
@@ -409,7 +422,7 @@ int collect_timing(pt_ctx* ctx) {
 
 // Enqueue one generation: objective over all units, then the DE step.  L:
 // the launch's index within the fit (the leading-step form's kernel argument).
-int enqueue_generation(pt_ctx* ctx, const Plan& pl, ObjKernel obj, hipStream_t s, bool timed, int L) {
+int enqueue_generation(pt_ctx* ctx, const Plan& pl, hipStream_t s, bool timed, int L) {
     const BlockDesc* d = static_cast<const BlockDesc*>(ctx->desc.p);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (timed) {
@@ -422,13 +435,18 @@ int enqueue_generation(pt_ctx* ctx, const Plan& pl, ObjKernel obj, hipStream_t s
         // the DE step runs in each block's last objective workgroup (1), or
         // ahead of the objective in every workgroup (2 + launch index)
         const int f = pl.fused == 2 ? 2 + L : 1;
-        const int grid = pl.fused == 2 ? pl.grid_lead : pl.grid;
-        hipLaunchKernelGGL(obj, dim3(grid), dim3(kThreads), pl.de_lds, s, d, pl.nblk, pl.total_units, f);
-        HIPCHK(hipGetLastError());
+        for (const Plan::Launch& g : pl.launches) {
+            const int grid = pl.fused == 2 ? g.grid_lead : g.grid;
+            hipLaunchKernelGGL(g.obj, dim3(grid), dim3(kThreads), pl.de_lds, s, d + g.desc_off, g.nblk,
+                               g.total_units, f);
+            HIPCHK(hipGetLastError());
+        }
         return PT_OK;
     }
-    hipLaunchKernelGGL(obj, dim3(pl.grid), dim3(kThreads), 0, s, d, pl.nblk, pl.total_units, 0);
-    HIPCHK(hipGetLastError());
+    for (const Plan::Launch& g : pl.launches) {
+        hipLaunchKernelGGL(g.obj, dim3(g.grid), dim3(kThreads), 0, s, d + g.desc_off, g.nblk, g.total_units, 0);
+        HIPCHK(hipGetLastError());
+    }
     if (timed) {
         HIPCHK(hipEventRecord(e1, s));
         ctx->ev_pending.push_back({e0, e1});
@@ -441,10 +459,17 @@ int enqueue_generation(pt_ctx* ctx, const Plan& pl, ObjKernel obj, hipStream_t s
 // Graph of `iters` generations starting at launch `base` (the leading-step
 // form passes the launch index, so its graphs are kept per base; the others
 // share base 0).
-int get_graph(pt_ctx* ctx, const Plan& pl, ObjKernel obj, int iters, int base, hipGraphExec_t* out) {
+int get_graph(pt_ctx* ctx, const Plan& pl, int iters, int base, hipGraphExec_t* out) {
     if (pl.fused != 2) base = 0;
+    std::vector<int> sig;
+    for (const Plan::Launch& g : pl.launches) {
+        sig.push_back(g.desc_off);
+        sig.push_back(g.nblk);
+        sig.push_back(g.mode);
+        sig.push_back(g.total_units);
+    }
     pt_ctx::GraphKey key{ctx->desc.p, pl.nblk, pl.grid, pl.total_units, pl.geo.spl, pl.geo.cpg, pl.dtype,
-                         pl.mode, (int)pl.slope, pl.de_threads, pl.de_lds, iters, (int)pl.fused, base};
+                         pl.mode, (int)pl.slope, pl.de_threads, pl.de_lds, iters, (int)pl.fused, base, sig};
     auto it = ctx->graphs.find(key);
     if (it != ctx->graphs.end()) {
         *out = it->second;
@@ -453,7 +478,7 @@ int get_graph(pt_ctx* ctx, const Plan& pl, ObjKernel obj, int iters, int base, h
     hipStream_t cs = ctx->cap_stream;
     HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     int rc = PT_OK;
-    for (int k = 0; k < iters && rc == PT_OK; ++k) rc = enqueue_generation(ctx, pl, obj, cs, false, base + k);
+    for (int k = 0; k < iters && rc == PT_OK; ++k) rc = enqueue_generation(ctx, pl, cs, false, base + k);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(cs, &g);
     if (rc != PT_OK) {
@@ -491,15 +516,17 @@ int prepare(pt_ctx* ctx, const pt_block* blocks, int nblk, const pt_de_settings*
     // geometry from the largest block (one kernel instance per launch)
     pl->geo = choose_geometry(ctx, nmax, P, pl->mixed);
     pl->mode = pl->mixed ? kModeMixed : kModePoly;
+    std::vector<char> phasor(nblk, 0);
+    int nphasor = 0;
     if (!pl->mixed && ctx->fp64_method != PT_FP64_POLY) {
-        bool ok = true;
-        for (int b = 0; b < nblk && ok; ++b) {
+        for (int b = 0; b < nblk; ++b) {
             const pt_box& bx = blocks[b].box;
             const double span = (double)blocks[b].n + std::fabs(block_ref(&blocks[b]));
-            ok = phasor_ok(pl->geo.spl, blocks[b].fs, span, bx.lo[2], bx.hi[2], box_max(bx, 3), box_max(bx, 4),
-                           box_max(bx, 6));
+            phasor[b] = phasor_ok(pl->geo.spl, blocks[b].fs, span, bx.lo[2], bx.hi[2], box_max(bx, 3),
+                                  box_max(bx, 4), box_max(bx, 6));
+            nphasor += phasor[b];
         }
-        if (ok) pl->mode = kModePhasor;
+        if (nphasor == nblk) pl->mode = kModePhasor;  // one kernel for every block
     }
     const int tile = kThreads * pl->geo.spl;
     const int groups = (P + pl->geo.cpg - 1) / pl->geo.cpg;
@@ -533,14 +560,14 @@ int prepare(pt_ctx* ctx, const pt_block* blocks, int nblk, const pt_de_settings*
     // two slots of the DE buffers (the leading-step form alternates between them)
     const size_t rows = (size_t)nblk * P * kStride * sizeof(double);
     int rc;
-    if ((rc = ctx->desc.ensure(sizeof(BlockDesc) * nblk)) || (rc = ctx->pop.ensure(2 * rows)) ||
+    if ((rc = ctx->desc.ensure(2 * sizeof(BlockDesc) * nblk)) || (rc = ctx->pop.ensure(2 * rows)) ||
         (rc = ctx->trial.ensure(2 * rows)) || (rc = ctx->fpop.ensure(2 * (size_t)nblk * P * sizeof(double))) ||
         (rc = ctx->partials.ensure(2 * part_elems * sizeof(double))) ||
         (rc = ctx->hist.ensure((size_t)nblk * (de->max_gens + 1) * sizeof(double))) ||
         (rc = ctx->state.ensure(2 * (size_t)nblk * sizeof(DeState))) ||
         (rc = ctx->sync.ensure((size_t)nblk * kSyncInts * sizeof(int))) ||
         (rc = ctx->rec.ensure((size_t)nblk * sizeof(FitRecord))) ||
-        (rc = ctx->hdesc.ensure(sizeof(BlockDesc) * nblk)) ||
+        (rc = ctx->hdesc.ensure(2 * sizeof(BlockDesc) * nblk)) ||
         (rc = ctx->hrec.ensure((size_t)nblk * sizeof(FitRecord))) ||
         (rc = ctx->hstate.ensure(2 * (size_t)nblk * sizeof(DeState))))
         return rc;
@@ -613,7 +640,38 @@ int prepare(pt_ctx* ctx, const pt_block* blocks, int nblk, const pt_de_settings*
         d.quartic = box_quartic(B.box);
         hd[b] = d;
     }
-    HIPCHK(hipMemcpyAsync(ctx->desc.p, hd, sizeof(BlockDesc) * nblk, hipMemcpyHostToDevice, s));
+    // objective launches: one over the main table, or (FP64 batches whose
+    // blocks differ in arithmetic) the phasor blocks and the others apart
+    pl->launches.clear();
+    auto add_launch = [&](int desc_off, int n, int mode, int64_t u) {
+        Plan::Launch L;
+        L.desc_off = desc_off;
+        L.nblk = n;
+        L.mode = mode;
+        L.total_units = (int)u;
+        L.grid = (int)((u + 7) / 8 * 8);
+        L.grid_lead = (int)((u + n + 7) / 8 * 8);
+        L.obj = objective_kernel(pl->dtype, pl->geo, mode, pl->slope);
+        pl->launches.push_back(L);
+    };
+    int ndesc = nblk;
+    if (nphasor == 0 || nphasor == nblk) {
+        add_launch(0, nblk, pl->mode, units);
+    } else {
+        for (int want = 1; want >= 0; --want) {
+            const int off = ndesc;
+            int64_t u = 0;
+            for (int b = 0; b < nblk; ++b) {
+                if (phasor[b] != want) continue;
+                BlockDesc d = hd[b];
+                d.unit_begin = (int)u;
+                u += (int64_t)d.ntiles * d.ngroups;
+                hd[ndesc++] = d;
+            }
+            add_launch(off, ndesc - off, want ? kModePhasor : kModePoly, u);
+        }
+    }
+    HIPCHK(hipMemcpyAsync(ctx->desc.p, hd, sizeof(BlockDesc) * ndesc, hipMemcpyHostToDevice, s));
     return PT_OK;
 }
 
@@ -650,7 +708,6 @@ int run_fit(pt_ctx* ctx, const pt_block* blocks, int nblk, const pt_de_settings*
     void* old_desc = ctx->desc.p;
     if ((rc = prepare(ctx, blocks, nblk, de, s, &pl, true))) return rc;
     if (ctx->desc.p != old_desc) ctx->drop_graphs();
-    ObjKernel obj = objective_kernel(pl.dtype, pl.geo, pl.mode, pl.slope);
     const BlockDesc* d = static_cast<const BlockDesc*>(ctx->desc.p);
 
     // persistent launch: one cooperative grid runs every generation
@@ -695,20 +752,22 @@ int run_fit(pt_ctx* ctx, const pt_block* blocks, int nblk, const pt_de_settings*
         }
     }
     ctx->last_launch = persistent ? PT_LAUNCH_PERSISTENT : PT_LAUNCH_GRAPH;
-    ctx->last_arith = pl.mode;
+    // (a batch split by arithmetic reports the phasor path, whose per-sample
+    // error is the larger)
+    ctx->last_arith = persistent || pl.launches.size() == 1 ? pl.mode : kModePhasor;
     ctx->last_fit_launches = persistent ? 1 : iters;
     if (persistent) {
         // nothing else to enqueue
     } else if (ctx->timing) {
         for (int k = 0; k < iters; ++k)
-            if ((rc = enqueue_generation(ctx, pl, obj, s, true, k))) return rc;
+            if ((rc = enqueue_generation(ctx, pl, s, true, k))) return rc;
     } else {
         hipGraphExec_t ex = nullptr;
         const int full = iters / kChunk, rem = iters % kChunk;
         DeState* hst = static_cast<DeState*>(ctx->hstate.p);
         bool all = false;
         for (int c = 0; c < full && !all; ++c) {
-            if ((c == 0 || lead) && (rc = get_graph(ctx, pl, obj, kChunk, c * kChunk, &ex))) return rc;
+            if ((c == 0 || lead) && (rc = get_graph(ctx, pl, kChunk, c * kChunk, &ex))) return rc;
             HIPCHK(hipGraphLaunch(ex, s));
             if (pl.window && c + 1 < full) {
                 // stop launching once every block has met its stop rule (the
@@ -721,7 +780,7 @@ int run_fit(pt_ctx* ctx, const pt_block* blocks, int nblk, const pt_de_settings*
             }
         }
         for (int k = 0; k < rem && !all; ++k)
-            if ((rc = enqueue_generation(ctx, pl, obj, s, false, full * kChunk + k))) return rc;
+            if ((rc = enqueue_generation(ctx, pl, s, false, full * kChunk + k))) return rc;
     }
     hipLaunchKernelGGL(k_finalize, dim3(nblk), dim3(64), 0, s, d, static_cast<FitRecord*>(ctx->rec.p));
     HIPCHK(hipGetLastError());

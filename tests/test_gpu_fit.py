@@ -217,3 +217,37 @@ def test_amplitude_slope_fit_matches_oracle():
     ref = _oracle_fit(b, b.de.max_gens)
     _compare(b, f, ref, 40, "slope")
     assert abs(f.coef[5] - x[5]) < 0.01
+
+
+def test_batch_splits_blocks_by_arithmetic():
+    # block 48 of the uneven batch has its carrier near 0 Hz, outside the
+    # phasor bounds; the others qualify.  The batch runs them as separate
+    # objective launches per generation, so every block gets the fit it gets
+    # alone, bit for bit, in every one-launch form.
+    blocks = synth.config3(0, nblocks=49, gens=20)
+    sel = [blocks[0], blocks[1], blocks[48]]
+    devs = [to_dev(b.samples) for b in sel]
+    pbs = [block_of(b, d) for b, d in zip(sel, devs)]
+    de = settings_of(sel[0])
+    c = ctx()
+    ptk.pt_ctx_set_tile(c.handle, 16, 8)  # one geometry (hence one summation order) for all fits
+    try:
+        alone = []
+        for pb in pbs:
+            f = c.fit_block(pb, de)
+            alone.append((f, ptk.pt_ctx_last_arithmetic(c.handle)))
+        assert [a for _, a in alone] == [ptk.PT_ARITH_FP64_PHASOR, ptk.PT_ARITH_FP64_PHASOR,
+                                         ptk.PT_ARITH_FP64_POLY]
+        for mode in (ptk.PT_FUSION_LEAD, ptk.PT_FUSION_LAST, ptk.PT_FUSION_OFF):
+            ptk.pt_ctx_set_step_fusion(c.handle, mode)
+            try:
+                batch = c.fit_batch(pbs, de)
+            finally:
+                ptk.pt_ctx_set_step_fusion(c.handle, ptk.PT_FUSION_AUTO)
+            for b, x, (y, _) in zip(sel, batch, alone):
+                assert list(x.coef) == list(y.coef) and x.objective == y.objective, (b.name, mode)
+    finally:
+        ptk.pt_ctx_set_tile(c.handle, 0, 0)
+    # the poly block against the oracle
+    ref = _oracle_fit(sel[2], 20)
+    assert_chi2_close([batch[2].objective], [ref["objective"]], sel[2].n)
