@@ -458,8 +458,9 @@ int pt_ctx_set_fp64_method(pt_ctx* ctx, int method);
  * How a fit's generations map onto launches (graph-replayed fits; the DE
  * step is that of Table 4, DE/rand/1/bin, in every form):
  * PT_FUSION_AUTO (default): PT_FUSION_LEAD when the launch's work units fit
- *   in one round of resident workgroups (at most four per compute unit: a
- *   latency-bound fit, such as one paper-scale block), else PT_FUSION_LAST
+ *   in one round of resident workgroups (the kernel's occupancy times the
+ *   compute units: a latency-bound fit, such as one paper-scale block), else
+ *   PT_FUSION_LAST
  *   (a throughput-bound batch, where the leading step's repeated work costs
  *   more than the last workgroup's wait).
  * PT_FUSION_LEAD (P <= 256): one launch per generation.  Every

@@ -196,11 +196,6 @@ PersistKernel persistent_kernel(int dtype, Geometry g, int mode, bool slope) {
     return dtype == PT_F64 ? ppick_spl<double>(g, mode, slope) : ppick_spl<float>(g, mode, slope);
 }
 
-// The phasor recurrence drops the cubic term inside a lane chunk and uses a
-// Taylor series for the second-difference rotation; it is exact to 1e-12
-// turns when (S - 1)^3 |f2| / (6 fs^3) <= 1e-12 and the chunk's second
-// difference 2 |b2| <= 1e-2 / (2 pi), with b2 = f1 / (2 fs^2) + f2 m / (2 fs^3)
-// over the block's sample offsets |m| <= n + |ref|.
 // Validity of the FP64 phasor path (see lane_rot) for every candidate with
 // f0 in [f0lo, f0hi], |f1| <= f1max, |f2| <= f2max, |f3| <= f3max and lane
 // anchors |m0| <= span samples from the reference (turns per sample^k:
@@ -320,6 +315,9 @@ struct pt_ctx {
         }
     };
     std::map<GraphKey, hipGraphExec_t> graphs;
+    // resident workgroups per compute unit of an objective kernel instance
+    // with the leading step's LDS, by (kernel, dynamic LDS bytes)
+    std::map<std::pair<const void*, size_t>, int> resident;
 
     void drop_graphs() {
         for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
@@ -549,9 +547,24 @@ int prepare(pt_ctx* ctx, const pt_block* blocks, int nblk, const pt_de_settings*
     pl->de_threads = pow2_at_least(P);  // >= 256 and >= P: also fixes the partial-sum order
     pl->de_lds = (size_t)P * kSlots * 8 + (size_t)pl->de_threads * (8 + 8 + 4);
     // leading step (2) for launches that fit in one round of resident
-    // workgroups (four per compute unit), last-workgroup step (1) for larger ones
+    // workgroups, last-workgroup step (1) for larger ones
     int fusion = ctx->step_fusion;
-    if (fusion == PT_FUSION_AUTO) fusion = units <= 4LL * ctx->ncu ? PT_FUSION_LEAD : PT_FUSION_LAST;
+    if (fusion == PT_FUSION_AUTO) {
+        const ObjKernel k = objective_kernel(pl->dtype, pl->geo, pl->mode, pl->slope);
+        const size_t lds = pl->de_lds + (size_t)P * kSlots * 8;
+        auto key = std::make_pair(reinterpret_cast<const void*>(k), lds);
+        auto it = ctx->resident.find(key);
+        int per_cu = 0;
+        if (it != ctx->resident.end()) {
+            per_cu = it->second;
+        } else {
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k), kThreads,
+                                                            lds) != hipSuccess)
+                per_cu = 0;
+            ctx->resident[key] = per_cu;
+        }
+        fusion = units + nblk <= (int64_t)per_cu * ctx->ncu ? PT_FUSION_LEAD : PT_FUSION_LAST;
+    }
     pl->fused = (with_state && fusion != PT_FUSION_OFF && pl->de_threads == (unsigned)kThreads)
                     ? (fusion == PT_FUSION_LAST ? 1 : 2)
                     : 0;
