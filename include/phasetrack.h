@@ -439,7 +439,7 @@ int pt_ctx_last_launch(pt_ctx* ctx, int* mode);
  * PT_FP64_AUTO (default): inside each lane's chunk of S samples the phasor
  *   exp(2 pi i Phi) follows from an exact FP64 anchor by a three-term
  *   recurrence for the linear phase and a first-order correction for the
- *   quadratic one (six operations per sample), wherever that is accurate to
+ *   quadratic one (five operations per sample), wherever that is accurate to
  *   2e-11 per sample for the whole box: the dropped cubic and quartic terms
  *   below 1e-12 turns, the quadratic correction's error below 1e-11, and
  *   the carrier at least S * 2.2e-4 / (2 pi) of fs away from 0 and fs / 2
@@ -458,7 +458,7 @@ int pt_ctx_set_fp64_method(pt_ctx* ctx, int method);
  * How a fit's generations map onto launches (graph-replayed fits; the DE
  * step is that of Table 4, DE/rand/1/bin, in every form):
  * PT_FUSION_AUTO (default): PT_FUSION_LEAD when the launch's work units fit
- *   in one round of resident workgroups (the kernel's occupancy times the
+ *   in two rounds of resident workgroups (the kernel's occupancy times the
  *   compute units: a latency-bound fit, such as one paper-scale block), else
  *   PT_FUSION_LAST
  *   (a throughput-bound batch, where the leading step's repeated work costs

@@ -287,10 +287,10 @@ __device__ __forceinline__ double lane_chi2_f64(const double (&sv)[S], const Anc
 //     grows by at most j ulp / |sin 2 pi b1|, held below 1e-12 by (3);
 //   - cos(2 pi Phi(j)) = Re(u_j) cos theta_j - Im(u_j) sin theta_j, taken as
 //     Re(u_j) - Im(u_j) theta_j, whose error theta^2 / 2 is bounded by (2).
-// Six FP64 operations per sample and candidate (two recurrence FMAs, theta,
-// the correction FMA, residual, square-accumulate) instead of a reduction
-// and a degree-10 cosine; u_0 and exp(2 pi i b1) come from the sine / cosine
-// polynomials of exactly reduced turns.
+// Five FP64 operations per sample and candidate (two recurrence FMAs, the
+// difference s - R, the correction FMA, square-accumulate; see lane_rot)
+// instead of a reduction and a degree-10 cosine; u_0 and exp(2 pi i b1) come
+// from the sine / cosine polynomials of exactly reduced turns.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void sincos_turns64(double r, double& c, double& sn) {
     const double u = r * r;
@@ -312,19 +312,28 @@ template <int S, bool TAIL, bool SLOPE, bool COR, int NC>
 __device__ __forceinline__ void lane_rot(const double (&sv)[S], const Anchor* an, const double* amp0,
                                          const double* ad, int valid, double* out) {
     static_assert(kSinDeg64 == kCosDeg64, "sine and cosine tables have one degree");
-    double pr[NC], pi[NC], cr[NC], ci[NC], c2[NC], th[NC], acc0[NC], acc1[NC];
+    // The recurrence is linear, so it carries scaled parts: R = g Re(u) and
+    // W = g theta Im(u), g = A when the amplitude is constant (else 1).  Then
+    // A cos(2 pi Phi(j)) = R_j - W_j j^2 and the residual is (s - R_j) + W_j j^2:
+    // five operations per sample (four for the correlation sum).
+    double rp[NC], wp[NC], r[NC], w[NC], c2[NC], acc0[NC], acc1[NC];
 #pragma unroll
     for (int q = 0; q < NC; ++q) {
-        double wr, wi;
-        sincos_turns64(an[q].b0, cr[q], ci[q]);  // u_0; b0 is already reduced to [-1/2, 1/2]
+        double cr, ci, wr, wi;
+        sincos_turns64(an[q].b0, cr, ci);  // u_0; b0 is already reduced to [-1/2, 1/2]
         double e = an[q].b1;
         e -= rint(e);
         sincos_turns64(e, wr, wi);  // exp(2 pi i b1)
         c2[q] = 2.0 * wr;
         // u_{-1} = u_0 exp(-2 pi i b1) starts the recurrence
-        pr[q] = __fma_rn(cr[q], wr, ci[q] * wi);
-        pi[q] = __fma_rn(ci[q], wr, -(cr[q] * wi));
-        th[q] = 6.283185307179586477 * an[q].b2;  // radians per j^2
+        const double pr = __fma_rn(cr, wr, ci * wi);
+        const double pi = __fma_rn(ci, wr, -(cr * wi));
+        const double g = SLOPE ? 1.0 : amp0[q];
+        const double gth = g * (6.283185307179586477 * an[q].b2);  // g theta, theta in radians per j^2
+        r[q] = g * cr;
+        rp[q] = g * pr;
+        w[q] = gth * ci;
+        wp[q] = gth * pi;
         acc0[q] = 0.0;
         acc1[q] = 0.0;
     }
@@ -333,22 +342,29 @@ __device__ __forceinline__ void lane_rot(const double (&sv)[S], const Anchor* an
 #pragma unroll
         for (int q = 0; q < NC; ++q) {
             if (j > 0) {
-                const double nr = __fma_rn(c2[q], cr[q], -pr[q]);
-                const double ni = __fma_rn(c2[q], ci[q], -pi[q]);
-                pr[q] = cr[q];
-                pi[q] = ci[q];
-                cr[q] = nr;
-                ci[q] = ni;
+                const double nr = __fma_rn(c2[q], r[q], -rp[q]);
+                const double nw = __fma_rn(c2[q], w[q], -wp[q]);
+                rp[q] = r[q];
+                wp[q] = w[q];
+                r[q] = nr;
+                w[q] = nw;
             }
-            // (Im(u) theta) j^2 with j^2 an immediate, so no per-sample product is hoisted into registers
-            const double zr = j == 0 ? cr[q] : __fma_rn(-(ci[q] * th[q]), (double)(j * j), cr[q]);
+            // j^2 is an immediate, so no per-sample constant is held in registers
+            const double k2 = (double)(j * j);
             double& acc = (j & 1) ? acc1[q] : acc0[q];
             if constexpr (COR) {
+                const double zr = j == 0 ? r[q] : __fma_rn(-w[q], k2, r[q]);
                 const double m = SLOPE ? __fma_rn(ad[q], (double)j, amp0[q]) * zr : zr;
                 acc = __fma_rn(sv[j], m, acc);
             } else {
-                const double amp = SLOPE ? __fma_rn(ad[q], (double)j, amp0[q]) : amp0[q];
-                const double rho = __fma_rn(-amp, zr, sv[j]);
+                double rho;
+                if constexpr (SLOPE) {
+                    const double zr = j == 0 ? r[q] : __fma_rn(-w[q], k2, r[q]);
+                    rho = __fma_rn(-__fma_rn(ad[q], (double)j, amp0[q]), zr, sv[j]);
+                } else {
+                    const double d = sv[j] - r[q];
+                    rho = j == 0 ? d : __fma_rn(w[q], k2, d);
+                }
                 if (TAIL) {
                     if (j < valid) acc = __fma_rn(rho, rho, acc);
                 } else {
@@ -358,7 +374,7 @@ __device__ __forceinline__ void lane_rot(const double (&sv)[S], const Anchor* an
         }
     }
 #pragma unroll
-    for (int q = 0; q < NC; ++q) out[q] = (COR && !SLOPE) ? amp0[q] * (acc0[q] + acc1[q]) : acc0[q] + acc1[q];
+    for (int q = 0; q < NC; ++q) out[q] = acc0[q] + acc1[q];
 }
 
 // ---------------------------------------------------------------------------

@@ -546,8 +546,11 @@ int prepare(pt_ctx* ctx, const pt_block* blocks, int nblk, const pt_de_settings*
     pl->grid_lead = (int)((units + nblk + 7) / 8 * 8);
     pl->de_threads = pow2_at_least(P);  // >= 256 and >= P: also fixes the partial-sum order
     pl->de_lds = (size_t)P * kSlots * 8 + (size_t)pl->de_threads * (8 + 8 + 4);
-    // leading step (2) for launches that fit in one round of resident
-    // workgroups, last-workgroup step (1) for larger ones
+    // leading step (2) for launches that fit in two rounds of resident
+    // workgroups, last-workgroup step (1) for larger ones (measured on the
+    // paper-scale block at 16 x 4, 981 units in two rounds of 768: 32.6 ms
+    // leading against 35.8 ms last-workgroup; a 64-block batch of 15 000
+    // units: 533 ms against 486 ms)
     int fusion = ctx->step_fusion;
     if (fusion == PT_FUSION_AUTO) {
         const ObjKernel k = objective_kernel(pl->dtype, pl->geo, pl->mode, pl->slope);
@@ -563,7 +566,7 @@ int prepare(pt_ctx* ctx, const pt_block* blocks, int nblk, const pt_de_settings*
                 per_cu = 0;
             ctx->resident[key] = per_cu;
         }
-        fusion = units + nblk <= (int64_t)per_cu * ctx->ncu ? PT_FUSION_LEAD : PT_FUSION_LAST;
+        fusion = units + nblk <= 2LL * per_cu * ctx->ncu ? PT_FUSION_LEAD : PT_FUSION_LAST;
     }
     pl->fused = (with_state && fusion != PT_FUSION_OFF && pl->de_threads == (unsigned)kThreads)
                     ? (fusion == PT_FUSION_LAST ? 1 : 2)
