@@ -272,6 +272,10 @@ struct pt_ctx {
     int device = 0;
     int ncu = 0;
     hipStream_t cap_stream = nullptr;
+    // second stream and fork / join events: the objective launches of a batch
+    // split by arithmetic run side by side (their blocks share nothing)
+    hipStream_t aux_stream = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     DevBuf desc, pop, trial, fpop, partials, hist, state, rec, staging, eval_pop, scratch, sync;
     PinBuf hdesc, hrec, hstate;
     // last fit (for pt_last_population / pt_last_history)
@@ -431,13 +435,25 @@ int enqueue_generation(pt_ctx* ctx, const Plan& pl, hipStream_t s, bool timed, i
     }
     if (pl.fused && !timed) {
         // the DE step runs in each block's last objective workgroup (1), or
-        // ahead of the objective in every workgroup (2 + launch index)
+        // ahead of the objective in every workgroup (2 + launch index); a
+        // second launch (blocks of the other arithmetic) runs beside the
+        // first on the auxiliary stream, forked from and joined back to s
         const int f = pl.fused == 2 ? 2 + L : 1;
-        for (const Plan::Launch& g : pl.launches) {
+        const bool fork = pl.launches.size() > 1;
+        if (fork) {
+            HIPCHK(hipEventRecord(ctx->ev_fork, s));
+            HIPCHK(hipStreamWaitEvent(ctx->aux_stream, ctx->ev_fork, 0));
+        }
+        for (size_t k = 0; k < pl.launches.size(); ++k) {
+            const Plan::Launch& g = pl.launches[k];
             const int grid = pl.fused == 2 ? g.grid_lead : g.grid;
-            hipLaunchKernelGGL(g.obj, dim3(grid), dim3(kThreads), pl.de_lds, s, d + g.desc_off, g.nblk,
-                               g.total_units, f);
+            hipLaunchKernelGGL(g.obj, dim3(grid), dim3(kThreads), pl.de_lds, k ? ctx->aux_stream : s,
+                               d + g.desc_off, g.nblk, g.total_units, f);
             HIPCHK(hipGetLastError());
+        }
+        if (fork) {
+            HIPCHK(hipEventRecord(ctx->ev_join, ctx->aux_stream));
+            HIPCHK(hipStreamWaitEvent(s, ctx->ev_join, 0));
         }
         return PT_OK;
     }
@@ -867,6 +883,9 @@ int pt_ctx_create(int device, pt_ctx** out) {
             break;
         }
     HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    HIPCHK(hipStreamCreateWithFlags(&c->aux_stream, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
     *out = c.release();
     return PT_OK;
 }
@@ -890,6 +909,9 @@ void pt_ctx_destroy(pt_ctx* ctx) {
     ctx->hseed.release();
     ctx->hstate.release();
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    if (ctx->aux_stream) (void)hipStreamDestroy(ctx->aux_stream);
+    if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
+    if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
     delete ctx;
 }
 
