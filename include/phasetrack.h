@@ -363,7 +363,10 @@ typedef struct {
     int32_t spl, cpg;           /* objective geometry; 0, 0 = default for 400K samples */
     int32_t range_rule;         /* PT_RUN_WARM or PT_RUN_EXTRAPOLATE */
     double warm_narrow;         /* box scale of warm starts, 0 (no warm start) .. 1 */
-    uint64_t hbm_budget_bytes;  /* device bytes resident blocks may hold */
+    uint64_t hbm_budget_bytes;  /* device bytes resident blocks may hold; a block of n samples
+                                   holds n * sizeof(sample) + (max_gens + 1) * 8 + 2 * (P * 136 +
+                                   P * ntiles * 8 + 48), ntiles = ceil(n / (256 * spl)): samples,
+                                   history and two slots of rows, objectives, partials and state */
     pt_de_settings de;          /* settings of every block (pop <= 256) */
     int32_t seed_first;         /* 1: seed each track's first box from its samples */
     int32_t seed_snippet;       /* pt_seed_opts.snippet (0 = default) */
@@ -388,6 +391,11 @@ typedef struct {
     double border_dfreq;
 } pt_server_result;
 
+/* Create a server on ctx.  Its generations run as objective + DE step
+ * launches, or, when the context's step fusion is PT_FUSION_LEAD at this
+ * call (and pop <= 256), as one leading-step launch per generation for every
+ * resident block; the choice holds for the server's lifetime.  Both give
+ * bit-identical fits. */
 int pt_server_create(pt_ctx* ctx, const pt_server_config* cfg, pt_server** out);
 
 /* Destroy a server (its queued and running blocks are dropped). */

@@ -67,7 +67,8 @@ struct BlockDesc {
     double* hist;      // max_gens + 1 best-so-far values
     DeState* st;       // may be null (bare objective evaluation)
     int* sync;         // persistent kernel: kSyncInts counters (see k_fit_persistent), or null
-    int gen_begin;     // persistent kernel: generation whose trial is ready at launch
+    int gen_begin;     // persistent kernel: generation whose trial is ready at launch; leading-step
+                       // form: the block's launch index at the launch's first step (0 for a fit)
     int objective;     // 0 = chi-square (Eq. 2-2-4), 1 = correlation (Eq. 2-2-5)
     int quartic;       // nonzero: the phase has the fourth-order term f3 (slot 6)
     int pad2;

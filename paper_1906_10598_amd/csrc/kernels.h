@@ -1237,11 +1237,12 @@ __device__ __forceinline__ int units_in_range(const BlockDesc* d, int x, int Ux,
 // (xst / xld), so the fences only order each wave's accesses around its
 // counter update.
 //
-// fused = 2 + L (fits with P <= 256): launch L of the leading-step form
-// (de_lead): every objective workgroup first runs the DE step of generation
-// L - 1 for itself, then evaluates its candidates of generation L; the grid
-// has one more unit per block (after the objective units) that keeps the
-// block's DE state.
+// fused = 2 + k (fits with P <= 256): the leading-step form (de_lead), launch
+// L = gen_begin + k of each block (gen_begin is 0 for a fit, a block's own
+// offset in the serving loop): every objective workgroup first runs the DE
+// step of generation L - 1 for itself, then evaluates its candidates of
+// generation L; the grid has one more unit per block (after the objective
+// units) that keeps the block's DE state.
 //
 // Dynamic LDS for fused != 0: the DE step's (P * kSlots + 2 * 256 doubles +
 // 256 ints), and P * kSlots doubles more for fused >= 2.
@@ -1258,7 +1259,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 4))
         // leading-step form: unit total_units + b keeps block b's DE state
         if (fused >= 2 && unit < total_units + nblk) {
             const float none[1] = {0.0f};
-            de_lead<CPG, true>(descs + (unit - total_units), fused - 2, 0, 0, cs, de_lds, none);
+            const BlockDesc* db = descs + (unit - total_units);
+            de_lead<CPG, true>(db, db->gen_begin + fused - 2, 0, 0, cs, de_lds, none);
         }
         return;
     }
@@ -1281,7 +1283,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 4))
         // type until then (fewer registers across the step)
         T raw[S];
         load_lane_raw<T, S>(d, tile, raw);
-        const int L = fused - 2;  // the launch's index within the fit
+        const int L = d->gen_begin + fused - 2;  // the block's launch index (gen_begin: its offset)
         if (!de_lead<CPG, false>(d, L, tile, group, cs, de_lds, raw)) return;
         finish_lane<V, T, S>(d, tile, raw, sv, full, valid);
         objective_unit<S, CPG, MODE, SLOPE>(d, tile, group, sv, full, valid, cs, red, nullptr,

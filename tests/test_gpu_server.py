@@ -122,10 +122,18 @@ def test_warm_start_tracks_the_phase():
     print(f"[server warm] generations cold {cold} warm mean {np.mean(warm):.0f}", flush=True)
 
 
+def _slot_bytes(n, spl=16, P=40):
+    # bytes a resident block holds (pt_server_config.hbm_budget_bytes)
+    ntiles = -(-n // (256 * spl))
+    return n * 4 + (GENS + 1) * 8 + 2 * (P * 136 + P * ntiles * 8 + 48)
+
+
 def test_tiny_budget_admits_one_at_a_time():
     items = _stream(ntracks=3, nblocks=5, seed=3)
     ref, _ = _serve(items)
-    budget = 830_000  # room for one 200 000-sample block (827 560 B), not for two 100 000-sample ones
+    # room for one 200 000-sample block, not for two 100 000-sample ones
+    assert _slot_bytes(200_000) < 2 * _slot_bytes(100_000)
+    budget = (_slot_bytes(200_000) + 2 * _slot_bytes(100_000)) // 2
     small, max_active = _serve(items, budget=budget)
     assert max_active == 1
     for k in ref:
@@ -143,3 +151,20 @@ def test_full_queue_is_busy():
         assert ptk.pt_server_stats(srv)[1] == 2
     finally:
         ptk.pt_server_destroy(srv)
+
+
+def test_leading_step_server_equals_default():
+    # a server created under PT_FUSION_LEAD runs one leading-step launch per
+    # generation (each block at its own launch index); its fits must equal
+    # the default two-launch server's bit for bit
+    items = _stream(ntracks=3, nblocks=6, seed=5)
+    ref, _ = _serve(items)
+    c = ctx()
+    ptk.pt_ctx_set_step_fusion(c.handle, ptk.PT_FUSION_LEAD)
+    try:
+        lead, max_active = _serve(items)
+    finally:
+        ptk.pt_ctx_set_step_fusion(c.handle, ptk.PT_FUSION_AUTO)
+    assert max_active >= 2
+    for k in ref:
+        assert _key(ref[k]) == _key(lead[k]), k
