@@ -467,8 +467,9 @@ int pt_ctx_set_fp64_method(pt_ctx* ctx, int method);
  * step is that of Table 4, DE/rand/1/bin, in every form):
  * PT_FUSION_AUTO (default): PT_FUSION_LEAD when the launch's work units fit
  *   in two rounds of resident workgroups (the kernel's occupancy times the
- *   compute units: a latency-bound fit, such as one paper-scale block), else
- *   PT_FUSION_LAST
+ *   compute units: a latency-bound fit, such as one paper-scale block) and
+ *   max_gens <= 20000 (the leading form keeps one captured graph per 50
+ *   generations), else PT_FUSION_LAST
  *   (a throughput-bound batch, where the leading step's repeated work costs
  *   more than the last workgroup's wait).
  * PT_FUSION_LEAD (P <= 256): one launch per generation.  Every

@@ -46,6 +46,7 @@ int fail(int code, const char* fmt, ...) {
     } while (0)
 
 constexpr int kChunk = 50;  // generations per captured graph
+constexpr int kMaxLeadGens = 20000;  // longest fit PT_FUSION_AUTO runs in the leading-step form
 // the leading-step form takes a launch's buffer slot from its parity, so every
 // graph must start at an even launch
 static_assert(kChunk % 2 == 0, "graph chunks must hold an even number of launches");
@@ -585,10 +586,14 @@ int prepare(pt_ctx* ctx, const pt_block* blocks, int nblk, const pt_de_settings*
     // paper-scale block at 16 x 4, 981 units in two rounds of 768: 32.6 ms
     // leading against 35.8 ms last-workgroup; a 64-block batch of 15 000
     // units: 533 ms against 486 ms)
+    // (the leading form keeps one graph per 50-launch chunk, since the launch
+    // index is a kernel argument: fits longer than kMaxLeadGens generations
+    // use the last-workgroup form, whose graph is replayed)
     int fusion = ctx->step_fusion;
     if (fusion == PT_FUSION_AUTO)
-        fusion = lead_fits(ctx, objective_kernel(pl->dtype, pl->geo, pl->mode, pl->slope),
-                           pl->de_lds + (size_t)P * kSlots * 8, units + nblk)
+        fusion = de->max_gens <= kMaxLeadGens &&
+                         lead_fits(ctx, objective_kernel(pl->dtype, pl->geo, pl->mode, pl->slope),
+                                   pl->de_lds + (size_t)P * kSlots * 8, units + nblk)
                      ? PT_FUSION_LEAD
                      : PT_FUSION_LAST;
     pl->fused = (with_state && fusion != PT_FUSION_OFF && pl->de_threads == (unsigned)kThreads)
