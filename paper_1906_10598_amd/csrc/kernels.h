@@ -1246,7 +1246,10 @@ __device__ __forceinline__ int units_in_range(const BlockDesc* d, int x, int Ux,
 //
 // Dynamic LDS for fused != 0: the DE step's (P * kSlots + 2 * 256 doubles +
 // 256 ints), and P * kSlots doubles more for fused >= 2.
-template <typename T, int S, int CPG, int MODE, bool SLOPE>
+// LEAD: the instance for the leading-step form (fused >= 2 only); the other
+// forms use the instance without it, which needs fewer registers (four waves
+// per SIMD instead of three).
+template <typename T, int S, int CPG, int MODE, bool SLOPE, bool LEAD>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_objective(
     const BlockDesc* __restrict__ descs, int nblk, int total_units, int fused) {
     const int nwg = gridDim.x;  // multiple of 8
@@ -1257,17 +1260,19 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 4))
     extern __shared__ double de_lds[];
     if (unit >= total_units) {
         // leading-step form: unit total_units + b keeps block b's DE state
-        if (fused >= 2 && unit < total_units + nblk) {
-            const float none[1] = {0.0f};
-            const BlockDesc* db = descs + (unit - total_units);
-            de_lead<CPG, true>(db, db->gen_begin + fused - 2, 0, 0, cs, de_lds, none);
+        if constexpr (LEAD) {
+            if (unit < total_units + nblk) {
+                const float none[1] = {0.0f};
+                const BlockDesc* db = descs + (unit - total_units);
+                de_lead<CPG, true>(db, db->gen_begin + fused - 2, 0, 0, cs, de_lds, none);
+            }
         }
         return;
     }
     const BlockDesc* __restrict__ d = descs + find_block(descs, nblk, unit);
     // (the leading-step form reads its stop state inside de_lead, which must
     // also run after a stop to copy the state forward)
-    if (fused < 2 && d->st != nullptr && d->st->done) return;
+    if (!LEAD && d->st != nullptr && d->st->done) return;
     const int local = unit - d->unit_begin;
     const int tile = local / d->ngroups;
     const int group = local - tile * d->ngroups;
@@ -1278,7 +1283,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 4))
     V sv[S];
     bool full;
     int valid;
-    if (fused >= 2) {
+    if constexpr (LEAD) {
         // the samples' loads overlap the DE step's; they stay in their stored
         // type until then (fewer registers across the step)
         T raw[S];
@@ -1288,41 +1293,42 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 4))
         finish_lane<V, T, S>(d, tile, raw, sv, full, valid);
         objective_unit<S, CPG, MODE, SLOPE>(d, tile, group, sv, full, valid, cs, red, nullptr,
                                             (L & 1) ? d->partials2 : d->partials);
-        return;
-    }
-    load_lane<V, T, S>(d, tile, sv, full, valid);
-    objective_unit<S, CPG, MODE, SLOPE>(d, tile, group, sv, full, valid, cs, red, d->trial, d->partials);
-    if (!fused) return;
+    } else {
+        load_lane<V, T, S>(d, tile, sv, full, valid);
+        objective_unit<S, CPG, MODE, SLOPE>(d, tile, group, sv, full, valid, cs, red, d->trial, d->partials);
+        if (!fused) return;
 
-    int* sync = d->sync;
-    const int xcd = bid & 7;
-    __syncthreads();  // every wave's partial stores are issued
-    // (one counter per block instead of per XCD range: fits 30 % slower on MI355X,
-    // the same-address atomics from all XCDs serialise)
-    if (threadIdx.x == 0) {
-        const int nx = units_in_range(d, xcd, Ux, total_units);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, PT_REL_SCOPE);
-        const int old = __hip_atomic_fetch_add(sync + xcd * kSyncLine, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        bool last = false;
-        if (old == nx - 1) {
-            int nranges = 0;
-            for (int x = 0; x < 8; ++x) nranges += units_in_range(d, x, Ux, total_units) > 0;
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, PT_ACQ_SCOPE);
+        int* sync = d->sync;
+        const int xcd = bid & 7;
+        __syncthreads();  // every wave's partial stores are issued
+        // (one counter per block instead of per XCD range: fits 30 % slower on MI355X,
+        // the same-address atomics from all XCDs serialise)
+        if (threadIdx.x == 0) {
+            const int nx = units_in_range(d, xcd, Ux, total_units);
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, PT_REL_SCOPE);
-            const int old2 =
-                __hip_atomic_fetch_add(sync + 16 * kSyncLine, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            last = old2 == nranges - 1;
-            if (last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, PT_ACQ_SCOPE);
+            const int old =
+                __hip_atomic_fetch_add(sync + xcd * kSyncLine, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            bool last = false;
+            if (old == nx - 1) {
+                int nranges = 0;
+                for (int x = 0; x < 8; ++x) nranges += units_in_range(d, x, Ux, total_units) > 0;
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, PT_ACQ_SCOPE);
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, PT_REL_SCOPE);
+                const int old2 =
+                    __hip_atomic_fetch_add(sync + 16 * kSyncLine, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                last = old2 == nranges - 1;
+                if (last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, PT_ACQ_SCOPE);
+            }
+            s_last = last;
         }
-        s_last = last;
+        __syncthreads();
+        if (!s_last) return;
+        de_step_body<false, true>(d, de_lds);
+        __syncthreads();
+        if (threadIdx.x < 8) __hip_atomic_store(sync + threadIdx.x * kSyncLine, 0, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+        if (threadIdx.x == 8) __hip_atomic_store(sync + 16 * kSyncLine, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    __syncthreads();
-    if (!s_last) return;
-    de_step_body<false, true>(d, de_lds);
-    __syncthreads();
-    if (threadIdx.x < 8) __hip_atomic_store(sync + threadIdx.x * kSyncLine, 0, __ATOMIC_RELAXED,
-                                            __HIP_MEMORY_SCOPE_AGENT);
-    if (threadIdx.x == 8) __hip_atomic_store(sync + 16 * kSyncLine, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 

@@ -124,39 +124,41 @@ using ObjKernel = void (*)(const BlockDesc*, int, int, int);
 enum { kModePoly = PT_ARITH_FP64_POLY, kModeMixed = PT_ARITH_MIXED, kModePhasor = PT_ARITH_FP64_PHASOR };
 
 template <typename T, int S, int C, int M>
-ObjKernel pick_slope(bool slope) {
-    return slope ? k_objective<T, S, C, M, true> : k_objective<T, S, C, M, false>;
+ObjKernel pick_slope(bool slope, bool lead) {
+    if (lead) return slope ? k_objective<T, S, C, M, true, true> : k_objective<T, S, C, M, false, true>;
+    return slope ? k_objective<T, S, C, M, true, false> : k_objective<T, S, C, M, false, false>;
 }
 
 template <typename T, int S, int C>
-ObjKernel pick_mode(int mode, bool slope) {
-    if (mode == kModeMixed) return pick_slope<T, S, C, kModeMixed>(slope);
-    if (mode == kModePhasor) return pick_slope<T, S, C, kModePhasor>(slope);
-    return pick_slope<T, S, C, kModePoly>(slope);
+ObjKernel pick_mode(int mode, bool slope, bool lead) {
+    if (mode == kModeMixed) return pick_slope<T, S, C, kModeMixed>(slope, lead);
+    if (mode == kModePhasor) return pick_slope<T, S, C, kModePhasor>(slope, lead);
+    return pick_slope<T, S, C, kModePoly>(slope, lead);
 }
 
 template <typename T, int S>
-ObjKernel pick_cpg(int cpg, int mode, bool slope) {
+ObjKernel pick_cpg(int cpg, int mode, bool slope, bool lead) {
     switch (cpg) {
-        case 1: return pick_mode<T, S, 1>(mode, slope);
-        case 2: return pick_mode<T, S, 2>(mode, slope);
-        case 4: return pick_mode<T, S, 4>(mode, slope);
-        default: return pick_mode<T, S, 8>(mode, slope);
+        case 1: return pick_mode<T, S, 1>(mode, slope, lead);
+        case 2: return pick_mode<T, S, 2>(mode, slope, lead);
+        case 4: return pick_mode<T, S, 4>(mode, slope, lead);
+        default: return pick_mode<T, S, 8>(mode, slope, lead);
     }
 }
 
 template <typename T>
-ObjKernel pick_spl(Geometry g, int mode, bool slope) {
+ObjKernel pick_spl(Geometry g, int mode, bool slope, bool lead) {
     switch (g.spl) {
-        case 4: return pick_cpg<T, 4>(g.cpg, mode, slope);
-        case 8: return pick_cpg<T, 8>(g.cpg, mode, slope);
-        case 16: return pick_cpg<T, 16>(g.cpg, mode, slope);
-        default: return pick_cpg<T, 32>(g.cpg, mode, slope);
+        case 4: return pick_cpg<T, 4>(g.cpg, mode, slope, lead);
+        case 8: return pick_cpg<T, 8>(g.cpg, mode, slope, lead);
+        case 16: return pick_cpg<T, 16>(g.cpg, mode, slope, lead);
+        default: return pick_cpg<T, 32>(g.cpg, mode, slope, lead);
     }
 }
 
-ObjKernel objective_kernel(int dtype, Geometry g, int mode, bool slope) {
-    return dtype == PT_F64 ? pick_spl<double>(g, mode, slope) : pick_spl<float>(g, mode, slope);
+// lead: the instance of the leading-step form (launched with fused >= 2)
+ObjKernel objective_kernel(int dtype, Geometry g, int mode, bool slope, bool lead = false) {
+    return dtype == PT_F64 ? pick_spl<double>(g, mode, slope, lead) : pick_spl<float>(g, mode, slope, lead);
 }
 
 using PersistKernel = void (*)(const BlockDesc*, int, int, int, int, int*, uint64_t);
@@ -592,7 +594,7 @@ int prepare(pt_ctx* ctx, const pt_block* blocks, int nblk, const pt_de_settings*
     int fusion = ctx->step_fusion;
     if (fusion == PT_FUSION_AUTO)
         fusion = de->max_gens <= kMaxLeadGens &&
-                         lead_fits(ctx, objective_kernel(pl->dtype, pl->geo, pl->mode, pl->slope),
+                         lead_fits(ctx, objective_kernel(pl->dtype, pl->geo, pl->mode, pl->slope, true),
                                    pl->de_lds + (size_t)P * kSlots * 8, units + nblk)
                      ? PT_FUSION_LEAD
                      : PT_FUSION_LAST;
@@ -695,7 +697,7 @@ int prepare(pt_ctx* ctx, const pt_block* blocks, int nblk, const pt_de_settings*
         L.total_units = (int)u;
         L.grid = (int)((u + 7) / 8 * 8);
         L.grid_lead = (int)((u + n + 7) / 8 * 8);
-        L.obj = objective_kernel(pl->dtype, pl->geo, mode, pl->slope);
+        L.obj = objective_kernel(pl->dtype, pl->geo, mode, pl->slope, pl->fused == 2);
         pl->launches.push_back(L);
     };
     int ndesc = nblk;
@@ -1841,7 +1843,7 @@ int pt_server_step(pt_server* sv, void* hip_stream, int32_t* n_active, int32_t* 
         if (launches.empty() || kernel_key(act[q]) != kernel_key(act[launches.back().first])) {
             const auto key = kernel_key(act[q]);
             launches.push_back({q, 0, 0, objective_kernel(std::get<1>(key), sv->geo, std::get<0>(key),
-                                                          std::get<2>(key) != 0)});
+                                                          std::get<2>(key) != 0, lead)});
         }
         Launch& L = launches.back();
         BlockDesc d;
