@@ -1398,8 +1398,12 @@ int pt_ctx_autotune(pt_ctx* ctx, int64_t n, int P, int precision, void* hip_stre
         const size_t cnt = (size_t)std::min<int64_t>((int64_t)hs.size(), n - off);
         HIPCHK(hipMemcpy(static_cast<float*>(ctx->scratch.p) + off, hs.data(), cnt * 4, hipMemcpyHostToDevice));
     }
-    // a box around one carrier with the paper's widths (so the FP64 path uses
-    // the arithmetic it uses in a fit of a paper-scale box)
+    // a box around one carrier with the paper's widths and the largest drift
+    // rate and drift acceleration of the paper-scale synthetic blocks
+    // (5 Hz/s, 0.05 Hz/s^2), so that every
+    // geometry is timed with the arithmetic the phasor bounds allow it at the
+    // edge of a paper-scale box; a geometry whose bounds only hold for slow
+    // drifts would otherwise win here and run the per-sample cosine in a fit
     pt_block b;
     std::memset(&b, 0, sizeof b);
     b.samples = ctx->scratch.p;
@@ -1408,8 +1412,8 @@ int pt_ctx_autotune(pt_ctx* ctx, int64_t n, int P, int precision, void* hip_stre
     b.on_device = 1;
     b.fs = 50000.0;
     b.ref = NAN;
-    const double lo[PT_NSLOT] = {0.8, 0.0, 1000.0, 0.4, -0.01, 0.0, 0.0};
-    const double hi[PT_NSLOT] = {1.2, 6.28, 1001.0, 0.6, 0.01, 0.0, 0.0};
+    const double lo[PT_NSLOT] = {0.8, 0.0, 1000.0, 4.8, -0.05, 0.0, 0.0};
+    const double hi[PT_NSLOT] = {1.2, 6.28, 1001.0, 5.0, 0.05, 0.0, 0.0};
     for (int j = 0; j < PT_NSLOT; ++j) {
         b.box.lo[j] = lo[j];
         b.box.hi[j] = hi[j];
