@@ -504,8 +504,10 @@ int pt_ctx_last_fit_launches(pt_ctx* ctx, int64_t* launches);
 /* ---- instrumentation ---- */
 
 /* Turn per-kernel timing of the objective kernel on (1) or off (0).  While
- * on, fits launch kernels one by one (no graph replay) and bracket every
- * objective launch with HIP events on the fit's stream. */
+ * on, fits launch kernels one by one (no graph replay), each generation as
+ * the objective alone and then the DE step whatever the step-fusion
+ * setting, and bracket every objective launch with HIP events on the fit's
+ * stream; results are bit-identical to those of the other forms. */
 int pt_ctx_set_timing(pt_ctx* ctx, int on);
 
 /* Launch count and summed duration [ms] of objective-kernel launches timed

@@ -263,7 +263,8 @@ struct Plan {
         int nblk;
         int mode;
         int total_units, grid, grid_lead;
-        ObjKernel obj;
+        ObjKernel obj;       // objective alone, or with the last-workgroup step
+        ObjKernel obj_lead;  // leading-step instance (null unless that form is planned)
     };
     std::vector<Launch> launches;
 };
@@ -450,7 +451,8 @@ int enqueue_generation(pt_ctx* ctx, const Plan& pl, hipStream_t s, bool timed, i
         for (size_t k = 0; k < pl.launches.size(); ++k) {
             const Plan::Launch& g = pl.launches[k];
             const int grid = pl.fused == 2 ? g.grid_lead : g.grid;
-            hipLaunchKernelGGL(g.obj, dim3(grid), dim3(kThreads), pl.de_lds, k ? ctx->aux_stream : s,
+            hipLaunchKernelGGL(pl.fused == 2 ? g.obj_lead : g.obj, dim3(grid), dim3(kThreads), pl.de_lds,
+                               k ? ctx->aux_stream : s,
                                d + g.desc_off, g.nblk, g.total_units, f);
             HIPCHK(hipGetLastError());
         }
@@ -460,6 +462,8 @@ int enqueue_generation(pt_ctx* ctx, const Plan& pl, hipStream_t s, bool timed, i
         }
         return PT_OK;
     }
+    // (objective alone, then the DE step: the timed path, and the form
+    // without fusion)
     for (const Plan::Launch& g : pl.launches) {
         hipLaunchKernelGGL(g.obj, dim3(g.grid), dim3(kThreads), 0, s, d + g.desc_off, g.nblk, g.total_units, 0);
         HIPCHK(hipGetLastError());
@@ -697,7 +701,8 @@ int prepare(pt_ctx* ctx, const pt_block* blocks, int nblk, const pt_de_settings*
         L.total_units = (int)u;
         L.grid = (int)((u + 7) / 8 * 8);
         L.grid_lead = (int)((u + n + 7) / 8 * 8);
-        L.obj = objective_kernel(pl->dtype, pl->geo, mode, pl->slope, pl->fused == 2);
+        L.obj = objective_kernel(pl->dtype, pl->geo, mode, pl->slope, false);
+        L.obj_lead = pl->fused == 2 ? objective_kernel(pl->dtype, pl->geo, mode, pl->slope, true) : nullptr;
         pl->launches.push_back(L);
     };
     int ndesc = nblk;

@@ -105,3 +105,22 @@ def test_stop_at_generation_zero_and_no_generations(mode):
 def test_invalid_fusion_mode():
     with pytest.raises(ptk.PtError):
         ptk.pt_ctx_set_step_fusion(ctx().handle, 4)
+
+
+@pytest.mark.parametrize("mode", FORMS)
+def test_timed_fit_equals_two_launch_form(mode):
+    # with per-launch timing on, every form runs the objective alone and then
+    # the DE step (events bracket the objective launches): the leading-step
+    # instance must not be the one launched there
+    b = synth.config1(0)
+    dev = to_dev(b.samples)
+    de = settings_of(b, gens=120)
+    c = ctx()
+    ptk.pt_ctx_set_timing(c.handle, True)
+    try:
+        a = _fit(mode, [block_of(b, dev)], de)
+        nl, ms = ptk.pt_ctx_kernel_stats(c.handle)
+    finally:
+        ptk.pt_ctx_set_timing(c.handle, False)
+    assert nl == de.max_gens + 1 and ms > 0.0
+    _same(a, _fit(ptk.PT_FUSION_OFF, [block_of(b, dev)], de), f"timed fusion {mode} paper")
