@@ -11,8 +11,9 @@ be bit-identical: coefficients, objectives, flags, generations, final
 populations and the best-so-far history.  Covered: the tiny block in both
 precisions, the paper-scale block, a batch of uneven blocks sharing each
 launch, the window stop rule with blocks stopping at different generations
-(in both launch parities), a stop at generation 0 (value to reach) and a
-fit with no generation after the initial one.
+(in both launch parities), a stop at generation 0 (value to reach), a
+fit with no generation after the initial one, and fits with per-launch
+timing on (which run every form as the objective alone plus the DE step).
 """
 import numpy as np
 import pytest
