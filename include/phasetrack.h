@@ -529,7 +529,7 @@ int pt_ctx_get_tile(pt_ctx* ctx, int64_t n, int P, int precision, int* samples_p
 
 /* Force a chunk geometry for every later fit in this context (0, 0 = back
  * to the tuned/default choice).  Supported samples_per_lane: 4, 8, 16, 32;
- * cand_per_group: 1, 2, 4, 5, 8. */
+ * cand_per_group: 1, 2, 4, 8. */
 int pt_ctx_set_tile(pt_ctx* ctx, int samples_per_lane, int cand_per_group);
 
 /* Time every supported geometry on a block of n samples and population P
