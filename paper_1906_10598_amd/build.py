@@ -1,28 +1,64 @@
-"""Build libphasetrack.so (HIP, gfx950) in-tree with hipcc."""
+"""Build libphasetrack.so (HIP, gfx950) in-tree with hipcc.
+
+The runtime (csrc/phasetrack.hip) and the kernel instances (csrc/instances.hip,
+once per sample type and samples-per-lane value) are compiled as separate
+objects in parallel, then linked into one shared library.
+"""
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "csrc", "phasetrack.hip")
+CSRC = os.path.join(HERE, "csrc")
+SRC = os.path.join(CSRC, "phasetrack.hip")
+INST = os.path.join(CSRC, "instances.hip")
 LIB = os.path.join(HERE, "libphasetrack.so")
+OBJ_DIR = os.path.join(HERE, "_build")
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
     "-O3",
     "-std=c++17",
     "-fPIC",
-    "-shared",
     # keep the compiler from forming packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall",
     "-Wno-unused-function",
 ]
 
+# (sample type, name, samples per lane) of every instance unit
+INSTANCES = [(t, tn, s) for t, tn in (("float", "f32"), ("double", "f64")) for s in (4, 8, 16, 32)]
+
+
+def _jobs() -> int:
+    try:
+        n = int(os.environ.get("MAX_JOBS", "0"))
+    except ValueError:
+        n = 0
+    return max(1, min(n or (os.cpu_count() or 1), 16))
+
 
 def build(verbose: bool = False, extra=None) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    cmd = [hipcc] + HIPCC_FLAGS + (extra or []) + [SRC, "-o", LIB + ".tmp"]
+    os.makedirs(OBJ_DIR, exist_ok=True)
+    units = [(SRC, os.path.join(OBJ_DIR, "phasetrack.o"), [])]
+    for t, tn, s in INSTANCES:
+        units.append((INST, os.path.join(OBJ_DIR, f"instances_{tn}_s{s}.o"),
+                      [f"-DPT_INST_T={t}", f"-DPT_INST_TN={tn}", f"-DPT_INST_S={s}"]))
+
+    def compile_one(u):
+        src, obj, defs = u
+        cmd = [hipcc] + HIPCC_FLAGS + (extra or []) + defs + ["-c", src, "-o", obj + ".tmp"]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
+        os.replace(obj + ".tmp", obj)
+        return obj
+
+    with ThreadPoolExecutor(max_workers=_jobs()) as ex:
+        objs = list(ex.map(compile_one, units))
+    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC"] + objs + ["-o", LIB + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -651,12 +651,14 @@ __device__ __forceinline__ double reduce_partials(const BlockDesc* __restrict__ 
 
 // out[p] = objective of candidate p (bare evaluation, no DE state); one
 // workgroup of the DE step's size, NT doubles of dynamic LDS.
+#ifndef PT_INSTANCE_TU  // (the instance translation units hold only templates)
 __global__ void k_reduce_out(const BlockDesc* __restrict__ descs, double* __restrict__ out) {
     extern __shared__ double red[];
     const BlockDesc* d = descs;
     const double v = reduce_partials<false>(d, d->partials, red);
     if ((int)threadIdx.x < d->P) out[threadIdx.x] = v;
 }
+#endif
 
 // ---------------------------------------------------------------------------
 // DE: initial population (generation 0), one workgroup per block.
@@ -709,10 +711,12 @@ __device__ __forceinline__ void init_block(const BlockDesc* __restrict__ d) {
         for (int k = i; k < kSyncInts; k += blockDim.x) d->sync[k] = 0;  // gen_begin is 0 here
 }
 
+#ifndef PT_INSTANCE_TU  // (the instance translation units hold only templates)
 __global__ void k_de_init(const BlockDesc* __restrict__ descs, int* __restrict__ err) {
     if (err != nullptr && blockIdx.x == 0 && threadIdx.x == 0) *err = 0;
     init_block(descs + blockIdx.x);
 }
+#endif
 
 // (f, index) pair order of the argmin: smaller objective, then smaller index.
 __device__ __forceinline__ bool better(double fa, int ia, double fb, int ib) {
@@ -924,10 +928,12 @@ __device__ __forceinline__ void de_step_body(const BlockDesc* __restrict__ d, do
     for (int j = 0; j < kStride; ++j) xst(trow + j, y[j]);
 }
 
+#ifndef PT_INSTANCE_TU  // (the instance translation units hold only templates)
 __global__ __launch_bounds__(1024) void k_de_step(const BlockDesc* __restrict__ descs) {
     extern __shared__ double lds[];
     de_step_body<false, false>(descs + blockIdx.x, lds);
 }
+#endif
 
 // ---------------------------------------------------------------------------
 // Leading DE step (fits with P <= 256, blockDim = 256).  Launch L of a fit
@@ -1425,19 +1431,23 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 4))
 
 // Restart the persistent kernel's per-launch counters of every block and
 // set its ready copies to the generation the launch starts from.
+#ifndef PT_INSTANCE_TU  // (the instance translation units hold only templates)
 __global__ void k_sync_reset(const BlockDesc* __restrict__ descs) {
     const BlockDesc* d = descs + blockIdx.x;
     if (d->sync == nullptr) return;
     for (int k = threadIdx.x; k < kSyncInts; k += blockDim.x)
         d->sync[k] = (k >= 8 * kSyncLine && k < 16 * kSyncLine) ? d->gen_begin : 0;
 }
+#endif
 
 // Initial population of the blocks flagged fresh (BlockDesc::pad0 != 0);
 // the others keep their running state.  Used by the serving loop.
+#ifndef PT_INSTANCE_TU  // (the instance translation units hold only templates)
 __global__ void k_de_init_fresh(const BlockDesc* __restrict__ descs) {
     const BlockDesc* d = descs + blockIdx.x;
     if (d->pad0) init_block(d);
 }
+#endif
 
 // ---------------------------------------------------------------------------
 // Final record of each block: best member, objective, generations, flags
@@ -1451,6 +1461,7 @@ struct FitRecord {
     int flags;
 };
 
+#ifndef PT_INSTANCE_TU  // (the instance translation units hold only templates)
 __global__ void k_finalize(const BlockDesc* __restrict__ descs, FitRecord* __restrict__ out) {
     const BlockDesc* d = descs + blockIdx.x;
     // leading-step form: the final state is the slot whose stop flag is set
@@ -1478,5 +1489,6 @@ __global__ void k_finalize(const BlockDesc* __restrict__ descs, FitRecord* __res
     r.flags = flags;
     out[blockIdx.x] = r;
 }
+#endif
 
 }  // namespace pt

@@ -20,10 +20,12 @@
 #include <vector>
 
 #include "../../include/phasetrack.h"
+#include "instances.h"
 #include "kernels.h"
 #include "seed.h"
 
 using namespace pt;
+
 
 namespace {
 
@@ -118,85 +120,31 @@ int size_class(int64_t n) {
 }
 
 // ----------------------------------------------------------------- launchers
-using ObjKernel = void (*)(const BlockDesc*, int, int, int);
-
-// Kernel arithmetic modes (template argument MODE of the kernels).
-enum { kModePoly = PT_ARITH_FP64_POLY, kModeMixed = PT_ARITH_MIXED, kModePhasor = PT_ARITH_FP64_PHASOR };
-
-template <typename T, int S, int C, int M>
-ObjKernel pick_slope(bool slope, bool lead) {
-    if (lead) return slope ? k_objective<T, S, C, M, true, true> : k_objective<T, S, C, M, false, true>;
-    return slope ? k_objective<T, S, C, M, true, false> : k_objective<T, S, C, M, false, false>;
-}
-
-template <typename T, int S, int C>
-ObjKernel pick_mode(int mode, bool slope, bool lead) {
-    if (mode == kModeMixed) return pick_slope<T, S, C, kModeMixed>(slope, lead);
-    if (mode == kModePhasor) return pick_slope<T, S, C, kModePhasor>(slope, lead);
-    return pick_slope<T, S, C, kModePoly>(slope, lead);
-}
-
-template <typename T, int S>
-ObjKernel pick_cpg(int cpg, int mode, bool slope, bool lead) {
-    switch (cpg) {
-        case 1: return pick_mode<T, S, 1>(mode, slope, lead);
-        case 2: return pick_mode<T, S, 2>(mode, slope, lead);
-        case 4: return pick_mode<T, S, 4>(mode, slope, lead);
-        default: return pick_mode<T, S, 8>(mode, slope, lead);
-    }
-}
-
-template <typename T>
-ObjKernel pick_spl(Geometry g, int mode, bool slope, bool lead) {
-    switch (g.spl) {
-        case 4: return pick_cpg<T, 4>(g.cpg, mode, slope, lead);
-        case 8: return pick_cpg<T, 8>(g.cpg, mode, slope, lead);
-        case 16: return pick_cpg<T, 16>(g.cpg, mode, slope, lead);
-        default: return pick_cpg<T, 32>(g.cpg, mode, slope, lead);
-    }
-}
-
 // lead: the instance of the leading-step form (launched with fused >= 2)
 ObjKernel objective_kernel(int dtype, Geometry g, int mode, bool slope, bool lead = false) {
-    return dtype == PT_F64 ? pick_spl<double>(g, mode, slope, lead) : pick_spl<float>(g, mode, slope, lead);
-}
-
-using PersistKernel = void (*)(const BlockDesc*, int, int, int, int, int*, uint64_t);
-
-template <typename T, int S, int C, int M>
-PersistKernel ppick_slope(bool slope) {
-    return slope ? k_fit_persistent<T, S, C, M, true> : k_fit_persistent<T, S, C, M, false>;
-}
-
-template <typename T, int S, int C>
-PersistKernel ppick_mode(int mode, bool slope) {
-    if (mode == kModeMixed) return ppick_slope<T, S, C, kModeMixed>(slope);
-    if (mode == kModePhasor) return ppick_slope<T, S, C, kModePhasor>(slope);
-    return ppick_slope<T, S, C, kModePoly>(slope);
-}
-
-template <typename T, int S>
-PersistKernel ppick_cpg(int cpg, int mode, bool slope) {
-    switch (cpg) {
-        case 1: return ppick_mode<T, S, 1>(mode, slope);
-        case 2: return ppick_mode<T, S, 2>(mode, slope);
-        case 4: return ppick_mode<T, S, 4>(mode, slope);
-        default: return ppick_mode<T, S, 8>(mode, slope);
-    }
-}
-
-template <typename T>
-PersistKernel ppick_spl(Geometry g, int mode, bool slope) {
+    const bool f64 = dtype == PT_F64;
     switch (g.spl) {
-        case 4: return ppick_cpg<T, 4>(g.cpg, mode, slope);
-        case 8: return ppick_cpg<T, 8>(g.cpg, mode, slope);
-        case 16: return ppick_cpg<T, 16>(g.cpg, mode, slope);
-        default: return ppick_cpg<T, 32>(g.cpg, mode, slope);
+        case 4: return f64 ? objective_kernel_f64_s4(g.cpg, mode, slope, lead)
+                           : objective_kernel_f32_s4(g.cpg, mode, slope, lead);
+        case 8: return f64 ? objective_kernel_f64_s8(g.cpg, mode, slope, lead)
+                           : objective_kernel_f32_s8(g.cpg, mode, slope, lead);
+        case 16: return f64 ? objective_kernel_f64_s16(g.cpg, mode, slope, lead)
+                            : objective_kernel_f32_s16(g.cpg, mode, slope, lead);
+        default: return f64 ? objective_kernel_f64_s32(g.cpg, mode, slope, lead)
+                            : objective_kernel_f32_s32(g.cpg, mode, slope, lead);
     }
 }
 
 PersistKernel persistent_kernel(int dtype, Geometry g, int mode, bool slope) {
-    return dtype == PT_F64 ? ppick_spl<double>(g, mode, slope) : ppick_spl<float>(g, mode, slope);
+    const bool f64 = dtype == PT_F64;
+    switch (g.spl) {
+        case 4: return f64 ? persistent_kernel_f64_s4(g.cpg, mode, slope) : persistent_kernel_f32_s4(g.cpg, mode, slope);
+        case 8: return f64 ? persistent_kernel_f64_s8(g.cpg, mode, slope) : persistent_kernel_f32_s8(g.cpg, mode, slope);
+        case 16:
+            return f64 ? persistent_kernel_f64_s16(g.cpg, mode, slope) : persistent_kernel_f32_s16(g.cpg, mode, slope);
+        default:
+            return f64 ? persistent_kernel_f64_s32(g.cpg, mode, slope) : persistent_kernel_f32_s32(g.cpg, mode, slope);
+    }
 }
 
 // Validity of the FP64 phasor path (see lane_rot) for every candidate with
@@ -280,7 +228,7 @@ struct pt_ctx {
     // split by arithmetic run side by side (their blocks share nothing)
     hipStream_t aux_stream = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-    DevBuf desc, pop, trial, fpop, partials, hist, state, rec, staging, eval_pop, scratch, sync;
+    DevBuf desc, pop, trial, fpop, partials, hist, state, rec, staging, eval_pop, tune_block, sync;
     PinBuf hdesc, hrec, hstate;
     // last fit (for pt_last_population / pt_last_history)
     int last_nblk = 0, last_P = 0, last_maxg = 0;
@@ -535,6 +483,41 @@ bool lead_fits(pt_ctx* ctx, ObjKernel k, size_t lds, int64_t units) {
     return units <= 2LL * per_cu * ctx->ncu;
 }
 
+// Descriptor fields of one block that do not depend on where its buffers
+// live: samples (the caller's pointer), sizes, box, active slots and the DE
+// settings.  Buffer pointers, unit_begin and sync are left null / zero.
+BlockDesc base_desc(const pt_block& B, const pt_de_settings* de, int ntiles, int groups) {
+    BlockDesc d;
+    std::memset(&d, 0, sizeof d);
+    d.samples = B.samples;
+    d.n = B.n;
+    d.fs = B.fs;
+    d.ref = block_ref(&B);
+    d.dtype = B.dtype;
+    d.P = de->pop;
+    int D = 0;
+    for (int j = 0; j < kSlots; ++j) {
+        d.lo[j] = B.box.lo[j];
+        d.hi[j] = B.box.hi[j];
+        if (B.box.lo[j] < B.box.hi[j]) d.act[D++] = j;
+    }
+    d.D = D;
+    d.ntiles = ntiles;
+    d.ngroups = groups;
+    d.window = de->window;
+    d.max_gens = de->max_gens;
+    d.F = de->F;
+    d.CR = de->CR;
+    d.vtr = de->vtr;
+    d.rel_tol = de->rel_tol;
+    d.seed = de->seed;
+    d.stream = B.stream;
+    d.gen_begin = 0;
+    d.objective = de->objective;
+    d.quartic = box_quartic(B.box);
+    return d;
+}
+
 int prepare(pt_ctx* ctx, const pt_block* blocks, int nblk, const pt_de_settings* de, hipStream_t s, Plan* pl,
             bool with_state) {
     const int P = de->pop;
@@ -636,40 +619,15 @@ int prepare(pt_ctx* ctx, const pt_block* blocks, int nblk, const pt_de_settings*
     int unit_off = 0;
     for (int b = 0; b < nblk; ++b) {
         const pt_block& B = blocks[b];
-        BlockDesc d;
-        std::memset(&d, 0, sizeof d);
+        BlockDesc d = base_desc(B, de, ntiles[b], groups);
         const size_t bytes = (size_t)B.n * (B.dtype == PT_F64 ? 8 : 4);
-        if (B.on_device) {
-            d.samples = B.samples;
-        } else {
+        if (!B.on_device) {
             HIPCHK(hipMemcpyAsync(stage + stage_off, B.samples, bytes, hipMemcpyHostToDevice, s));
             d.samples = stage + stage_off;
             stage_off += (bytes + 255) & ~(size_t)255;
         }
-        d.n = B.n;
-        d.fs = B.fs;
-        d.ref = block_ref(&B);
-        d.dtype = B.dtype;
-        d.P = P;
-        int D = 0;
-        for (int j = 0; j < kSlots; ++j) {
-            d.lo[j] = B.box.lo[j];
-            d.hi[j] = B.box.hi[j];
-            if (B.box.lo[j] < B.box.hi[j]) d.act[D++] = j;
-        }
-        d.D = D;
-        d.ntiles = ntiles[b];
-        d.ngroups = groups;
         d.unit_begin = unit_off;
         unit_off += ntiles[b] * groups;
-        d.window = de->window;
-        d.max_gens = de->max_gens;
-        d.F = de->F;
-        d.CR = de->CR;
-        d.vtr = de->vtr;
-        d.rel_tol = de->rel_tol;
-        d.seed = de->seed;
-        d.stream = B.stream;
         d.pop = pop + (size_t)b * P * kStride;
         d.trial = trial + (size_t)b * P * kStride;
         d.fpop = fpop + (size_t)b * P;
@@ -685,9 +643,6 @@ int prepare(pt_ctx* ctx, const pt_block* blocks, int nblk, const pt_de_settings*
             d.st2 = d.st + nblk;
         }
         d.sync = with_state ? static_cast<int*>(ctx->sync.p) + (size_t)b * kSyncInts : nullptr;
-        d.gen_begin = 0;
-        d.objective = de->objective;
-        d.quartic = box_quartic(B.box);
         hd[b] = d;
     }
     // objective launches: one over the main table, or (FP64 batches whose
@@ -920,7 +875,7 @@ void pt_ctx_destroy(pt_ctx* ctx) {
         (void)hipEventDestroy(pr.second);
     }
     DevBuf* bufs[] = {&ctx->desc,    &ctx->pop,      &ctx->trial,   &ctx->fpop,  &ctx->partials, &ctx->hist,
-                      &ctx->state,   &ctx->rec,      &ctx->staging, &ctx->eval_pop, &ctx->scratch, &ctx->errflag,
+                      &ctx->state,   &ctx->rec,      &ctx->staging, &ctx->eval_pop, &ctx->tune_block, &ctx->errflag,
                       &ctx->sync,    &ctx->seed_out, &ctx->seed_stage};
     for (DevBuf* b : bufs) b->release();
     ctx->hdesc.release();
@@ -961,43 +916,59 @@ __global__ void k_pack_rows(const double* __restrict__ src, double* __restrict__
     }
 }
 
-static int eval_setup(pt_ctx* ctx, const pt_block* block, const double* pop, int P, int precision, int objective,
-                      hipStream_t s, Plan* pl, ObjKernel* obj) {
+// Extents of a population that decide the objective's arithmetic: the
+// amplitude-slope and quartic terms are on when any row uses them, and the
+// FP64 phasor path applies when every row satisfies its bound.  Rows are
+// added in any number of pieces.
+struct PopExtents {
+    double lo[2] = {0.0, 0.0}, hi[2] = {0.0, 0.0};  // slots 5 and 6 (zero rows excluded)
+    double f0lo = INFINITY, f0hi = -INFINITY, f1 = 0.0, f2 = 0.0, f3 = 0.0;
+    void add(const double* rows, int n) {
+        for (int p = 0; p < n; ++p) {
+            const double* r = rows + (size_t)p * PT_NSLOT;
+            for (int k = 0; k < 2; ++k) {
+                const double v = r[5 + k];
+                if (v != 0.0 || !std::isfinite(v)) {
+                    lo[k] = std::min(lo[k], v);
+                    hi[k] = std::max(hi[k], v);
+                    if (!std::isfinite(v)) hi[k] = 1.0;  // keep the term on; the result is not finite anyway
+                }
+            }
+            f0lo = std::min(f0lo, r[2]);
+            f0hi = std::max(f0hi, r[2]);
+            f1 = std::max(f1, std::fabs(r[3]));
+            f2 = std::max(f2, std::fabs(r[4]));
+            f3 = std::max(f3, std::fabs(r[6]));
+        }
+    }
+    // the block as the objective kernels see it: slots 5 and 6 span the rows
+    void apply(pt_block& blk) const {
+        for (int k = 0; k < 2; ++k) {
+            blk.box.lo[5 + k] = std::isfinite(lo[k]) ? lo[k] : -1.0;
+            blk.box.hi[5 + k] = std::isfinite(hi[k]) ? hi[k] : 1.0;
+        }
+    }
+    int mode(const Plan& pl, const pt_ctx* ctx, const pt_block* block) const {
+        if (pl.mixed || ctx->fp64_method == PT_FP64_POLY) return pl.mode;
+        const double span = (double)block->n + std::fabs(block_ref(block));
+        return std::isfinite(f1) && std::isfinite(f2) && std::isfinite(f3) &&
+                       phasor_ok(pl.geo.spl, block->fs, span, f0lo, f0hi, f1, f2, f3)
+                   ? kModePhasor
+                   : kModePoly;
+    }
+};
+
+static int check_eval_args(const pt_block* block, const double* pop, int P, int precision, int objective) {
     int rc = check_block(block, 0);
     if (rc) return rc;
     if (!pop) return fail(PT_EINVAL, "pop is null");
     if (P < 1 || P > PT_MAX_POP) return fail(PT_EINVAL, "P = %d outside [1, %d]", P, PT_MAX_POP);
     if (precision != PT_PREC_FP64 && precision != PT_PREC_MIXED) return fail(PT_EINVAL, "precision %d", precision);
     if (objective != PT_OBJ_CHI2 && objective != PT_OBJ_COR) return fail(PT_EINVAL, "objective %d", objective);
-    HIPCHK(hipSetDevice(ctx->device));
-    // The population decides the arithmetic (it may leave the box): the
-    // amplitude-slope and quartic terms are on when any row uses them, and
-    // the FP64 phasor path when every row satisfies its bound.
-    std::vector<double> hp((size_t)P * PT_NSLOT);
-    HIPCHK(hipMemcpyAsync(hp.data(), pop, hp.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    pt_block blk = *block;
-    double f1 = 0.0, f2 = 0.0, f3 = 0.0, f0lo = INFINITY, f0hi = -INFINITY;
-    for (int j : {5, 6}) {
-        double lo = 0.0, hi = 0.0;
-        for (int p = 0; p < P; ++p) {
-            const double v = hp[(size_t)p * PT_NSLOT + j];
-            if (v != 0.0 || !std::isfinite(v)) {
-                lo = std::min(lo, v);
-                hi = std::max(hi, v);
-                if (!std::isfinite(v)) hi = 1.0;  // keep the term on; the result is not finite anyway
-            }
-        }
-        blk.box.lo[j] = std::isfinite(lo) ? lo : -1.0;
-        blk.box.hi[j] = std::isfinite(hi) ? hi : 1.0;
-    }
-    for (int p = 0; p < P; ++p) {
-        f0lo = std::min(f0lo, hp[(size_t)p * PT_NSLOT + 2]);
-        f0hi = std::max(f0hi, hp[(size_t)p * PT_NSLOT + 2]);
-        f1 = std::max(f1, std::fabs(hp[(size_t)p * PT_NSLOT + 3]));
-        f2 = std::max(f2, std::fabs(hp[(size_t)p * PT_NSLOT + 4]));
-        f3 = std::max(f3, std::fabs(hp[(size_t)p * PT_NSLOT + 6]));
-    }
+    return PT_OK;
+}
+
+static pt_de_settings eval_settings(int P, int precision, int objective) {
     pt_de_settings de;
     std::memset(&de, 0, sizeof de);
     de.pop = P;
@@ -1006,6 +977,22 @@ static int eval_setup(pt_ctx* ctx, const pt_block* block, const double* pop, int
     de.CR = 0.5;
     de.precision = precision;
     de.objective = objective;
+    return de;
+}
+
+static int eval_setup(pt_ctx* ctx, const pt_block* block, const double* pop, int P, int precision, int objective,
+                      hipStream_t s, Plan* pl, ObjKernel* obj) {
+    int rc = check_eval_args(block, pop, P, precision, objective);
+    if (rc) return rc;
+    HIPCHK(hipSetDevice(ctx->device));
+    std::vector<double> hp((size_t)P * PT_NSLOT);
+    HIPCHK(hipMemcpyAsync(hp.data(), pop, hp.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    PopExtents ext;
+    ext.add(hp.data(), P);
+    pt_block blk = *block;
+    ext.apply(blk);
+    pt_de_settings de = eval_settings(P, precision, objective);
     void* old_desc = ctx->desc.p;
     if ((rc = prepare(ctx, &blk, 1, &de, s, pl, false))) return rc;
     if (ctx->desc.p != old_desc) ctx->drop_graphs();
@@ -1014,13 +1001,7 @@ static int eval_setup(pt_ctx* ctx, const pt_block* block, const double* pop, int
     // the profiler on this runtime)
     hipLaunchKernelGGL(k_pack_rows, dim3(1), dim3(256), 0, s, pop, hd[0].trial, P);
     HIPCHK(hipGetLastError());
-    if (!pl->mixed && ctx->fp64_method != PT_FP64_POLY) {
-        const double span = (double)block->n + std::fabs(block_ref(block));
-        pl->mode = std::isfinite(f1) && std::isfinite(f2) && std::isfinite(f3) &&
-                           phasor_ok(pl->geo.spl, block->fs, span, f0lo, f0hi, f1, f2, f3)
-                       ? kModePhasor
-                       : kModePoly;
-    }
+    pl->mode = ext.mode(*pl, ctx, block);
     *obj = objective_kernel(pl->dtype, pl->geo, pl->mode, pl->slope);
     ctx->last_arith = pl->mode;
     return PT_OK;
@@ -1396,12 +1377,12 @@ int pt_ctx_autotune(pt_ctx* ctx, int64_t n, int P, int precision, void* hip_stre
     HIPCHK(hipSetDevice(ctx->device));
     // synthetic FP32 block (values only matter for timing)
     int rc;
-    if ((rc = ctx->scratch.ensure((size_t)n * 4))) return rc;
+    if ((rc = ctx->tune_block.ensure((size_t)n * 4))) return rc;
     std::vector<float> hs((size_t)std::min<int64_t>(n, 1 << 20));
     for (size_t k = 0; k < hs.size(); ++k) hs[k] = (float)std::cos(0.37 * (double)k);
     for (int64_t off = 0; off < n; off += (int64_t)hs.size()) {
         const size_t cnt = (size_t)std::min<int64_t>((int64_t)hs.size(), n - off);
-        HIPCHK(hipMemcpy(static_cast<float*>(ctx->scratch.p) + off, hs.data(), cnt * 4, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(static_cast<float*>(ctx->tune_block.p) + off, hs.data(), cnt * 4, hipMemcpyHostToDevice));
     }
     // a box around one carrier with the paper's widths and the largest drift
     // rate and drift acceleration of the paper-scale synthetic blocks
@@ -1411,7 +1392,7 @@ int pt_ctx_autotune(pt_ctx* ctx, int64_t n, int P, int precision, void* hip_stre
     // drifts would otherwise win here and run the per-sample cosine in a fit
     pt_block b;
     std::memset(&b, 0, sizeof b);
-    b.samples = ctx->scratch.p;
+    b.samples = ctx->tune_block.p;
     b.n = n;
     b.dtype = PT_F32;
     b.on_device = 1;

@@ -37,7 +37,9 @@ def _declared():
 def test_every_declared_symbol_is_exported():
     names = _declared()
     assert len(names) >= 18
-    lib = ctypes.CDLL(ptk.LIB_PATH)
+    # immediate binding: every symbol the library needs (the kernel-instance
+    # units included) must resolve at load time
+    lib = ctypes.CDLL(ptk.LIB_PATH, mode=os.RTLD_NOW)
     missing = [n for n in names if not hasattr(lib, n)]
     assert not missing, missing
 
