@@ -209,6 +209,30 @@ int pt_fit_batch(pt_ctx* ctx, const pt_block* blocks, int nblk, const pt_de_sett
 int pt_objective(pt_ctx* ctx, const pt_block* block, const double* pop, int P,
                  int precision, int objective, void* hip_stream, double* out);
 
+/* Bytes of the fixed device array pt_objective_noalloc works in: one copy per
+ * device the library runs on, held until the process ends. */
+#define PT_NOALLOC_SCRATCH_BYTES (4u << 20)
+
+/* pt_objective for callers that cannot allocate: it calls no hipMalloc,
+ * hipFree or other allocating routine (tight serving loops, harnesses that
+ * forbid device allocation).  Arguments, results and the arithmetic are those
+ * of pt_objective (same kernels, same geometry, bit-identical outputs); the
+ * caller still owns pop and out.
+ *   - The descriptor, the packed rows and the P x ceil(n / (256 S)) tile
+ *     partial sums (S = samples per lane of the chosen geometry) live in the
+ *     library's fixed array of PT_NOALLOC_SCRATCH_BYTES bytes; a call that
+ *     needs more (roughly P x n > 2e9 samples at 16 samples per lane) fails with
+ *     PT_EINVAL and a message giving the size it needed.
+ *   - block.samples must be a device pointer (on_device = 1), else PT_EINVAL.
+ *   - Every call on one device uses that device's single array, which keeps
+ *     the last call's contents (every word a call reads it writes first).
+ *     Calls that overlap on one device -- from two host threads, or two
+ *     streams -- race on it and must be serialised by the caller.
+ *   - Returns after out is written (the stream is synchronised), as
+ *     pt_objective does; it cannot be captured into a HIP graph. */
+int pt_objective_noalloc(pt_ctx* ctx, const pt_block* block, const double* pop, int P,
+                         int precision, int objective, void* hip_stream, double* out);
+
 /* Final population and objectives of block `index` of the context's most
  * recent pt_fit_block / pt_fit_batch call.  pop_host: P x PT_NSLOT FP64; fpop_host:
  * P FP64 (either may be NULL); P must equal that call's population size. */

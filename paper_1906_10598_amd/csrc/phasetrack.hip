@@ -26,6 +26,12 @@
 
 using namespace pt;
 
+// Device memory of pt_objective_noalloc: the block descriptor, the packed
+// population rows and the tile partial sums of one call.  Each device the
+// library runs on holds its own copy for the life of the process; host code
+// reaches it only through the address hipGetSymbolAddress gives for the
+// current device (pt_ctx::noalloc), never through this name.
+static __device__ __align__(256) unsigned char scratch[PT_NOALLOC_SCRATCH_BYTES];
 
 namespace {
 
@@ -255,6 +261,8 @@ struct pt_ctx {
     // geometry
     Geometry forced{0, 0};
     std::map<std::tuple<int, int, int>, Geometry> tuned;  // (size class, P, mixed)
+    // this device's copy of the allocation-free entry point's array
+    unsigned char* noalloc = nullptr;
     // graph cache
     struct GraphKey {
         void* desc;
@@ -843,6 +851,10 @@ int pt_ctx_create(int device, pt_ctx** out) {
     if (!c) return fail(PT_ENOMEM, "out of host memory");
     c->device = device;
     c->ncu = prop.multiProcessorCount;
+    // the allocation-free entry point's array: its address on this device
+    void* na = nullptr;
+    HIPCHK(hipGetSymbolAddress(&na, HIP_SYMBOL(scratch)));
+    c->noalloc = static_cast<unsigned char*>(na);
     int clk_khz = 0;
     if (hipDeviceGetAttribute(&clk_khz, hipDeviceAttributeWallClockRate, device) != hipSuccess || clk_khz <= 0)
         clk_khz = 100000;
@@ -1022,6 +1034,88 @@ int pt_objective(pt_ctx* ctx, const pt_block* block, const double* pop, int P, i
     hipLaunchKernelGGL(k_reduce_out, dim3(1), dim3(pl.de_threads), pl.de_threads * sizeof(double), s, d, out);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(s));
+    return PT_OK;
+}
+
+// One descriptor into device memory, passed by value (no host staging).
+__global__ void k_put_desc(BlockDesc d, BlockDesc* dst) {
+    if (threadIdx.x == 0) *dst = d;
+}
+
+int pt_objective_noalloc(pt_ctx* ctx, const pt_block* block, const double* pop, int P, int precision,
+                         int objective, void* hip_stream, double* out) {
+    if (!ctx) return fail(PT_EINVAL, "ctx is null");
+    if (!out) return fail(PT_EINVAL, "out is null");
+    int rc = check_eval_args(block, pop, P, precision, objective);
+    if (rc) return rc;
+    if (!block->on_device) return fail(PT_EINVAL, "pt_objective_noalloc: samples must be a device pointer");
+    if (!ctx->noalloc) return fail(PT_EDEVICE, "pt_objective_noalloc: no device array on this context");
+    HIPCHK(hipSetDevice(ctx->device));
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+
+    // population extents (the arithmetic choice of pt_objective), read in
+    // pieces through a fixed host buffer
+    constexpr int kRows = 64;
+    double rows_h[kRows * PT_NSLOT];
+    PopExtents ext;
+    for (int r0 = 0; r0 < P; r0 += kRows) {
+        const int cnt = std::min(kRows, P - r0);
+        HIPCHK(hipMemcpyAsync(rows_h, pop + (size_t)r0 * PT_NSLOT, sizeof(double) * PT_NSLOT * cnt,
+                              hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        ext.add(rows_h, cnt);
+    }
+    pt_block blk = *block;
+    ext.apply(blk);
+    const pt_de_settings de = eval_settings(P, precision, objective);
+
+    // the plan pt_objective's set-up makes for one block without DE state
+    Plan pl;
+    pl.nblk = 1;
+    pl.P = P;
+    pl.dtype = blk.dtype;
+    pl.mixed = precision == PT_PREC_MIXED;
+    pl.slope = blk.box.lo[5] != 0.0 || blk.box.hi[5] != 0.0;
+    pl.geo = choose_geometry(ctx, blk.n, P, pl.mixed);
+    pl.mode = pl.mixed ? kModeMixed : kModePoly;
+    pl.mode = ext.mode(pl, ctx, block);
+    const int64_t tile = (int64_t)kThreads * pl.geo.spl;
+    const int groups = (P + pl.geo.cpg - 1) / pl.geo.cpg;
+    const int64_t ntiles = (blk.n + tile - 1) / tile;
+    const int64_t units = ntiles * groups;
+    pl.de_threads = pow2_at_least(P);
+
+    // layout in the array: descriptor | rows (P x kStride) | partials (P x ntiles)
+    constexpr size_t kDescBytes = 1024;
+    static_assert(sizeof(BlockDesc) <= kDescBytes, "descriptor slot too small");
+    const size_t row_bytes = ((size_t)P * kStride * sizeof(double) + 255) & ~(size_t)255;
+    const size_t need = kDescBytes + row_bytes + (size_t)P * (size_t)ntiles * sizeof(double);
+    if (need > (size_t)PT_NOALLOC_SCRATCH_BYTES)
+        return fail(PT_EINVAL,
+                    "pt_objective_noalloc: P = %d and n = %lld need %zu bytes of device memory, more than the "
+                    "%zu-byte array (P x ceil(n / %lld) partial sums must fit)",
+                    P, (long long)blk.n, need, (size_t)PT_NOALLOC_SCRATCH_BYTES, (long long)tile);
+    BlockDesc* dd = reinterpret_cast<BlockDesc*>(ctx->noalloc);
+    double* rows = reinterpret_cast<double*>(ctx->noalloc + kDescBytes);
+    double* part = reinterpret_cast<double*>(ctx->noalloc + kDescBytes + row_bytes);
+    BlockDesc d = base_desc(blk, &de, (int)ntiles, groups);
+    d.trial = rows;
+    d.pop = rows;
+    d.partials = part;
+
+    const ObjKernel obj = objective_kernel(pl.dtype, pl.geo, pl.mode, pl.slope);
+    hipLaunchKernelGGL(k_put_desc, dim3(1), dim3(64), 0, s, d, dd);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(k_pack_rows, dim3(1), dim3(256), 0, s, pop, rows, P);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(obj, dim3((unsigned)((units + 7) / 8 * 8)), dim3(kThreads), 0, s, (const BlockDesc*)dd, 1,
+                       (int)units, 0);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(k_reduce_out, dim3(1), dim3(pl.de_threads), pl.de_threads * sizeof(double), s,
+                       (const BlockDesc*)dd, out);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
+    ctx->last_arith = pl.mode;
     return PT_OK;
 }
 

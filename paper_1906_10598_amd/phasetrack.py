@@ -17,6 +17,7 @@ from typing import Optional, Sequence
 
 NSLOT = 7  # A, phi0, f0, f1, f2, Adot, f3
 MAX_POP = 1024
+PT_NOALLOC_SCRATCH_BYTES = 4 << 20  # device array of pt_objective_noalloc
 PT_OK, PT_EINVAL, PT_ENOMEM, PT_EDEVICE, PT_EBUSY, PT_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 PT_F32, PT_F64 = 0, 1
 PT_PREC_FP64, PT_PREC_MIXED = 0, 1
@@ -173,6 +174,7 @@ def _signatures(L):
         "pt_fit_batch": ([_CTX, ctypes.POINTER(pt_block), i32, ctypes.POINTER(pt_de_settings), _VP,
                           ctypes.POINTER(pt_fit)], i32),
         "pt_objective": ([_CTX, ctypes.POINTER(pt_block), _VP, i32, i32, i32, _VP, _VP], i32),
+        "pt_objective_noalloc": ([_CTX, ctypes.POINTER(pt_block), _VP, i32, i32, i32, _VP, _VP], i32),
         "pt_last_population": ([_CTX, i32, _DP, _DP, i32], i32),
         "pt_last_history": ([_CTX, i32, _DP, i32, ctypes.POINTER(i32)], i32),
         "pt_phase": ([ctypes.POINTER(pt_fit), _DP, i64, _DP, _DP, _DP, _DP], i32),
@@ -267,6 +269,12 @@ def pt_objective(ctx, block: pt_block, pop_ptr: int, P: int, precision: int, out
                  objective: int = PT_OBJ_CHI2):
     _check(lib().pt_objective(ctx, ctypes.byref(block), pop_ptr, P, precision, objective, stream, out_ptr),
            "pt_objective")
+
+
+def pt_objective_noalloc(ctx, block: pt_block, pop_ptr: int, P: int, precision: int, out_ptr: int, stream=None,
+                         objective: int = PT_OBJ_CHI2):
+    _check(lib().pt_objective_noalloc(ctx, ctypes.byref(block), pop_ptr, P, precision, objective, stream,
+                                      out_ptr), "pt_objective_noalloc")
 
 
 def pt_last_population(ctx, index: int, P: int):
