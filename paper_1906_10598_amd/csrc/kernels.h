@@ -273,24 +273,39 @@ __device__ __forceinline__ double lane_chi2_f64(const double (&sv)[S], const Anc
 }
 
 // ---------------------------------------------------------------------------
-// FP64 phasor lane accumulation.  Within one lane chunk the phase is
-// Phi(j) = b0 + b1 j + b2 j^2 + (b3 j^3 + b4 j^4) turns, j < S.  The host
-// selects this path only where, for every candidate of the box,
-//   (1) the dropped terms (S - 1)^3 |b3| + (S - 1)^4 |b4| stay below 1e-12 turns,
-//   (2) theta = 2 pi b2 (S - 1)^2 satisfies theta^2 / 2 <= 1e-11, and
-//   (3) the local frequency b1 stays at least S * 2.2e-4 / (2 pi) turns away
-//       from 0 and 1/2 (|sin 2 pi b1| >= S * 2.2e-4).
-// Then exp(2 pi i Phi(j)) = u_j g_j with u_j = exp(2 pi i (b0 + b1 j)) and
-// g_j = exp(i theta_j), theta_j = 2 pi b2 j^2:
+// FP64 phasor lane accumulation.  A lane's chunk of S samples is expanded
+// about its centre: with j = 0..S-1 the sample index in the chunk and
+// C = S / 2, the phase is
+//   Phi(j) = c0 + c1 (j - C) + c2 (j - C)^2 + (c3 (j - C)^3 + c4 (j - C)^4) turns.
+// The host selects this path only where, for every candidate of the box,
+//   (1) the dropped terms C^3 |c3| + C^4 |c4| stay below 1e-12 turns,
+//   (2) theta = 2 pi |c2| C^2 satisfies theta^2 / 2 <= 1e-11,
+//   (3) the local frequency c1 stays at least S * 2.2e-4 / (2 pi) turns away
+//       from 0 and 1/2 (|sin 2 pi c1| >= S * 2.2e-4), and
+//   (4) across a tile the local frequency moves by at most 6e-3 / (2 pi)
+//       turns (the small-angle rotation below).
+// Then exp(2 pi i Phi(j)) = u_j g_j with u_j = exp(2 pi i (c0 + c1 (j - C)))
+// and g_j = exp(i theta_j), theta_j = 2 pi c2 (j - C)^2:
 //   - both parts of u_j follow the real three-term (Chebyshev) recurrence
-//     u_{j+1} = 2 cos(2 pi b1) u_j - u_{j-1}, one FMA each; its rounding
-//     grows by at most j ulp / |sin 2 pi b1|, held below 1e-12 by (3);
+//     u_{j+1} = 2 cos(2 pi c1) u_j - u_{j-1}, one FMA each; its rounding
+//     grows by at most j ulp / |sin 2 pi c1|, held below 1e-12 by (3);
 //   - cos(2 pi Phi(j)) = Re(u_j) cos theta_j - Im(u_j) sin theta_j, taken as
 //     Re(u_j) - Im(u_j) theta_j, whose error theta^2 / 2 is bounded by (2).
 // Five FP64 operations per sample and candidate (two recurrence FMAs, the
-// difference s - R, the correction FMA, square-accumulate; see lane_rot)
-// instead of a reduction and a degree-10 cosine; u_0 and exp(2 pi i b1) come
-// from the sine / cosine polynomials of exactly reduced turns.
+// difference s - R, the correction FMA, square-accumulate) instead of a
+// reduction and a degree-10 cosine.
+//
+// Per (lane, candidate) set-up.  The workgroup first forms, once per
+// candidate, the phase and its Taylor coefficients B0..B4 at the centre of
+// the tile's first chunk (RotConst, FP64 with the linear coefficient kept as
+// a double-double B1h + B1l, B1h short enough that B1h n is exact for every
+// lane offset n), and exp(2 pi i B1).  A lane at offset n = lane * S then
+// needs only polynomial updates in n: its start phase
+//   c0 - C c1 = B0 + B1 (n - C) + B2 n^2 + B3 n^3 + B4 n^4 - C delta,
+//   delta = c1 - B1 = n (2 B2 + 3 B3 n + 4 B4 n^2),
+// one sine / cosine polynomial of that (reduced) phase for u_0, and
+// exp(2 pi i c1) = exp(2 pi i B1) exp(2 pi i delta) with a fourth-order
+// series of the small angle 2 pi delta.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void sincos_turns64(double r, double& c, double& sn) {
     const double u = r * r;
@@ -304,77 +319,117 @@ __device__ __forceinline__ void sincos_turns64(double r, double& c, double& sn) 
     sn = r * ps;
 }
 
-// NC candidates at once (NC = 1 or 2): their recurrences are independent, so
-// interleaving two of them gives the FMA pipeline two dependency chains per
-// wave.  Each candidate's arithmetic is the same as alone, so results do not
-// depend on the pairing.
-template <int S, bool TAIL, bool SLOPE, bool COR, int NC>
-__device__ __forceinline__ void lane_rot(const double (&sv)[S], const Anchor* an, const double* amp0,
-                                         const double* ad, int valid, double* out) {
-    static_assert(kSinDeg64 == kCosDeg64, "sine and cosine tables have one degree");
-    // The recurrence is linear, so it carries scaled parts: R = g Re(u) and
-    // W = g theta Im(u), g = A when the amplitude is constant (else 1).  Then
-    // A cos(2 pi Phi(j)) = R_j - W_j j^2 and the residual is (s - R_j) + W_j j^2:
-    // five operations per sample (four for the correlation sum).
-    double rp[NC], wp[NC], r[NC], w[NC], c2[NC], acc0[NC], acc1[NC];
-#pragma unroll
-    for (int q = 0; q < NC; ++q) {
-        double cr, ci, wr, wi;
-        sincos_turns64(an[q].b0, cr, ci);  // u_0; b0 is already reduced to [-1/2, 1/2]
-        double e = an[q].b1;
-        e -= rint(e);
-        sincos_turns64(e, wr, wi);  // exp(2 pi i b1)
-        c2[q] = 2.0 * wr;
-        // u_{-1} = u_0 exp(-2 pi i b1) starts the recurrence
-        const double pr = __fma_rn(cr, wr, ci * wi);
-        const double pi = __fma_rn(ci, wr, -(cr * wi));
-        const double g = SLOPE ? 1.0 : amp0[q];
-        const double gth = g * (6.283185307179586477 * an[q].b2);  // g theta, theta in radians per j^2
-        r[q] = g * cr;
-        rp[q] = g * pr;
-        w[q] = gth * ci;
-        wp[q] = gth * pi;
-        acc0[q] = 0.0;
-        acc1[q] = 0.0;
-    }
+struct RotConst {
+    double B0, B1h, B1l, B2, B3, B4;  // turns: phase and Taylor coefficients at the first chunk's centre
+    double D2, D3, D4;                // 2 B2, 3 B3, 4 B4 (frequency change with the lane offset)
+    double T2, T3, T4;                // 2 pi g (B2, 3 B3, 6 B4) (g theta at a chunk centre)
+    double Or, Oi;                    // exp(2 pi i B1)
+    double g;                         // amplitude carried by the recurrence: A, or 1 with a slope
+};
+
+// Tile constants of one candidate; mt: offset of the tile's first sample
+// from the reference sample.
+template <int S, bool SLOPE>
+__device__ __forceinline__ RotConst make_rot_const(const Cand& c, double mt) {
+    constexpr double C = S / 2;
+    const double M = mt + C;
+    const Anchor a = make_anchor(c, M);
+    RotConst k;
+    k.B0 = a.b0;
+    k.B2 = a.b2;
+    k.B3 = a.b3;
+    k.B4 = a.b4;
+    // B1 = a1 + M (2 a2 + M (3 a3 + 4 a4 M)) as hi + lo (two-sum), then hi
+    // split into 40 leading bits (B1h) and the rest (folded into B1l)
+    const double sm = __fma_rn(__fma_rn(4.0 * c.a4, M, 3.0 * c.a3), M, 2.0 * c.a2) * M;
+    const double hi = c.a1 + sm;
+    const double bb = hi - c.a1;
+    const double lo = (c.a1 - (hi - bb)) + (sm - bb);
+    const double h40 = __longlong_as_double(__double_as_longlong(hi) & ~0x1FFFLL);
+    k.B1h = h40;
+    k.B1l = (hi - h40) + lo;
+    double r = h40 - rint(h40);
+    r += k.B1l;
+    sincos_turns64(r, k.Or, k.Oi);
+    k.D2 = 2.0 * k.B2;
+    k.D3 = 3.0 * k.B3;
+    k.D4 = 4.0 * k.B4;
+    k.g = SLOPE ? 1.0 : c.A;
+    const double G = 6.283185307179586477 * k.g;
+    k.T2 = G * k.B2;
+    k.T3 = G * (3.0 * k.B3);
+    k.T4 = G * (6.0 * k.B4);
+    return k;
+}
+
+// Lane sum of one candidate.  n: the lane's offset from the tile's first
+// chunk (lane * S), n2 = n^2, nc = n - C; amp0, ad: amplitude at the chunk's
+// first sample and its slope per sample (SLOPE).
+template <int S, bool TAIL, bool SLOPE, bool COR>
+__device__ __forceinline__ double lane_rot(const double (&sv)[S], const RotConst& k, double n, double n2,
+                                           double nc, double amp0, double ad, int valid) {
+    constexpr int C = S / 2;
+    // start phase of the chunk's linear part and its frequency offset
+    const double inner = __fma_rn(__fma_rn(k.D4, n, k.D3), n, k.D2);
+    const double delta = n * inner;
+    double p = k.B1h * nc;  // exact
+    p -= rint(p);
+    const double t = __fma_rn(__fma_rn(k.B4, n, k.B3), n, k.B2);
+    const double q = __fma_rn(k.B1l, nc, __fma_rn(delta, -(double)C, n2 * t));
+    double l0 = (k.B0 + p) + q;
+    l0 -= rint(l0);
+    double cr, ci;
+    sincos_turns64(l0, cr, ci);  // u_0
+    // exp(2 pi i c1) = exp(2 pi i B1) exp(i x): |x| <= 6e-3, series error <= x^6 / 720
+    const double x = 6.283185307179586477 * delta;
+    const double x2 = x * x;
+    const double cx = __fma_rn(__fma_rn(x2, 1.0 / 24.0, -0.5), x2, 1.0);
+    const double sx = x * __fma_rn(__fma_rn(x2, 1.0 / 120.0, -1.0 / 6.0), x2, 1.0);
+    const double wr = __fma_rn(k.Or, cx, -(k.Oi * sx));
+    const double wi = __fma_rn(k.Or, sx, k.Oi * cx);
+    const double c2 = wr + wr;
+    // u_{-1} = u_0 exp(-2 pi i c1) starts the recurrence; it carries R = g Re(u)
+    // and W = g theta Im(u), so that g cos(2 pi Phi(j)) = R_j - W_j (j - C)^2 and
+    // the residual is (s - R_j) + W_j (j - C)^2
+    const double pr = __fma_rn(cr, wr, ci * wi);
+    const double pi = __fma_rn(ci, wr, -(cr * wi));
+    const double gth = __fma_rn(__fma_rn(k.T4, n, k.T3), n, k.T2);
+    double r = k.g * cr, rp = k.g * pr, w = gth * ci, wp = gth * pi;
+    double acc0 = 0.0, acc1 = 0.0;
 #pragma unroll
     for (int j = 0; j < S; ++j) {
-#pragma unroll
-        for (int q = 0; q < NC; ++q) {
-            if (j > 0) {
-                const double nr = __fma_rn(c2[q], r[q], -rp[q]);
-                const double nw = __fma_rn(c2[q], w[q], -wp[q]);
-                rp[q] = r[q];
-                wp[q] = w[q];
-                r[q] = nr;
-                w[q] = nw;
-            }
-            // j^2 is an immediate, so no per-sample constant is held in registers
-            const double k2 = (double)(j * j);
-            double& acc = (j & 1) ? acc1[q] : acc0[q];
-            if constexpr (COR) {
-                const double zr = j == 0 ? r[q] : __fma_rn(-w[q], k2, r[q]);
-                const double m = SLOPE ? __fma_rn(ad[q], (double)j, amp0[q]) * zr : zr;
-                acc = __fma_rn(sv[j], m, acc);
+        if (j > 0) {
+            const double nr = __fma_rn(c2, r, -rp);
+            const double nw = __fma_rn(c2, w, -wp);
+            rp = r;
+            wp = w;
+            r = nr;
+            w = nw;
+        }
+        // (j - C)^2 is an immediate, so no per-sample constant is held in registers
+        const double k2 = (double)((j - C) * (j - C));
+        double& acc = (j & 1) ? acc1 : acc0;
+        if constexpr (COR) {
+            const double zr = j == C ? r : __fma_rn(-w, k2, r);
+            const double m = SLOPE ? __fma_rn(ad, (double)j, amp0) * zr : zr;
+            acc = __fma_rn(sv[j], m, acc);
+        } else {
+            double rho;
+            if constexpr (SLOPE) {
+                const double zr = j == C ? r : __fma_rn(-w, k2, r);
+                rho = __fma_rn(-__fma_rn(ad, (double)j, amp0), zr, sv[j]);
             } else {
-                double rho;
-                if constexpr (SLOPE) {
-                    const double zr = j == 0 ? r[q] : __fma_rn(-w[q], k2, r[q]);
-                    rho = __fma_rn(-__fma_rn(ad[q], (double)j, amp0[q]), zr, sv[j]);
-                } else {
-                    const double d = sv[j] - r[q];
-                    rho = j == 0 ? d : __fma_rn(w[q], k2, d);
-                }
-                if (TAIL) {
-                    if (j < valid) acc = __fma_rn(rho, rho, acc);
-                } else {
-                    acc = (j < 2) ? rho * rho : __fma_rn(rho, rho, acc);
-                }
+                const double d = sv[j] - r;
+                rho = j == C ? d : __fma_rn(w, k2, d);
+            }
+            if (TAIL) {
+                if (j < valid) acc = __fma_rn(rho, rho, acc);
+            } else {
+                acc = (j < 2) ? rho * rho : __fma_rn(rho, rho, acc);
             }
         }
     }
-#pragma unroll
-    for (int q = 0; q < NC; ++q) out[q] = acc0[q] + acc1[q];
+    return acc0 + acc1;
 }
 
 // ---------------------------------------------------------------------------
@@ -536,66 +591,66 @@ __device__ __forceinline__ double lane_sum(const V (&sv)[S], const Anchor& an, d
 // 2 = FP64 phasor recurrence.  COH: the trial rows may be written inside the
 // launch (persistent kernel).  trows: the population rows to evaluate, or
 // null when the caller has already put the group's candidates into cs (and
-// passed a barrier); part: the partial sums to write.
+// passed a barrier); part: the partial sums to write.  rc: LDS for the phasor
+// path's tile constants (CPG entries).
 template <int S, int CPG, int MODE, bool SLOPE, bool COH = false, typename V>
 __device__ __forceinline__ void objective_unit(const BlockDesc* __restrict__ d, int tile, int group,
-                                               const V (&sv)[S], bool full, int valid, Cand* cs,
+                                               const V (&sv)[S], bool full, int valid, Cand* cs, RotConst* rc,
                                                double (*red)[kThreads], const double* trows, double* part) {
     const int cbase = group * CPG;
     const int ncand = min(CPG, d->P - cbase);
     const int tid = threadIdx.x;
     const bool cor = d->objective != 0;
     const bool quart = d->quartic != 0;
-    const double m0 = (double)((int64_t)tile * (kThreads * S) + (int64_t)tid * S) - d->ref;
+    const double mt = (double)((int64_t)tile * (kThreads * S)) - d->ref;  // the tile's first sample
+    const double m0 = mt + (double)(tid * S);                             // the lane's first sample
     if (trows != nullptr) {
-        if (tid < ncand) cs[tid] = make_cand<COH>(trows + (size_t)(cbase + tid) * kStride, d->fs);
+        if (tid < ncand) {
+            const Cand cc = make_cand<COH>(trows + (size_t)(cbase + tid) * kStride, d->fs);
+            cs[tid] = cc;
+            if constexpr (MODE == 2) rc[tid] = make_rot_const<S, SLOPE>(cc, mt);
+        }
+        __syncthreads();
+    } else if constexpr (MODE == 2) {
+        if (tid < ncand) rc[tid] = make_rot_const<S, SLOPE>(cs[tid], mt);
         __syncthreads();
     }
 
-    int c0 = 0;
-#ifndef PT_ROT_PAIR
-// 0: one candidate at a time -- 109 VGPRs, four waves per SIMD -- measured
-// faster on MI355X than pairs (187 VGPRs, two waves per SIMD)
-#define PT_ROT_PAIR 0
-#endif
-    if constexpr (MODE == 2 && PT_ROT_PAIR) {
-        // phasor path: candidates in pairs (two independent recurrences per lane)
-        for (; c0 + 1 < ncand; c0 += 2) {
-            const Cand ca = cs[c0], cb = cs[c0 + 1];
-            const Anchor an[2] = {make_anchor(ca, m0), make_anchor(cb, m0)};
-            const double amp0[2] = {SLOPE ? __fma_rn(ca.Ad, m0, ca.A) : ca.A, SLOPE ? __fma_rn(cb.Ad, m0, cb.A) : cb.A};
-            const double ad[2] = {ca.Ad, cb.Ad};
-            double acc[2];
-            if (cor)
-                lane_rot<S, false, SLOPE, true, 2>(sv, an, amp0, ad, valid, acc);
-            else if (full)
-                lane_rot<S, false, SLOPE, false, 2>(sv, an, amp0, ad, valid, acc);
+    if constexpr (MODE == 2) {
+        // the phasor path: tile constants plus per-lane polynomial updates (the
+        // anchor carries the cubic and quartic terms; inside the chunk they are
+        // part of the dropped terms the host bounds).  One loop per variant:
+        // with the variant chosen inside the loop the compiler computes the
+        // recurrence once ahead of the branch and holds the whole chunk's
+        // values live.
+        const double n = (double)(tid * S), n2 = n * n, nc = n - (double)(S / 2);
+        auto run = [&](auto tail, auto corr) {
+            for (int c = 0; c < ncand; ++c) {
+                const RotConst k = rc[c];
+                const double ad = SLOPE ? cs[c].Ad : 0.0;
+                const double amp0 = SLOPE ? __fma_rn(ad, m0, cs[c].A) : 0.0;
+                red[c][tid] = lane_rot<S, decltype(tail)::value, SLOPE, decltype(corr)::value>(sv, k, n, n2, nc,
+                                                                                               amp0, ad, valid);
+            }
+        };
+        if (cor)
+            run(std::false_type{}, std::true_type{});
+        else if (full)
+            run(std::false_type{}, std::false_type{});
+        else
+            run(std::true_type{}, std::false_type{});
+    } else {
+        for (int c = 0; c < ncand; ++c) {
+            const Cand cc = cs[c];
+            const Anchor an = make_anchor(cc, m0);
+            const double amp0 = SLOPE ? __fma_rn(cc.Ad, m0, cc.A) : cc.A;
+            double acc;
+            if (quart)
+                acc = lane_sum<MODE, S, SLOPE, true>(sv, an, amp0, cc.Ad, valid, cor, full);
             else
-                lane_rot<S, true, SLOPE, false, 2>(sv, an, amp0, ad, valid, acc);
-            red[c0][tid] = acc[0];
-            red[c0 + 1][tid] = acc[1];
+                acc = lane_sum<MODE, S, SLOPE, false>(sv, an, amp0, cc.Ad, valid, cor, full);
+            red[c][tid] = acc;
         }
-    }
-    for (int c = c0; c < ncand; ++c) {
-        const Cand cc = cs[c];
-        const Anchor an = make_anchor(cc, m0);
-        const double amp0 = SLOPE ? __fma_rn(cc.Ad, m0, cc.A) : cc.A;
-        double acc;
-        if constexpr (MODE == 2) {
-            // the anchor carries the quartic term; inside the chunk it is part of
-            // the dropped terms the host bounds
-            if (cor)
-                lane_rot<S, false, SLOPE, true, 1>(sv, &an, &amp0, &cc.Ad, valid, &acc);
-            else if (full)
-                lane_rot<S, false, SLOPE, false, 1>(sv, &an, &amp0, &cc.Ad, valid, &acc);
-            else
-                lane_rot<S, true, SLOPE, false, 1>(sv, &an, &amp0, &cc.Ad, valid, &acc);
-        } else if (quart) {
-            acc = lane_sum<MODE, S, SLOPE, true>(sv, an, amp0, cc.Ad, valid, cor, full);
-        } else {
-            acc = lane_sum<MODE, S, SLOPE, false>(sv, an, amp0, cc.Ad, valid, cor, full);
-        }
-        red[c][tid] = acc;
     }
     __syncthreads();
 
@@ -1263,6 +1318,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 4))
     const int Ux = nwg >> 3;
     const int unit = (bid & 7) * Ux + (bid >> 3);
     __shared__ Cand cs[CPG];
+    __shared__ RotConst rc[MODE == 2 ? CPG : 1];
     extern __shared__ double de_lds[];
     if (unit >= total_units) {
         // leading-step form: unit total_units + b keeps block b's DE state
@@ -1297,11 +1353,11 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 4))
         const int L = d->gen_begin + fused - 2;  // the block's launch index (gen_begin: its offset)
         if (!de_lead<CPG, false>(d, L, tile, group, cs, de_lds, raw)) return;
         finish_lane<V, T, S>(d, tile, raw, sv, full, valid);
-        objective_unit<S, CPG, MODE, SLOPE>(d, tile, group, sv, full, valid, cs, red, nullptr,
+        objective_unit<S, CPG, MODE, SLOPE>(d, tile, group, sv, full, valid, cs, rc, red, nullptr,
                                             (L & 1) ? d->partials2 : d->partials);
     } else {
         load_lane<V, T, S>(d, tile, sv, full, valid);
-        objective_unit<S, CPG, MODE, SLOPE>(d, tile, group, sv, full, valid, cs, red, d->trial, d->partials);
+        objective_unit<S, CPG, MODE, SLOPE>(d, tile, group, sv, full, valid, cs, rc, red, d->trial, d->partials);
         if (!fused) return;
 
         int* sync = d->sync;
@@ -1346,6 +1402,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 4))
     __shared__ int s_ok, s_done, s_last;
     Cand* cs = reinterpret_cast<Cand*>(lds);
     double(*red)[kThreads] = reinterpret_cast<double(*)[kThreads]>(lds + 64);
+    RotConst* rc = reinterpret_cast<RotConst*>(lds + 64 + kMaxCpg * kThreads);
+    static_assert(64 + kMaxCpg * kThreads + kMaxCpg * sizeof(RotConst) / sizeof(double) <= kPersistLds,
+                  "persistent kernel LDS holds the candidates, the lane sums and the phasor constants");
 
     const int G = gridDim.x, w = blockIdx.x;
     const int xcd = w & 7, k = w >> 3, Gx = G >> 3;
@@ -1385,7 +1444,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 4))
             if (s_done) continue;
             any = true;
             if (!resident) load_lane<V, T, S>(d, tile, sv, full, valid);
-            objective_unit<S, CPG, MODE, SLOPE, true>(d, tile, group, sv, full, valid, cs, red, d->trial,
+            objective_unit<S, CPG, MODE, SLOPE, true>(d, tile, group, sv, full, valid, cs, rc, red, d->trial,
                                                       d->partials);
             // The workgroup barrier makes every wave's partial stores visible
             // at the XCD's L2; one release fence then publishes them device-wide

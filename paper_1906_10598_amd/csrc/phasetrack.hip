@@ -154,24 +154,29 @@ PersistKernel persistent_kernel(int dtype, Geometry g, int mode, bool slope) {
 }
 
 // Validity of the FP64 phasor path (see lane_rot) for every candidate with
-// f0 in [f0lo, f0hi], |f1| <= f1max, |f2| <= f2max, |f3| <= f3max and lane
-// anchors |m0| <= span samples from the reference (turns per sample^k:
-// b3 = a3 + 4 a4 m0, b2 = a2 + 3 a3 m0 + 6 a4 m0^2, b1 = f(t) / fs):
-//   (1) (S - 1)^3 |b3| + (S - 1)^4 |b4| <= 1e-12 turns (dropped terms);
-//   (2) theta^2 / 2 <= 1e-11 with theta = 2 pi |b2| (S - 1)^2 (first-order
+// f0 in [f0lo, f0hi], |f1| <= f1max, |f2| <= f2max, |f3| <= f3max and chunk
+// centres |m| <= span samples from the reference (turns per sample^k at a
+// centre: c3 = a3 + 4 a4 m, c2 = a2 + 3 a3 m + 6 a4 m^2, c1 = f(t) / fs), with
+// C = S / 2 and T = 256 S samples per tile:
+//   (1) C^3 |c3| + C^4 |c4| <= 1e-12 turns (dropped terms);
+//   (2) theta^2 / 2 <= 1e-11 with theta = 2 pi |c2| C^2 (first-order
 //       quadratic correction);
-//   (3) |sin 2 pi b1| >= S * 2.2e-4 over the block's frequency range
-//       (conditioning of the three-term recurrence).
+//   (3) |sin 2 pi c1| >= S * 2.2e-4 over the block's frequency range
+//       (conditioning of the three-term recurrence);
+//   (4) 2 pi T (2 |c2| + 3 |c3| T + 4 |c4| T^2) <= 6e-3: the local frequency
+//       moves by less than that angle across a tile (small-angle rotation).
 bool phasor_ok(int spl, double fs, double span, double f0lo, double f0hi, double f1max, double f2max,
                double f3max) {
     const double a3 = f2max / (6.0 * fs * fs * fs);
     const double a4 = f3max / (24.0 * fs * fs * fs * fs);
     const double b3 = a3 + 4.0 * a4 * span;
     const double b2 = f1max / (2.0 * fs * fs) + 3.0 * a3 * span + 6.0 * a4 * span * span;
-    const double s1 = spl - 1;
-    if (!(s1 * s1 * s1 * (b3 + s1 * a4) <= 1e-12)) return false;
-    const double th = 2.0 * M_PI * b2 * s1 * s1;
+    const double C = spl / 2;
+    if (!(C * C * C * (b3 + C * a4) <= 1e-12)) return false;
+    const double th = 2.0 * M_PI * b2 * C * C;
     if (!(0.5 * th * th <= 1e-11)) return false;
+    const double T = 256.0 * spl;
+    if (!(2.0 * M_PI * T * (2.0 * b2 + 3.0 * b3 * T + 4.0 * a4 * T * T) <= 6e-3)) return false;
     const double tmax = span / fs;
     const double dev = f1max * tmax + f2max * tmax * tmax / 2.0 + f3max * tmax * tmax * tmax / 6.0;
     const double xlo = (f0lo - dev) / fs, xhi = (f0hi + dev) / fs;  // turns per sample
