@@ -13,8 +13,8 @@ Contents
     (instantaneous phase and frequency, total-count phase, integration
     Doppler, line-of-sight acceleration), in NumPy FP64.
 
-Parameter vectors have six slots: A, phi0 [rad], f0 [Hz], f1 [Hz/s],
-f2 [Hz/s^2], Adot [1/s]; t_n = (n - ref) / fs.
+Parameter vectors have seven slots (ORC_NSLOT): A, phi0 [rad], f0 [Hz],
+f1 [Hz/s], f2 [Hz/s^2], Adot [1/s], f3 [Hz/s^3]; t_n = (n - ref) / fs.
 """
 import ctypes
 import os

@@ -67,7 +67,7 @@ double orc_cor(const double* s, int64_t n, double fs, double ref, const double* 
 #define ORC_OBJ_CHI2 0
 #define ORC_OBJ_COR 1
 
-/* Objective of P candidates (row-major P x 6); candidates in parallel with
+/* Objective of P candidates (row-major P x ORC_NSLOT); candidates in parallel with
  * nthreads OpenMP threads (<= 0: library default).  Each candidate's sum is
  * sequential, so the result does not depend on the thread count. */
 void orc_chi2_pop(const double* s, int64_t n, double fs, double ref,
@@ -81,13 +81,13 @@ void orc_obj_pop(int kind, const double* s, int64_t n, double fs, double ref,
 void orc_de_draws(uint64_t seed, uint64_t stream, int g, int i, int P, int D,
                   int* r1, int* r2, int* r3, int* jrand, double* U /* D */);
 
-/* One DE/rand/1/bin trial vector from explicit draws (all 6 slots;
+/* One DE/rand/1/bin trial vector from explicit draws (all ORC_NSLOT slots;
  * act[0..D-1] lists the active slots in increasing order). */
 void orc_de_trial(const double* pop, int i, int r1, int r2, int r3, int jrand,
                   const double* U, int D, const int* act, double F, double CR,
                   const double* lo, const double* hi, double* trial);
 
-/* Initial population (P x 6) inside the box. */
+/* Initial population (P x ORC_NSLOT) inside the box. */
 void orc_de_init(uint64_t seed, uint64_t stream, int P, const double* lo,
                  const double* hi, double* pop);
 
@@ -104,8 +104,8 @@ typedef struct {
     int objective;    /* ORC_OBJ_CHI2 or ORC_OBJ_COR */
 } orc_de_cfg;
 
-/* Full DE fit.  Outputs: best vector (6), best objective, generations run,
- * flags, final population (P x 6, may be NULL), its objectives (P, may be
+/* Full DE fit.  Outputs: best vector (ORC_NSLOT), best objective, generations run,
+ * flags, final population (P x ORC_NSLOT, may be NULL), its objectives (P, may be
  * NULL), best-so-far history (max_gens + 1 entries, may be NULL).
  * Returns 0, or -1 on invalid arguments. */
 int orc_de_fit(const double* s, int64_t n, double fs, double ref,

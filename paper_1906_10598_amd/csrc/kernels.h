@@ -587,23 +587,18 @@ __device__ __forceinline__ double lane_sum(const V (&sv)[S], const Anchor& an, d
     }
 }
 
-// MODE: 0 = FP64 with per-sample cosine polynomial, 1 = mixed precision,
-// 2 = FP64 phasor recurrence.  COH: the trial rows may be written inside the
-// launch (persistent kernel).  trows: the population rows to evaluate, or
-// null when the caller has already put the group's candidates into cs (and
-// passed a barrier); part: the partial sums to write.  rc: LDS for the phasor
-// path's tile constants (CPG entries).
-template <int S, int CPG, int MODE, bool SLOPE, bool COH = false, typename V>
-__device__ __forceinline__ void objective_unit(const BlockDesc* __restrict__ d, int tile, int group,
-                                               const V (&sv)[S], bool full, int valid, Cand* cs, RotConst* rc,
-                                               double (*red)[kThreads], const double* trows, double* part) {
+// The candidates of one work unit into LDS before its evaluation: cs (and,
+// for the phasor path, the tile constants rc) from the population rows, or --
+// rows == nullptr -- rc from candidates the caller has already put into cs
+// (past a barrier).  Ends with a barrier.  COH: the rows may be written
+// inside the launch (persistent kernel).
+template <int S, int CPG, int MODE, bool SLOPE, bool COH = false>
+__device__ __forceinline__ void unit_setup(const BlockDesc* __restrict__ d, int tile, int group, Cand* cs,
+                                           RotConst* rc, const double* trows) {
     const int cbase = group * CPG;
     const int ncand = min(CPG, d->P - cbase);
     const int tid = threadIdx.x;
-    const bool cor = d->objective != 0;
-    const bool quart = d->quartic != 0;
     const double mt = (double)((int64_t)tile * (kThreads * S)) - d->ref;  // the tile's first sample
-    const double m0 = mt + (double)(tid * S);                             // the lane's first sample
     if (trows != nullptr) {
         if (tid < ncand) {
             const Cand cc = make_cand<COH>(trows + (size_t)(cbase + tid) * kStride, d->fs);
@@ -615,6 +610,25 @@ __device__ __forceinline__ void objective_unit(const BlockDesc* __restrict__ d, 
         if (tid < ncand) rc[tid] = make_rot_const<S, SLOPE>(cs[tid], mt);
         __syncthreads();
     }
+}
+
+// MODE: 0 = FP64 with per-sample cosine polynomial, 1 = mixed precision,
+// 2 = FP64 phasor recurrence.  The group's candidates are in cs (and rc)
+// (unit_setup); part: the partial sums to write.  red: LDS for the lane
+// sums (CPG x kThreads doubles).
+template <int S, int CPG, int MODE, bool SLOPE, typename V>
+__device__ __forceinline__ void objective_unit(const BlockDesc* __restrict__ d, int tile, int group,
+                                               const V (&sv)[S], bool full, int valid, const Cand* cs,
+                                               const RotConst* rc, double (*red)[kThreads], double* part) {
+    const int cbase = group * CPG;
+    const int ncand = min(CPG, d->P - cbase);
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const bool cor = d->objective != 0;
+    const bool quart = d->quartic != 0;
+    const double mt = (double)((int64_t)tile * (kThreads * S)) - d->ref;  // the tile's first sample
+    const double m0 = mt + (double)(tid * S);                             // the lane's first sample
+    auto keep = [&](int c, double acc) { red[c][tid] = acc; };
 
     if constexpr (MODE == 2) {
         // the phasor path: tile constants plus per-lane polynomial updates (the
@@ -629,8 +643,8 @@ __device__ __forceinline__ void objective_unit(const BlockDesc* __restrict__ d, 
                 const RotConst k = rc[c];
                 const double ad = SLOPE ? cs[c].Ad : 0.0;
                 const double amp0 = SLOPE ? __fma_rn(ad, m0, cs[c].A) : 0.0;
-                red[c][tid] = lane_rot<S, decltype(tail)::value, SLOPE, decltype(corr)::value>(sv, k, n, n2, nc,
-                                                                                               amp0, ad, valid);
+                keep(c, lane_rot<S, decltype(tail)::value, SLOPE, decltype(corr)::value>(sv, k, n, n2, nc, amp0,
+                                                                                         ad, valid));
             }
         };
         if (cor)
@@ -649,12 +663,12 @@ __device__ __forceinline__ void objective_unit(const BlockDesc* __restrict__ d, 
                 acc = lane_sum<MODE, S, SLOPE, true>(sv, an, amp0, cc.Ad, valid, cor, full);
             else
                 acc = lane_sum<MODE, S, SLOPE, false>(sv, an, amp0, cc.Ad, valid, cor, full);
-            red[c][tid] = acc;
+            keep(c, acc);
         }
     }
     __syncthreads();
-
-    const int wave = tid >> 6, lane = tid & 63;
+    // one FP64 partial per (candidate, tile): each wave adds one candidate's four
+    // wave-slices lane by lane, then a fixed-order shuffle butterfly
     for (int c = wave; c < ncand; c += kThreads / 64) {
         double v = ((red[c][lane] + red[c][lane + 64]) + red[c][lane + 128]) + red[c][lane + 192];
         v = wave_sum(v);
@@ -1030,15 +1044,21 @@ __device__ __forceinline__ bool de_lead(const BlockDesc* __restrict__ d, int L, 
     double* xp = reinterpret_cast<double*>(ix + NT);  // P x kSlots: population rows
     __shared__ int s_done, s_stop;
     __shared__ double s_old;
-    const DeState* st_in = p ? d->st2 : d->st;
-    DeState* st_out = p ? d->st : d->st2;
-    const double* rows_in = p ? d->pop : d->pop2;  // slot p ^ 1
-    const double* trial_in = p ? d->trial : d->trial2;
-    const double* fpop_in = p ? d->fpop : d->fpop2;
-    const double* part_in = p ? d->partials : d->partials2;
-    double* rows_out = p ? d->pop2 : d->pop;       // slot p
-    double* trial_out = p ? d->trial2 : d->trial;
-    double* fpop_out = p ? d->fpop2 : d->fpop;
+    // both slots' pointers are read unconditionally and then selected: read
+    // through a parity-selected field address they would cost one more
+    // dependent scalar round trip before any data load
+    DeState *st0 = d->st, *st1 = d->st2;
+    double *pop0 = d->pop, *pop1 = d->pop2, *tr0 = d->trial, *tr1 = d->trial2;
+    double *fp0 = d->fpop, *fp1 = d->fpop2, *pa0 = d->partials, *pa1 = d->partials2;
+    const DeState* st_in = p ? st1 : st0;
+    DeState* st_out = p ? st0 : st1;
+    const double* rows_in = p ? pop0 : pop1;  // slot p ^ 1
+    const double* trial_in = p ? tr0 : tr1;
+    const double* fpop_in = p ? fp0 : fp1;
+    const double* part_in = p ? pa0 : pa1;
+    double* rows_out = p ? pop1 : pop0;       // slot p
+    double* trial_out = p ? tr1 : tr0;
+    double* fpop_out = p ? fp1 : fp0;
     const int cbase = group * CPG;
     const int ncand = min(CPG, P - cbase);
 
@@ -1082,6 +1102,15 @@ __device__ __forceinline__ bool de_lead(const BlockDesc* __restrict__ d, int L, 
     //    coordinate (candidate c = i / 8 of the group, slot j = i % 8)
     const int c = i >> 3, j = i & 7;
     const bool tw = !BOOK && L > 0 && c < ncand;
+    // this thread's coordinate: its bounds (a per-lane index into the
+    // descriptor, so vector loads) and its place among the active slots, read
+    // with the step's other data rather than after the selection
+    const int jc = j < kSlots ? j : kSlots - 1;
+    const double lo_j = gld(&d->lo[jc]), hi_j = gld(&d->hi[jc]);
+    int a_j = -1;
+    for (int q = 0; q < d->D; ++q)
+        if (d->act[q] == j) a_j = q;
+    const double Fm = d->F, fs = d->fs;
     Draws dr{0, 0, 0, 0u};
     if (tw) dr = trial_draws(d, cbase + c, (uint32_t)L);
 
@@ -1104,6 +1133,7 @@ __device__ __forceinline__ bool de_lead(const BlockDesc* __restrict__ d, int L, 
     // their loads are issued with the step's and not after it
 #pragma unroll
     for (int q = 0; q < RS; ++q) asm volatile("" ::"v"(raw[q]));
+    asm volatile("" ::"v"(lo_j), "v"(hi_j));
     if (i < P * k) red[i] = sp;
 #pragma unroll
     for (int r = 0; r < kR; ++r) {
@@ -1170,17 +1200,14 @@ __device__ __forceinline__ bool de_lead(const BlockDesc* __restrict__ d, int L, 
             double y = 0.0;
             if (j < kSlots) {
                 y = xs[m * kSlots + j];
-                int a = -1;
-                for (int q = 0; q < d->D; ++q)
-                    if (d->act[q] == j) a = q;
-                if (a >= 0 && ((dr.cross >> a) & 1u)) {
+                if (a_j >= 0 && ((dr.cross >> a_j) & 1u)) {
                     const double x1 = xs[dr.r1 * kSlots + j];
-                    double vm = __fma_rn(d->F, xs[dr.r2 * kSlots + j] - xs[dr.r3 * kSlots + j], x1);
-                    if (vm < d->lo[j]) vm = (d->lo[j] + x1) * 0.5;
-                    if (vm > d->hi[j]) vm = (d->hi[j] + x1) * 0.5;
+                    double vm = __fma_rn(Fm, xs[dr.r2 * kSlots + j] - xs[dr.r3 * kSlots + j], x1);
+                    if (vm < lo_j) vm = (lo_j + x1) * 0.5;
+                    if (vm > hi_j) vm = (hi_j + x1) * 0.5;
                     y = vm;
                 }
-                cand_member(cs[c], j) = cand_value(j, y, d->fs);
+                cand_member(cs[c], j) = cand_value(j, y, fs);
             }
             if (tile == 0) gst(trial_out + (size_t)m * kStride + j, y);
         }
@@ -1352,12 +1379,14 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 4))
         load_lane_raw<T, S>(d, tile, raw);
         const int L = d->gen_begin + fused - 2;  // the block's launch index (gen_begin: its offset)
         if (!de_lead<CPG, false>(d, L, tile, group, cs, de_lds, raw)) return;
+        unit_setup<S, CPG, MODE, SLOPE>(d, tile, group, cs, rc, nullptr);
         finish_lane<V, T, S>(d, tile, raw, sv, full, valid);
-        objective_unit<S, CPG, MODE, SLOPE>(d, tile, group, sv, full, valid, cs, rc, red, nullptr,
+        objective_unit<S, CPG, MODE, SLOPE>(d, tile, group, sv, full, valid, cs, rc, red,
                                             (L & 1) ? d->partials2 : d->partials);
     } else {
         load_lane<V, T, S>(d, tile, sv, full, valid);
-        objective_unit<S, CPG, MODE, SLOPE>(d, tile, group, sv, full, valid, cs, rc, red, d->trial, d->partials);
+        unit_setup<S, CPG, MODE, SLOPE>(d, tile, group, cs, rc, d->trial);
+        objective_unit<S, CPG, MODE, SLOPE>(d, tile, group, sv, full, valid, cs, rc, red, d->partials);
         if (!fused) return;
 
         int* sync = d->sync;
@@ -1444,8 +1473,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 4))
             if (s_done) continue;
             any = true;
             if (!resident) load_lane<V, T, S>(d, tile, sv, full, valid);
-            objective_unit<S, CPG, MODE, SLOPE, true>(d, tile, group, sv, full, valid, cs, rc, red, d->trial,
-                                                      d->partials);
+            unit_setup<S, CPG, MODE, SLOPE, true>(d, tile, group, cs, rc, d->trial);
+            objective_unit<S, CPG, MODE, SLOPE>(d, tile, group, sv, full, valid, cs, rc, red, d->partials);
             // The workgroup barrier makes every wave's partial stores visible
             // at the XCD's L2; one release fence then publishes them device-wide
             // before the arrival is counted.  Arrivals are counted per XCD

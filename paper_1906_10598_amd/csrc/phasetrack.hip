@@ -239,6 +239,8 @@ struct pt_ctx {
     // split by arithmetic run side by side (their blocks share nothing)
     hipStream_t aux_stream = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    // the window rule's stop checks: copies of the state behind alternate chunks
+    hipEvent_t ev_state[2] = {nullptr, nullptr};
     DevBuf desc, pop, trial, fpop, partials, hist, state, rec, staging, eval_pop, tune_block, sync;
     PinBuf hdesc, hrec, hstate;
     // last fit (for pt_last_population / pt_last_history)
@@ -615,7 +617,7 @@ int prepare(pt_ctx* ctx, const pt_block* blocks, int nblk, const pt_de_settings*
         (rc = ctx->rec.ensure((size_t)nblk * sizeof(FitRecord))) ||
         (rc = ctx->hdesc.ensure(2 * sizeof(BlockDesc) * nblk)) ||
         (rc = ctx->hrec.ensure((size_t)nblk * sizeof(FitRecord))) ||
-        (rc = ctx->hstate.ensure(2 * (size_t)nblk * sizeof(DeState))))
+        (rc = ctx->hstate.ensure(4 * (size_t)nblk * sizeof(DeState) + sizeof(int))))
         return rc;
     if (stage_bytes && (rc = ctx->staging.ensure(stage_bytes))) return rc;
 
@@ -784,18 +786,29 @@ int run_fit(pt_ctx* ctx, const pt_block* blocks, int nblk, const pt_de_settings*
         hipGraphExec_t ex = nullptr;
         const int full = iters / kChunk, rem = iters % kChunk;
         DeState* hst = static_cast<DeState*>(ctx->hstate.p);
+        const int ns = lead ? 2 * nblk : nblk;  // leading-step form: either slot may hold the stop
+        auto stopped = [&](const DeState* h) {
+            for (int b = 0; b < nblk; ++b)
+                if (!(h[b].done != 0 || (lead && h[nblk + b].done != 0))) return false;
+            return true;
+        };
         bool all = false;
         for (int c = 0; c < full && !all; ++c) {
             if ((c == 0 || lead) && (rc = get_graph(ctx, pl, kChunk, c * kChunk, &ex))) return rc;
             HIPCHK(hipGraphLaunch(ex, s));
             if (pl.window && c + 1 < full) {
-                // stop launching once every block has met its stop rule (the
-                // leading-step form's launches must otherwise run in sequence)
-                const int ns = lead ? 2 * nblk : nblk;  // leading-step form: either slot may hold the stop
-                HIPCHK(hipMemcpyAsync(hst, ctx->state.p, sizeof(DeState) * ns, hipMemcpyDeviceToHost, s));
-                HIPCHK(hipStreamSynchronize(s));
-                all = true;
-                for (int b = 0; b < nblk && all; ++b) all = hst[b].done != 0 || (lead && hst[nblk + b].done != 0);
+                // Stop launching once every block has met its stop rule.  The
+                // state after chunk c is copied behind it; the host waits for
+                // the copy after chunk c - 1's only once chunk c is queued, so
+                // the device never idles for the check (a chunk queued after
+                // the stop runs as early-exit launches).
+                HIPCHK(hipMemcpyAsync(hst + (c & 1) * ns, ctx->state.p, sizeof(DeState) * ns,
+                                      hipMemcpyDeviceToHost, s));
+                HIPCHK(hipEventRecord(ctx->ev_state[c & 1], s));
+                if (c >= 1) {
+                    HIPCHK(hipEventSynchronize(ctx->ev_state[(c - 1) & 1]));
+                    all = stopped(hst + ((c - 1) & 1) * ns);
+                }
             }
         }
         for (int k = 0; k < rem && !all; ++k)
@@ -804,7 +817,7 @@ int run_fit(pt_ctx* ctx, const pt_block* blocks, int nblk, const pt_de_settings*
     hipLaunchKernelGGL(k_finalize, dim3(nblk), dim3(64), 0, s, d, static_cast<FitRecord*>(ctx->rec.p));
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(ctx->hrec.p, ctx->rec.p, sizeof(FitRecord) * nblk, hipMemcpyDeviceToHost, s));
-    int* herr = reinterpret_cast<int*>(static_cast<char*>(ctx->hstate.p));
+    int* herr = reinterpret_cast<int*>(static_cast<DeState*>(ctx->hstate.p) + 4 * nblk);
     HIPCHK(hipMemcpyAsync(herr, err, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (ctx->timing && (rc = collect_timing(ctx))) return rc;
@@ -877,6 +890,7 @@ int pt_ctx_create(int device, pt_ctx** out) {
     HIPCHK(hipStreamCreateWithFlags(&c->aux_stream, hipStreamNonBlocking));
     HIPCHK(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+    for (hipEvent_t& e : c->ev_state) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     *out = c.release();
     return PT_OK;
 }
@@ -903,6 +917,8 @@ void pt_ctx_destroy(pt_ctx* ctx) {
     if (ctx->aux_stream) (void)hipStreamDestroy(ctx->aux_stream);
     if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
     if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
+    for (hipEvent_t e : ctx->ev_state)
+        if (e) (void)hipEventDestroy(e);
     delete ctx;
 }
 

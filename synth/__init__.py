@@ -3,7 +3,9 @@
 This module only draws inputs (sample blocks, true coefficients, search
 boxes, DE settings).  It holds none of the fit's arithmetic: no objective,
 no DE, no observables.  Both the HIP path and the oracle take their inputs
-from here; neither is imported.
+from here; neither is imported.  ``synth.crlb`` gives the Cramer-Rao bounds
+of the drawn blocks' parameters (Fisher information of the signal model), by
+which the benchmark and the tests state f0 accuracy.
 
 The paper's recordings (Mars Express, Chang'E-4 relay; Sec. 2.1, Sec. 4) are
 not available, so these generators stand in for them with the paper's

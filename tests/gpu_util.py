@@ -98,9 +98,10 @@ def random_population(rng, lo, hi, P, far=0):
     return pop
 
 
-def crlb_f0(n, fs, amp, sigma):
-    """Cramer-Rao bound on f0 [Hz] of a real sinusoid in white noise with the
-    time origin at the block centre and f0 the only unknown besides the
-    amplitude and phase: var = 2 sigma^2 / (A^2 (2 pi)^2 sum t^2), sum t^2 ~ n T^2 / 12."""
-    T = n / fs
-    return math.sqrt(6.0) * sigma / (math.pi * amp * T * math.sqrt(n))
+def crlb_f0(b: synth.Block):
+    """Cramer-Rao bound on f0 [Hz] of a block over the parameters its box
+    frees (Fisher information of the signal model, synth.crlb): with f1 and
+    f2 free it is 2.5x the single-tone bound."""
+    from synth.crlb import crlb_f0_block
+
+    return crlb_f0_block(b)

@@ -6,7 +6,9 @@ objectives closer than their ~1e-13 disagreement.  The tests compare the
 populations after the run, the best-so-far history (1e-10 relative) and
 the recovered f0 (1e-6 Hz), and report how many members are bit-identical.
 """
+import json
 import math
+import os
 
 import numpy as np
 import pytest
@@ -17,6 +19,7 @@ from gpu_util import assert_chi2_close, block_of, crlb_f0, ctx, settings_of, to_
 from paper_1906_10598_amd import phasetrack as ptk
 
 pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
 def _oracle_fit(b: synth.Block, gens, **kw):
@@ -123,10 +126,39 @@ def test_paper_block_full_fit_sampled():
     assert np.all(pop >= b.lo) and np.all(pop <= b.hi)
     chi_truth = oracle.chi2(s64, b.fs, b.ref, b.truth)
     assert f.objective <= chi_truth
-    sig = crlb_f0(b.n, b.fs, b.truth[0], b.sigma)
-    print(f"[paper full] f0 err {f.coef[2] - b.truth[2]:.3e} Hz (f0-only CRLB {sig:.2e}), "
-          f"chi2 {f.objective:.6f} vs truth {chi_truth:.6f}", flush=True)
-    assert abs(f.coef[2] - b.truth[2]) < 8 * sig * 3
+    sig = crlb_f0(b)
+    print(f"[paper full] f0 err {f.coef[2] - b.truth[2]:.3e} Hz = {(f.coef[2] - b.truth[2]) / sig:+.2f} CRLB "
+          f"({sig:.2e} Hz over A, phi0, f0, f1, f2), chi2 {f.objective:.6f} vs truth {chi_truth:.6f}", flush=True)
+    assert abs(f.coef[2] - b.truth[2]) < 5 * sig
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_paper_block_whole_fit_matches_oracle_fit(seed):
+    # The whole paper-scale fit (400 000 samples, P = 40, 2000 generations,
+    # Sec. 1.3 / Table 4) against the oracle's whole fit of the same block and
+    # the exact least-squares minimiser, both stored by
+    # tests/golden/make_paper_fit.py (oracle only).  The two DE trajectories
+    # part at the first selection near-tie, but both converge to the minimiser:
+    # recovered f0 within 1e-6 Hz, best chi^2 within 1e-10 relative.
+    g = json.load(open(os.path.join(GOLD, f"paper_fit_seed{seed}.json")))
+    b = synth.config1(seed)
+    assert g["n"] == b.n and g["de"]["seed"] == b.de.seed and g["de"]["max_gens"] == b.de.max_gens
+    f = ctx().fit_block(block_of(b, to_dev(b.samples)), settings_of(b))
+    ox, oobj = np.array(g["oracle_fit"]["x"]), g["oracle_fit"]["objective"]
+    mx, mobj = np.array(g["minimiser"]["x"]), g["minimiser"]["objective"]
+    sig = crlb_f0(b)
+    print(f"[paper whole fit seed {seed}] gpu f0 - oracle f0 {f.coef[2] - ox[2]:+.3e} Hz, gpu f0 - minimiser "
+          f"{f.coef[2] - mx[2]:+.3e} Hz, chi2 rel diff {(f.objective - oobj) / oobj:+.3e}; "
+          f"f0 err vs truth {(f.coef[2] - b.truth[2]) / sig:+.2f} CRLB", flush=True)
+    assert f.generations == g["oracle_fit"]["generations"] == 2000
+    assert f.flags == g["oracle_fit"]["flags"]
+    assert abs(f.coef[2] - ox[2]) < 1e-6
+    assert abs(f.coef[2] - mx[2]) < 1e-6
+    assert abs(f.objective - oobj) <= 1e-10 * oobj
+    assert abs(f.objective - mobj) <= 1e-10 * mobj
+    # f1 and f2 sit at the same optimum too (within 1e-4 of their box widths)
+    for j, name in ((3, "f1"), (4, "f2")):
+        assert abs(f.coef[j] - ox[j]) < 1e-4 * (b.hi[j] - b.lo[j]), name
 
 
 def test_window_rule_and_vtr_match_oracle():

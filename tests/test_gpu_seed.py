@@ -104,8 +104,8 @@ def test_seeded_box_covers_truth_and_fit_converges():
               flush=True)
         assert np.all(lo[[0, 2, 3, 4]] < truth[[0, 2, 3, 4]]) and np.all(truth[[0, 2, 3, 4]] < hi[[0, 2, 3, 4]])
         f = ctx().fit_block(block_of(b, dev, lo=lo, hi=hi), settings_of(b))
-        sig = crlb_f0(b.n, b.fs, b.truth[0], b.sigma)
+        sig = crlb_f0(b)
         print(f"[seed {seed}] seeded fit f0 err {f.coef[2] - truth[2]:.3e} Hz = "
               f"{(f.coef[2] - truth[2]) / sig:.2f} CRLB, flags {f.flags}", flush=True)
-        assert abs(f.coef[2] - truth[2]) < 10 * sig
+        assert abs(f.coef[2] - truth[2]) < 5 * sig
         assert not (f.flags & ptk.PT_FLAG_AT_BOUND)

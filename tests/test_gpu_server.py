@@ -16,7 +16,7 @@ import pytest
 
 import oracle
 import synth
-from gpu_util import assert_chi2_close, ctx
+from gpu_util import assert_chi2_close, crlb_f0, ctx
 from paper_1906_10598_amd import phasetrack as ptk
 
 pytestmark = pytest.mark.gpu
@@ -108,8 +108,10 @@ def test_warm_start_tracks_the_phase():
         r = res[(it["track"], it["seq"])]
         b = it["block"]
         err = abs(r.fit.coef[2] - b.truth[2])
-        sig = np.sqrt(6.0) * b.sigma / (np.pi * b.truth[0] * (b.n / b.fs) * np.sqrt(b.n))
-        assert err < 30 * sig, (it["track"], it["seq"], err, sig)
+        sig = crlb_f0(b)  # over the parameters the box frees (f0, f1 and f2 couple)
+        print(f"[server warm] track {it['track']} seq {it['seq']} f0 err {err / sig:.2f} CRLB "
+              f"gens {r.fit.generations}", flush=True)
+        assert err < 12 * sig, (it["track"], it["seq"], err, sig)
         (warm if r.warm else cold).append(r.fit.generations)
         if r.warm:
             # the warm box is the cold half-width times 0.7 around the prediction
