@@ -1788,6 +1788,39 @@ int server_admit(pt_server* sv, hipStream_t s) {
     return PT_OK;
 }
 
+// Standard error of f2 [Hz/s^2] a block of the fitted amplitude and noise
+// determines (Cramer-Rao bound of the phase coefficients phi0, f0, f1, f2 of
+// a cosine in white noise): Fisher information (A^2 / 2 sigma^2) sum_n g g^T,
+// g = (1, 2 pi t, pi t^2, pi t^3 / 3), with the time sums sum t^k taken as
+// fs times the integral over the block's span; sigma^2 = chi^2 / n.
+double sd_f2(const pt_fit& f, const pt_block& b) {
+    const double n = (double)b.n, s2 = f.objective / n, A = std::fabs(f.coef[0]);
+    if (!(A > 0) || !(s2 > 0)) return INFINITY;
+    double m[7];  // sum over the block of t^k
+    for (int k = 0; k <= 6; ++k)
+        m[k] = b.fs * (std::pow(f.t_right, k + 1) - std::pow(f.t_left, k + 1)) / (k + 1);
+    const double c[4] = {1.0, 2.0 * M_PI, M_PI, M_PI / 3.0};  // g_i = c_i t^i
+    double J[4][5];
+    for (int i = 0; i < 4; ++i) {
+        for (int j = 0; j < 4; ++j) J[i][j] = c[i] * c[j] * m[i + j] * A * A / (2.0 * s2);
+        J[i][4] = i == 3 ? 1.0 : 0.0;  // solve J x = e_3: x_3 = (J^-1)_33
+    }
+    for (int col = 0; col < 4; ++col) {  // Gauss-Jordan with partial pivoting
+        int piv = col;
+        for (int r = col + 1; r < 4; ++r)
+            if (std::fabs(J[r][col]) > std::fabs(J[piv][col])) piv = r;
+        if (!(std::fabs(J[piv][col]) > 0)) return INFINITY;
+        for (int k = 0; k < 5; ++k) std::swap(J[col][k], J[piv][k]);
+        for (int r = 0; r < 4; ++r) {
+            if (r == col) continue;
+            const double q = J[r][col] / J[col][col];
+            for (int k = col; k < 5; ++k) J[r][k] -= q * J[col][k];
+        }
+    }
+    const double v = J[3][4] / J[3][3];
+    return v > 0 ? std::sqrt(v) : INFINITY;
+}
+
 // Widen a failed block's box for its next attempt (same centres).
 void enlarge_box(pt_box& b, double k) {
     for (int j = 0; j < PT_NSLOT; ++j) {
@@ -2071,14 +2104,19 @@ int pt_server_step(pt_server* sv, void* hip_stream, int32_t* n_active, int32_t* 
                              (cf.qc_freq_hz > 0 && !(std::fabs(dfreq) <= cf.qc_freq_hz));
             qc = bad ? -1 : 1;
         }
-        // a missed range: the best member on a bound of A, f0 or f1 (f2 and Adot
-        // of short blocks are noise-dominated and may sit on their bounds)
+        // a missed range: the best member on a bound of A, f0 or f1, or of f2
+        // when the block determines f2 to better than a quarter of its box's
+        // half-width (on short blocks f2 and Adot are noise-dominated and may
+        // sit on their bounds; on long ones an f2 pressed against a bound
+        // pulls f0, which correlates with it)
         bool miss = false;
-        for (int j : {0, 2, 3}) {
+        auto on_bound = [&](int j) {
             const double w = sl.blk.box.hi[j] - sl.blk.box.lo[j];
-            if (w > 0 && (f.coef[j] - sl.blk.box.lo[j] <= 1e-6 * w || sl.blk.box.hi[j] - f.coef[j] <= 1e-6 * w))
-                miss = true;
-        }
+            return w > 0 && (f.coef[j] - sl.blk.box.lo[j] <= 1e-6 * w || sl.blk.box.hi[j] - f.coef[j] <= 1e-6 * w);
+        };
+        for (int j : {0, 2, 3})
+            if (on_bound(j)) miss = true;
+        if (on_bound(4) && 0.5 * (sl.blk.box.hi[4] - sl.blk.box.lo[4]) > 4.0 * sd_f2(f, sl.blk)) miss = true;
         const bool policy = cf.max_attempts > 1 || qc_on;  // otherwise every fit is accepted as it is
         const bool failed = policy && (miss || qc < 0);
         if (failed && sl.attempts < cf.max_attempts) {

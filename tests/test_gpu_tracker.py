@@ -192,3 +192,23 @@ def test_discontinuity_is_abandoned_after_max_attempts():
     assert r1.attempts == 3 and r1.qc == -1
     assert r1.fit.flags & ptk.PT_FLAG_ABANDONED and r1.fit.flags & ptk.PT_FLAG_DISCONTINUOUS
     assert res[(0, 2)].qc == 0  # its predecessor was abandoned: no continuity check
+
+
+def test_f2_pressed_against_a_bound_of_a_long_block_is_a_missed_range():
+    # Track 7 of the serving stream: its first block is 2 s long, so the f2 it
+    # hands on is noise (standard error ~0.02 Hz/s^2) and the warm f2 box of the
+    # second, 8 s block (+-0.007 around that prediction) misses the truth.  The
+    # 8 s block determines f2 to 1.6e-4 Hz/s^2, so its best member pressed against
+    # the f2 bound counts as a missed range (Sec. 3.1.1): the block is fitted
+    # again in an enlarged box and its f0 lands within the Cramer-Rao bound
+    # instead of 17 bounds away (f0 and f2 correlate).
+    items = synth.config4_stream(seed=0, ntracks=16, nblocks=160, rate=20.0)[:4]
+    assert (items[3]["track"], items[3]["seq"]) == (7, 1)
+    b = items[3]["block"]
+    r = _serve(items, max_attempts=3, enlarge=2.0)[(7, 1)]
+    err = (r.fit.coef[2] - b.truth[2]) / _crlb(b)
+    print(f"[f2 bound] attempts {r.attempts} flags {r.fit.flags} f2 box [{r.box.lo[4]:.5f}, {r.box.hi[4]:.5f}] "
+          f"truth {b.truth[4]:.5f} f0 err {err:+.2f} CRLB", flush=True)
+    assert r.attempts >= 2 and not (r.fit.flags & ptk.PT_FLAG_ABANDONED)
+    assert r.box.lo[4] < b.truth[4] < r.box.hi[4]
+    assert abs(err) < 5
