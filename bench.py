@@ -258,14 +258,24 @@ def quartic_fit(ctx, ptk, synth, np, torch):
 
 
 def cpu_model():
+    """The host CPU as /proc/cpuinfo names it: model name, and the x86 family /
+    model / stepping numbers (a virtual machine may print only a vendor
+    string as the name)."""
+    info = {}
     try:
         with open("/proc/cpuinfo") as f:
             for line in f:
-                if line.startswith("model name"):
-                    return line.split(":", 1)[1].strip()
+                if not line.strip():
+                    break  # first processor only
+                k, _, v = line.partition(":")
+                info[k.strip()] = v.strip()
     except OSError:
-        pass
-    return None
+        return None
+    name = info.get("model name")
+    if name is None:
+        return None
+    ids = [f"{k} {info[k]}" for k in ("cpu family", "model", "stepping") if k in info]
+    return f"{name} ({', '.join(ids)})" if ids else name
 
 
 def cpu_baseline(b, gens, nthreads):
@@ -312,7 +322,9 @@ def batch_fits(ctx, ptk, synth, np, torch, P, seed, crlb_f0_block, tiles):
                                     "flop_per_candidate_sample": ALG_FLOP,
                                     "note": "whole-batch algorithmic rate (40 FLOP per candidate*sample over the "
                                             "wall time of the batch, DE steps and launch gaps included); above 1 "
-                                            "only because the phasor arithmetic needs ~7 of those 40 operations"}}
+                                            "because the FP64 phasor arithmetic executes ~12 FP64 operations per "
+                                            "candidate*sample for the same result (`executed` gives the counter "
+                                            "rate); the mixed path's per-sample FP32 cosine executes ~27 FP32 and ~2 FP64"}}
     batch["workload"] = ("64 blocks, N log-uniform in [5e4, 4e5] at 50 kHz (total %d samples), own "
                          "populations P=40, 1500 generations, one launch per generation" % sum(x.n for x in blocks))
     g = batch["fp64"]["geometry"]

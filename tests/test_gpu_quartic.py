@@ -21,7 +21,7 @@ from paper_1906_10598_amd import phasetrack as ptk
 
 pytestmark = pytest.mark.gpu
 
-MIXED_REL = 2e-6
+MIXED_REL = 3e-7  # see the derivation beside the same bound in test_gpu_objective.py
 
 
 def _check(b, pop, precision=ptk.PT_PREC_FP64, method=ptk.PT_FP64_AUTO, rel=1e-10):
