@@ -54,7 +54,7 @@ struct BlockDesc {
     int act[kSlots];  // active slots, increasing
     int window;
     int max_gens;
-    int pad0;
+    int fresh;        // serving: the block's slot starts a new fit (k_de_init_fresh)
     double lo[kSlots];
     double hi[kSlots];
     double F, CR, vtr, rel_tol;
@@ -71,7 +71,7 @@ struct BlockDesc {
                        // form: the block's launch index at the launch's first step (0 for a fit)
     int objective;     // 0 = chi-square (Eq. 2-2-4), 1 = correlation (Eq. 2-2-5)
     int quartic;       // nonzero: the phase has the fourth-order term f3 (slot 6)
-    int pad2;
+    int amask;         // bit j set when slot j is active (the slots of act[0 .. D))
     // Leading-step launches (k_objective with fused >= 2) alternate between two
     // copies of the DE buffers: launch parity p reads the state of slot p and
     // the rows, objectives and partials of slot p ^ 1, and writes the others.

@@ -803,9 +803,10 @@ struct Draws {
     unsigned cross;
 };
 
-__device__ __forceinline__ Draws trial_draws(const BlockDesc* __restrict__ d, int i, uint32_t gn) {
-    const int P = d->P;
-    const U4 w = draw4(d->seed, d->stream, (uint32_t)i, gn, kTagMut, 0u);
+// Draws from the Philox words of member i: w (the mutation call) and u0, u1
+// (the crossover calls of active coordinates 0-3 and 4-7).
+__device__ __forceinline__ Draws draws_from(const U4& w, const U4& u0, const U4& u1, int i, int P, int D,
+                                            double CR) {
     Draws r;
     int r1 = index_from(w.x, P - 1);
     if (r1 >= i) ++r1;
@@ -821,18 +822,47 @@ __device__ __forceinline__ Draws trial_draws(const BlockDesc* __restrict__ d, in
     if (r3 >= e0) ++r3;
     if (r3 >= e1) ++r3;
     if (r3 >= e2) ++r3;
-    const int jr = index_from(w.w, d->D);
+    const int jr = index_from(w.w, D);
     unsigned cross = 0;
-    U4 u{0, 0, 0, 0};
-    for (int a = 0; a < d->D; ++a) {
-        if ((a & 3) == 0) u = draw4(d->seed, d->stream, (uint32_t)i, gn, kTagXover, (uint32_t)(a >> 2));
-        if (unit_from(word(u, a & 3)) < d->CR || a == jr) cross |= 1u << a;
+#pragma unroll
+    for (int a = 0; a < kSlots; ++a) {
+        const uint32_t x = word(a < 4 ? u0 : u1, a & 3);
+        if (a < D && (unit_from(x) < CR || a == jr)) cross |= 1u << a;
     }
     r.r1 = r1;
     r.r2 = r2;
     r.r3 = r3;
     r.cross = cross;
     return r;
+}
+
+__device__ __forceinline__ Draws trial_draws(const BlockDesc* __restrict__ d, int i, uint32_t gn) {
+    const U4 w = draw4(d->seed, d->stream, (uint32_t)i, gn, kTagMut, 0u);
+    const U4 u0 = draw4(d->seed, d->stream, (uint32_t)i, gn, kTagXover, 0u);
+    U4 u1{0, 0, 0, 0};
+    if (d->D > 4) u1 = draw4(d->seed, d->stream, (uint32_t)i, gn, kTagXover, 1u);
+    return draws_from(w, u0, u1, i, d->P, d->D, d->CR);
+}
+
+// The same draws made by the eight lanes of an octet (lanes 8c .. 8c + 7 of
+// one wave, all active, all for member i): lane k of the octet evaluates one
+// Philox call (k = 0 the mutation call, k = 1, 2 the crossover calls), the
+// octet exchanges the words and every lane derives the draws.  One Philox
+// chain per lane instead of three in a row; bit-identical to trial_draws.
+__device__ __forceinline__ Draws trial_draws_octet(const BlockDesc* __restrict__ d, int i, uint32_t gn) {
+    const int lane = (int)(threadIdx.x & 63u), k = lane & 7, base = lane & ~7;
+    const U4 mine = draw4(d->seed, d->stream, (uint32_t)i, gn, k == 0 ? kTagMut : kTagXover,
+                          (uint32_t)(k == 0 ? 0 : k - 1));
+    auto from = [&](int src) {
+        U4 v;
+        v.x = (uint32_t)__shfl((int)mine.x, base + src, 64);
+        v.y = (uint32_t)__shfl((int)mine.y, base + src, 64);
+        v.z = (uint32_t)__shfl((int)mine.z, base + src, 64);
+        v.w = (uint32_t)__shfl((int)mine.w, base + src, 64);
+        return v;
+    };
+    const U4 w = from(0), u0 = from(1), u1 = from(2);
+    return draws_from(w, u0, u1, i, d->P, d->D, d->CR);
 }
 
 // Trial vector y of member i from the selected population xs (P x kSlots,
@@ -1030,13 +1060,16 @@ __global__ __launch_bounds__(1024) void k_de_step(const BlockDesc* __restrict__ 
 // Returns false when there is nothing to evaluate (BOOK, or the fit has
 // stopped); otherwise the group's candidates are in cs, past a barrier.
 // lds: the DE step's dynamic LDS plus P * kSlots doubles (2 P kSlots + 2 *
-// 256 doubles + 256 ints).
+// 256 doubles + 256 ints).  Workgroups of kThreads threads (k_objective's):
+// a compile-time count keeps the launch's geometry out of the chain of
+// dependent loads before the step's data loads.
 // ---------------------------------------------------------------------------
 template <int CPG, bool BOOK, typename RT, int RS>
 __device__ __forceinline__ bool de_lead(const BlockDesc* __restrict__ d, int L, int tile, int group, Cand* cs,
                                         double* lds, const RT (&raw)[RS]) {
     const int p = L & 1;
-    const int P = d->P, NT = blockDim.x, i = threadIdx.x;
+    constexpr int NT = kThreads;
+    const int P = d->P, i = threadIdx.x;
     double* xs = lds;                              // P x kSlots: trial rows, then the selected rows
     double* red = xs + (size_t)P * kSlots;         // NT
     double* fr = red + NT;                         // NT
@@ -1107,12 +1140,13 @@ __device__ __forceinline__ bool de_lead(const BlockDesc* __restrict__ d, int L, 
     // with the step's other data rather than after the selection
     const int jc = j < kSlots ? j : kSlots - 1;
     const double lo_j = gld(&d->lo[jc]), hi_j = gld(&d->hi[jc]);
-    int a_j = -1;
-    for (int q = 0; q < d->D; ++q)
-        if (d->act[q] == j) a_j = q;
+    const unsigned am = (unsigned)d->amask;
+    const int a_j = ((am >> j) & 1u) ? __builtin_popcount(am & ((1u << j) - 1u)) : -1;
     const double Fm = d->F, fs = d->fs;
     Draws dr{0, 0, 0, 0u};
-    if (tw) dr = trial_draws(d, cbase + c, (uint32_t)L);
+    // (every lane of the wave makes the octet draws, so that the octets'
+    // exchanges see all their lanes; only those with tw use them)
+    if (!BOOK && L > 0 && i < 64) dr = trial_draws_octet(d, cbase + c, (uint32_t)L);
 
     // 3. objectives of all P trials, in reduce_partials' order
     double sp = 0.0;
@@ -1359,6 +1393,15 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 4))
         return;
     }
     const BlockDesc* __restrict__ d = descs + find_block(descs, nblk, unit);
+    // leading-step form: every descriptor field read before the step's data
+    // loads, fetched together (left to the compiler, they came in three
+    // dependent scalar round trips).  The empty asm only makes the compiler
+    // hold them all in scalar registers at this point; it emits nothing.
+    if constexpr (LEAD)
+        asm volatile("" ::"s"(d->samples), "s"(d->n), "s"(d->P), "s"(d->ntiles), "s"(d->ngroups),
+                     "s"(d->unit_begin), "s"(d->gen_begin), "s"(d->st), "s"(d->st2), "s"(d->pop), "s"(d->pop2),
+                     "s"(d->trial), "s"(d->trial2), "s"(d->fpop), "s"(d->fpop2), "s"(d->partials),
+                     "s"(d->partials2));
     // (the leading-step form reads its stop state inside de_lead, which must
     // also run after a stop to copy the state forward)
     if (!LEAD && d->st != nullptr && d->st->done) return;
@@ -1528,12 +1571,12 @@ __global__ void k_sync_reset(const BlockDesc* __restrict__ descs) {
 }
 #endif
 
-// Initial population of the blocks flagged fresh (BlockDesc::pad0 != 0);
+// Initial population of the blocks flagged fresh (BlockDesc::fresh != 0);
 // the others keep their running state.  Used by the serving loop.
 #ifndef PT_INSTANCE_TU  // (the instance translation units hold only templates)
 __global__ void k_de_init_fresh(const BlockDesc* __restrict__ descs) {
     const BlockDesc* d = descs + blockIdx.x;
-    if (d->pad0) init_block(d);
+    if (d->fresh) init_block(d);
 }
 #endif
 

@@ -514,7 +514,10 @@ BlockDesc base_desc(const pt_block& B, const pt_de_settings* de, int ntiles, int
     for (int j = 0; j < kSlots; ++j) {
         d.lo[j] = B.box.lo[j];
         d.hi[j] = B.box.hi[j];
-        if (B.box.lo[j] < B.box.hi[j]) d.act[D++] = j;
+        if (B.box.lo[j] < B.box.hi[j]) {
+            d.act[D++] = j;
+            d.amask |= 1 << j;
+        }
     }
     d.D = D;
     d.ntiles = ntiles;
@@ -1996,7 +1999,10 @@ int pt_server_step(pt_server* sv, void* hip_stream, int32_t* n_active, int32_t* 
         for (int j = 0; j < kSlots; ++j) {
             d.lo[j] = B.box.lo[j];
             d.hi[j] = B.box.hi[j];
-            if (B.box.lo[j] < B.box.hi[j]) d.act[D++] = j;
+            if (B.box.lo[j] < B.box.hi[j]) {
+                d.act[D++] = j;
+                d.amask |= 1 << j;
+            }
         }
         d.D = D;
         d.ntiles = (int)((B.n + tile - 1) / tile);
@@ -2029,7 +2035,7 @@ int pt_server_step(pt_server* sv, void* hip_stream, int32_t* n_active, int32_t* 
             d.gen_begin = sl.fresh ? 0 : sl.lead;
         }
         d.objective = de.objective;
-        d.pad0 = sl.fresh ? 1 : 0;  // k_de_init initialises only fresh slots
+        d.fresh = sl.fresh ? 1 : 0;  // k_de_init_fresh initialises only these
         any_fresh = any_fresh || sl.fresh;
         hd[q] = d;
     }
