@@ -482,6 +482,11 @@ def main():
     extra = max(0, args.latency_fits - args.steps)
     _, lat_more, _ = run_fits(ctx, blk, lambda k: de(ptk.PT_PREC_FP64)(args.steps + k), extra, "fp64-lat")
     lat64 = lat_steps + lat_more
+    # first fits of a fresh context at the same geometry: the first one captures
+    # and instantiates the fit's launch graphs, the second replays them
+    with ptk.Context(0) as cold:
+        ptk.pt_ctx_set_tile(cold.handle, *tiles["fp64"])
+        _, lat_cold, _ = run_fits(cold, blk, de(ptk.PT_PREC_FP64), 2, "fp64-cold")
     run_fits(ctx, blk, de(ptk.PT_PREC_MIXED), max(1, args.warmup), "mixed-warm")
     el_mx, lat_mx, fits_mx = run_fits(ctx, blk, de(ptk.PT_PREC_MIXED), max(args.latency_fits, 1), "mixed")
     value_mx = pairs_per_fit * len(lat_mx) / el_mx
@@ -617,7 +622,8 @@ def main():
                    "arithmetic": arith64,
                    "geometry": {"samples_per_lane": tiles["fp64"][0], "cand_per_group": tiles["fp64"][1]}},
         "latency_ms": {
-            "fp64": {"p50": pct(lat64, 50), "p99": pct(lat64, 99), "fits": len(lat64)},
+            "fp64": {"p50": pct(lat64, 50), "p99": pct(lat64, 99), "fits": len(lat64),
+                     "first_fit_new_context": lat_cold[0], "second_fit_new_context": lat_cold[1]},
             "mixed": {"p50": pct(lat_mx, 50), "p99": pct(lat_mx, 99), "fits": len(lat_mx)},
         },
         "block_fits_per_s": {"fp64": args.steps / elapsed, "mixed": len(lat_mx) / el_mx},

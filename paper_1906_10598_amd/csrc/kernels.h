@@ -670,7 +670,9 @@ __device__ __forceinline__ void objective_unit(const BlockDesc* __restrict__ d, 
     // one FP64 partial per (candidate, tile): each wave adds one candidate's four
     // wave-slices lane by lane, then a fixed-order shuffle butterfly
     for (int c = wave; c < ncand; c += kThreads / 64) {
-        double v = ((red[c][lane] + red[c][lane + 64]) + red[c][lane + 128]) + red[c][lane + 192];
+        double v = red[c][lane];
+#pragma unroll
+        for (int q = 1; q < kThreads / 64; ++q) v += red[c][lane + 64 * q];
         v = wave_sum(v);
         if (lane == 0) xst(part + (size_t)(cbase + c) * d->ntiles + tile, v);
     }

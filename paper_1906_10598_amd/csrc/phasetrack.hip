@@ -285,13 +285,22 @@ struct pt_ctx {
                                                               o.iters, o.fused, o.base, o.launches);
         }
     };
-    std::map<GraphKey, hipGraphExec_t> graphs;
+    // Cached graph executables, at most kMaxGraphs (the leading-step form keeps
+    // one per chunk of a fit, so a context that fits many shapes would
+    // otherwise grow without bound); `used` orders them for eviction.
+    struct GraphEntry {
+        hipGraphExec_t exec;
+        uint64_t used;
+    };
+    static constexpr size_t kMaxGraphs = 256;
+    std::map<GraphKey, GraphEntry> graphs;
+    uint64_t graph_clock = 0;
     // resident workgroups per compute unit of an objective kernel instance
     // with the leading step's LDS, by (kernel, dynamic LDS bytes)
     std::map<std::pair<const void*, size_t>, int> resident;
 
     void drop_graphs() {
-        for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+        for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second.exec);
         graphs.clear();
     }
 };
@@ -456,8 +465,27 @@ int get_graph(pt_ctx* ctx, const Plan& pl, int iters, int base, hipGraphExec_t* 
                          pl.mode, (int)pl.slope, pl.de_threads, pl.de_lds, iters, (int)pl.fused, base, sig};
     auto it = ctx->graphs.find(key);
     if (it != ctx->graphs.end()) {
-        *out = it->second;
+        it->second.used = ++ctx->graph_clock;
+        *out = it->second.exec;
         return PT_OK;
+    }
+    if (ctx->graphs.size() >= pt_ctx::kMaxGraphs) {
+        // Evict the least recently used quarter.  A fit without the window rule
+        // queues all its chunks at once, so an old executable may still be
+        // queued: wait for the device first (a rare path, taken only when a
+        // new graph is captured anyway).
+        HIPCHK(hipDeviceSynchronize());
+        std::vector<std::pair<uint64_t, const pt_ctx::GraphKey*>> order;
+        for (const auto& kv : ctx->graphs) order.push_back({kv.second.used, &kv.first});
+        std::sort(order.begin(), order.end(),
+                  [](const auto& a, const auto& b) { return a.first < b.first; });
+        std::vector<pt_ctx::GraphKey> victims;
+        for (size_t k = 0; k < pt_ctx::kMaxGraphs / 4; ++k) victims.push_back(*order[k].second);
+        for (const pt_ctx::GraphKey& v : victims) {
+            auto vi = ctx->graphs.find(v);
+            (void)hipGraphExecDestroy(vi->second.exec);
+            ctx->graphs.erase(vi);
+        }
     }
     hipStream_t cs = ctx->cap_stream;
     HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
@@ -474,7 +502,7 @@ int get_graph(pt_ctx* ctx, const Plan& pl, int iters, int base, hipGraphExec_t* 
     e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) return fail(PT_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
-    ctx->graphs[key] = ex;
+    ctx->graphs[key] = {ex, ++ctx->graph_clock};
     *out = ex;
     return PT_OK;
 }

@@ -47,10 +47,14 @@ COUNTER_KEYS = {"SQ_INSTS_VALU": "valu", "SQ_WAVES": "waves",
 
 
 def kernel_hash():
+    """sha256 of the kernel sources and of build.py (its compiler flags shape
+    the code too), first 16 hex digits."""
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         with open(os.path.join(CSRC, f), "rb") as fh:
             h.update(fh.read())
+    with open(os.path.join(ROOT, "paper_1906_10598_amd", "build.py"), "rb") as fh:
+        h.update(fh.read())
     return h.hexdigest()[:16]
 
 
@@ -152,7 +156,7 @@ def summarise(root, kernel, command, form, workload):
     if m:
         geo = f" geometry={m.group(1)},{m.group(2)}"
     head = [f"# rocprofv3 summary: `{kernel}`\n", "Command(s):\n", "```", command, "```\n",
-            f"Kernel sources hash: {kernel_hash()} (sha256 of csrc/{', '.join(KERNEL_SOURCES)})\n"]
+            f"Kernel sources hash: {kernel_hash()} (sha256 of csrc/{', '.join(KERNEL_SOURCES)} and build.py)\n"]
     if avg_ns:
         head.append(f"Average duration of the kernel: {avg_ns / 1e3:.3f} us over {calls} dispatches\n")
     if traffic is not None:

@@ -125,3 +125,25 @@ def test_timed_fit_equals_two_launch_form(mode):
         ptk.pt_ctx_set_timing(c.handle, False)
     assert nl == de.max_gens + 1 and ms > 0.0
     _same(a, _fit(ptk.PT_FUSION_OFF, [block_of(b, dev)], de), f"timed fusion {mode} paper")
+
+
+def test_graph_cache_eviction_keeps_fits_bitwise():
+    # the leading-step form captures one graph per 50-generation chunk (the
+    # launch index is a kernel argument); a fit of 13 000 generations needs 260
+    # of them, more than a context caches (256), so the cache evicts its least
+    # recently used quarter in the middle of the fit (after waiting for the
+    # device, since the fit's earlier chunks are still queued) and again during
+    # the next fit, which finds its first chunks evicted
+    b = synth.config0(2)
+    dev = to_dev(b.samples)
+    de = settings_of(b, gens=13_000, rel_tol=0.0, window=0)
+    with ptk.Context(0) as c:
+        ptk.pt_ctx_set_step_fusion(c.handle, ptk.PT_FUSION_LEAD)
+        first = c.fit_block(block_of(b, dev), de)
+        second = c.fit_block(block_of(b, dev), de)
+    ref = _fit(ptk.PT_FUSION_OFF, [block_of(b, dev)], de)[0][0]
+    assert ref.generations == 13_000
+    for f in (first, second):
+        assert list(f.coef) == list(ref.coef) and f.objective == ref.objective
+        assert f.generations == ref.generations and f.flags == ref.flags
+    print(f"[graph eviction] 13000-generation fits bit-identical to the two-launch form", flush=True)

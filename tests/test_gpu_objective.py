@@ -27,11 +27,22 @@ pytestmark = pytest.mark.gpu
 # At the optimum, where the DE selection compares near-equal objectives, the
 # residuals are noise and those errors average down: 1.7e-9 measured at a
 # fitted best, bound 1e-8 (MIXED_REL_AT_OPTIMUM).  The hi/lo split of the
-# linear phase term keeps the FP32 phase offset exact to 2^-24 turns; a CPU
-# emulation without it moves the objective at the truth by 2e-9 instead of
-# 7e-10, below what either bound can separate.
+# linear phase term keeps the FP32 phase offset below one turn; without it
+# the objective at the truth of a noisy block moves by 2e-9 instead of 7e-10
+# (CPU emulation), below what either bound can separate, so the split is
+# pinned by the noise-free test below (MIXED_NOISE_FREE).
 MIXED_REL = 3e-7
 MIXED_REL_AT_OPTIMUM = 1e-8
+# Noise-free FP32 samples of the model at the truth: chi^2 / (n A^2) is the mean
+# square of the mixed path's per-sample model error.  With the hi/lo split the
+# FP32 local phase stays below one turn, so each of its ~4 roundings is
+# uniform within half an ulp of 2^-24 turns: variance 4 (2^-24)^2 / 12 turns^2,
+# (2 pi)^2 times that = 4.7e-14 rad^2; the FP32 cosine (1.1e-8), the FP32
+# samples and residual (ulp 6e-8 at |s| < 1) add ~1e-15.  Bound 1e-13.  Without
+# the split the FP32 product b1 j reaches 0.4 S turns (f0 near 20 kHz at
+# 50 kHz): roundings at an ulp of 2^-21 or 2^-20 give 5e-13 (S = 16) and 3e-12
+# (S = 32) in a CPU emulation of the same steps, against 1.2e-14 with it.
+MIXED_NOISE_FREE = 1e-13
 
 
 def _eval(block, pop, precision=ptk.PT_PREC_FP64):
@@ -201,6 +212,27 @@ def test_mixed_precision_error_stated():
     at_truth = abs(got[0] - want[0]) / want[0]
     print(f"[mixed at the truth] rel err {at_truth:.3e}", flush=True)
     assert at_truth <= MIXED_REL_AT_OPTIMUM
+
+
+@pytest.mark.parametrize("spl", [16, 32])
+def test_mixed_noise_free_high_frequency_pins_the_linear_term_split(spl):
+    n, fs = 200_000, 50_000.0
+    ref = n / 2
+    x = np.array([0.7, 1.3, 19_876.5, 2.5, 0.02, 0.0])
+    t = (np.arange(n) - ref) / fs
+    s = (x[0] * np.cos(x[1] + 2 * np.pi * (x[2] * t + x[3] * t * t / 2 + x[4] * t ** 3 / 6))).astype(np.float32)
+    b = synth.Block(s, fs, ref, x, x - [0.1, 3, 1, 1, 0.01, 0], x + [0.1, 3, 1, 1, 0.01, 0],
+                    synth.DESettings(8, 1), 0.0, name="noise-free 20 kHz")
+    c = ctx()
+    ptk.pt_ctx_set_tile(c.handle, spl, 8)
+    try:
+        got = _eval(block_of(b, to_dev(s)), np.vstack([x]), precision=ptk.PT_PREC_MIXED)
+        assert ptk.pt_ctx_last_arithmetic(c.handle) == ptk.PT_ARITH_MIXED
+    finally:
+        ptk.pt_ctx_set_tile(c.handle, 0, 0)
+    ms = got[0] / n / x[0] ** 2
+    print(f"[mixed noise-free f0 20 kHz S={spl}] chi2/(n A^2) {ms:.3e}, bound {MIXED_NOISE_FREE:.0e}", flush=True)
+    assert ms <= MIXED_NOISE_FREE
 
 
 def test_objective_deterministic():
