@@ -105,3 +105,32 @@ def crlb_f0(b: synth.Block):
     from synth.crlb import crlb_f0_block
 
     return crlb_f0_block(b)
+
+
+# Mixed precision, noise-free FP32 samples of the model at the truth:
+# chi^2 / (n A^2) is the mean square of the mixed path's per-sample model
+# error.  With the hi/lo split of the linear phase term the FP32 local phase
+# stays below one turn, so each of its ~4 roundings is uniform within half an
+# ulp of 2^-24 turns: variance 4 (2^-24)^2 / 12 turns^2, (2 pi)^2 times that
+# = 4.7e-14 rad^2; the FP32 cosine (1.1e-8), the FP32 samples and residual
+# (ulp 6e-8 at |s| < 1) add ~1e-15.  Bound 1e-13.  Without the split the FP32
+# product b1 j reaches 0.4 S turns (f0 near 20 kHz at 50 kHz): roundings at an
+# ulp of 2^-21 or 2^-20 give 5e-13 (S = 16) and 3e-12 (S = 32) in a CPU
+# emulation of the same steps, against 1.2e-14 with it.
+MIXED_NOISE_FREE = 1e-13
+
+
+def mixed_rel_at_optimum(n, chi2, amp, spl=32):
+    """Bound on the mixed path's relative chi^2 error at a fitted optimum of
+    an n-sample block (chi2: its objective, amp: the amplitude, spl: samples
+    per lane, 32 at most).  There the residuals rho are noise of variance
+    s^2 = chi2 / n, independent of the mixed model's per-sample error e
+    (rms e_m <= sqrt(MIXED_NOISE_FREE) A = 3.2e-7 A), so chi^2 moves by
+    2 sum rho e + sum e^2, of rms 2 s e_m sqrt(n): relative 2 (e_m / s) / sqrt(n).
+    The FP32 lane sums of spl terms add a relative rounding of rms
+    2^-24 / sqrt(3) per addition, 2e-8 spl / sqrt(n) over the block.  The
+    bound is five times the sum of the two rms figures: 1.2e-8 for the
+    paper-scale block at 0 dB, 1.2e-7 for a 50 000-sample block at 15 dB."""
+    s = math.sqrt(chi2 / n)
+    e_m = math.sqrt(MIXED_NOISE_FREE) * amp
+    return 5.0 * (2.0 * e_m / s + 2e-8 * spl) / math.sqrt(n)

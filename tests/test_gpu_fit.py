@@ -15,7 +15,7 @@ import pytest
 
 import oracle
 import synth
-from gpu_util import assert_chi2_close, block_of, crlb_f0, ctx, settings_of, to_dev
+from gpu_util import assert_chi2_close, block_of, crlb_f0, ctx, mixed_rel_at_optimum, settings_of, to_dev
 from paper_1906_10598_amd import phasetrack as ptk
 
 pytestmark = pytest.mark.gpu
@@ -283,3 +283,47 @@ def test_batch_splits_blocks_by_arithmetic():
     # the poly block against the oracle
     ref = _oracle_fit(sel[2], 20)
     assert_chi2_close([batch[2].objective], [ref["objective"]], sel[2].n)
+
+
+@pytest.mark.parametrize("precision", [ptk.PT_PREC_FP64, ptk.PT_PREC_MIXED])
+def test_full_64_block_batch_as_benchmarked(precision):
+    # The batched workload at full size -- 64 blocks, N log-uniform in
+    # [5e4, 4e5] at 50 kHz, SNR in [-5, 10] dB, own populations of 40, 1500
+    # generations -- launched as the benchmark launches it: automatic launch
+    # form, and the geometry the benchmark's autotuner picks on MI355X (32 x 8
+    # FP64, 16 x 8 mixed).  Sampled outputs against the oracle one by one:
+    # the reported objective is the oracle's chi^2 at the reported
+    # coefficients (FP64 1e-10; mixed, at its optimum, mixed_rel_at_optimum,
+    # which grows with the block's SNR and shrinks with its length), and
+    # the block fitted alone gives the same fit bit for bit.  Every block:
+    # all generations run and f0 within 6 Cramer-Rao bounds of the truth.
+    blocks = synth.config3(0)
+    assert len(blocks) == 64
+    devs = [to_dev(b.samples) for b in blocks]
+    pbs = [block_of(b, d) for b, d in zip(blocks, devs)]
+    seed = synth.config1(0).de.seed  # the benchmark's seed
+    de = ptk.make_settings(pop=40, max_gens=blocks[0].de.max_gens, F=0.5, CR=0.9, seed=seed, precision=precision)
+    c = ctx()
+    geo = (32, 8) if precision == ptk.PT_PREC_FP64 else (16, 8)
+    ptk.pt_ctx_set_tile(c.handle, *geo)
+    try:
+        fits = c.fit_batch(pbs, de)
+        sizes = [b.n for b in blocks]
+        sample = sorted({0, int(np.argmax(sizes)), int(np.argmin(sizes)), 48})
+        alone = {k: c.fit_block(pbs[k], de) for k in sample}
+    finally:
+        ptk.pt_ctx_set_tile(c.handle, 0, 0)
+    errs = []
+    for b, f in zip(blocks, fits):
+        assert f.generations == de.max_gens, b.name
+        errs.append(abs(f.coef[2] - b.truth[2]) / crlb_f0(b))
+    for k in sample:
+        b, f = blocks[k], fits[k]
+        want = oracle.chi2(np.asarray(b.samples, dtype=np.float64), b.fs, b.ref, list(f.coef))
+        rel = 1e-10 if precision == ptk.PT_PREC_FP64 else mixed_rel_at_optimum(b.n, want, f.coef[0], geo[0])
+        assert abs(f.objective - want) <= rel * want, (b.name, f.objective, want, rel)
+        a = alone[k]
+        assert list(a.coef) == list(f.coef) and a.objective == f.objective, b.name
+    print(f"[64-block batch prec={precision} geometry={geo}] sampled {sample}: objective == oracle chi^2 and "
+          f"== fit alone; f0 error median {np.median(errs):.2f}, max {max(errs):.2f} CRLB", flush=True)
+    assert max(errs) < 6.0

@@ -12,7 +12,8 @@ import pytest
 
 import oracle
 import synth
-from gpu_util import assert_chi2_close, block_of, ctx, model_phase_err, phase_rounding_bound, random_population, to_dev
+from gpu_util import (MIXED_NOISE_FREE, assert_chi2_close, block_of, ctx, mixed_rel_at_optimum, model_phase_err,
+                      phase_rounding_bound, random_population, to_dev)
 from paper_1906_10598_amd import phasetrack as ptk
 
 pytestmark = pytest.mark.gpu
@@ -26,23 +27,12 @@ pytestmark = pytest.mark.gpu
 # emulation of the same FP32 steps gives 2e-8 to 7e-8).  The bound is 3e-7.
 # At the optimum, where the DE selection compares near-equal objectives, the
 # residuals are noise and those errors average down: 1.7e-9 measured at a
-# fitted best, bound 1e-8 (MIXED_REL_AT_OPTIMUM).  The hi/lo split of the
-# linear phase term keeps the FP32 phase offset below one turn; without it
-# the objective at the truth of a noisy block moves by 2e-9 instead of 7e-10
-# (CPU emulation), below what either bound can separate, so the split is
-# pinned by the noise-free test below (MIXED_NOISE_FREE).
+# fitted best, bound mixed_rel_at_optimum (1.2e-8 for this block).  The hi/lo
+# split of the linear phase term keeps the FP32 phase offset below one turn;
+# without it the objective at the truth of a noisy block moves by 2e-9
+# instead of 7e-10 (CPU emulation), below what either bound can separate, so
+# the split is pinned by the noise-free test below (MIXED_NOISE_FREE).
 MIXED_REL = 3e-7
-MIXED_REL_AT_OPTIMUM = 1e-8
-# Noise-free FP32 samples of the model at the truth: chi^2 / (n A^2) is the mean
-# square of the mixed path's per-sample model error.  With the hi/lo split the
-# FP32 local phase stays below one turn, so each of its ~4 roundings is
-# uniform within half an ulp of 2^-24 turns: variance 4 (2^-24)^2 / 12 turns^2,
-# (2 pi)^2 times that = 4.7e-14 rad^2; the FP32 cosine (1.1e-8), the FP32
-# samples and residual (ulp 6e-8 at |s| < 1) add ~1e-15.  Bound 1e-13.  Without
-# the split the FP32 product b1 j reaches 0.4 S turns (f0 near 20 kHz at
-# 50 kHz): roundings at an ulp of 2^-21 or 2^-20 give 5e-13 (S = 16) and 3e-12
-# (S = 32) in a CPU emulation of the same steps, against 1.2e-14 with it.
-MIXED_NOISE_FREE = 1e-13
 
 
 def _eval(block, pop, precision=ptk.PT_PREC_FP64):
@@ -210,8 +200,9 @@ def test_mixed_precision_error_stated():
     pop[0] = b.truth
     got, want = _check(b, pop, precision=ptk.PT_PREC_MIXED, rel=MIXED_REL)
     at_truth = abs(got[0] - want[0]) / want[0]
-    print(f"[mixed at the truth] rel err {at_truth:.3e}", flush=True)
-    assert at_truth <= MIXED_REL_AT_OPTIMUM
+    bound = mixed_rel_at_optimum(b.n, want[0], b.truth[0])
+    print(f"[mixed at the truth] rel err {at_truth:.3e}, bound {bound:.2e}", flush=True)
+    assert at_truth <= bound
 
 
 @pytest.mark.parametrize("spl", [16, 32])
