@@ -170,3 +170,61 @@ def test_leading_step_server_equals_default():
     assert max_active >= 2
     for k in ref:
         assert _key(ref[k]) == _key(lead[k]), k
+
+
+def test_served_stream_as_benchmarked():
+    # The serving workload at full size: the first 32 arrivals of the 16-track
+    # stream the benchmark serves (N in {1e5, 2e5, 4e5, 1e6} at 50 kHz), with
+    # its settings (window 1e-9 over 50 generations, cap 3000; up to three
+    # attempts with the range doubled; continuity limits 0.5 rad / 0.1 Hz),
+    # submitted at once.  Sampled blocks -- the first of each length and every
+    # retried one -- equal pt_fit_block in the box the server used, bit for
+    # bit, and their objectives equal the oracle's chi^2 at their
+    # coefficients; every block's f0 is within 12 Cramer-Rao bounds.
+    items = synth.config4_stream(seed=0, ntracks=16, nblocks=160, rate=20.0)[:32]
+    de = ptk.make_settings(pop=40, max_gens=3000, F=0.5, CR=0.9, seed=0x19061059 ^ 0xDE, rel_tol=1e-9, window=50)
+    cfg = ptk.make_server_config(de, max_slots=64, gens_per_step=32, hbm_budget_bytes=64 << 30, max_attempts=3,
+                                 enlarge=2.0, qc_phase_rad=0.5, qc_freq_hz=0.1)
+    c = ctx()
+    srv = ptk.pt_server_create(c.handle, cfg)
+    try:
+        tick = {}
+        for k, it in enumerate(items):
+            t = ptk.pt_server_submit(srv, it["track"], _blk(it))
+            assert t is not None
+            tick[t] = k
+        res = {}
+        for _ in range(100_000):
+            a, p = ptk.pt_server_step(srv, ptk.current_stream())
+            for r in ptk.pt_server_poll(srv):
+                res[tick[r.ticket]] = r
+            if a == 0 and p == 0:
+                break
+    finally:
+        ptk.pt_server_destroy(srv)
+    assert len(res) == len(items)
+    lengths = sorted({it["block"].n for it in items})
+    sample = sorted({min(k for k, it in enumerate(items) if it["block"].n == n) for n in lengths} |
+                    {k for k, r in res.items() if r.attempts > 1})
+    errs = []
+    for k, it in enumerate(items):
+        r, b = res[k], it["block"]
+        assert not (r.fit.flags & ptk.PT_FLAG_ABANDONED), k
+        errs.append(abs(r.fit.coef[2] - b.truth[2]) / crlb_f0(b))
+    ptk.pt_ctx_set_tile(c.handle, 16, 4)  # the server's geometry
+    try:
+        for k in sample:
+            r, b = res[k], items[k]["block"]
+            blk = _blk(items[k])
+            blk.box = r.box
+            f = c.fit_block(blk, de)
+            assert list(f.coef) == list(r.fit.coef) and f.objective == r.fit.objective, k
+            assert f.generations == r.fit.generations, k
+            chi = oracle.chi2(b.samples.astype(np.float64), b.fs, b.ref, list(r.fit.coef))
+            assert abs(r.fit.objective - chi) <= 1e-10 * chi, (k, r.fit.objective, chi)
+    finally:
+        ptk.pt_ctx_set_tile(c.handle, 0, 0)
+    print(f"[served stream] {len(items)} blocks, lengths {lengths}, sampled {sample} (retried "
+          f"{sum(r.attempts > 1 for r in res.values())}): == pt_fit_block and the oracle's chi^2; f0 error median "
+          f"{np.median(errs):.2f}, max {max(errs):.2f} CRLB", flush=True)
+    assert max(errs) < 12.0
