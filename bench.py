@@ -311,7 +311,7 @@ def batch_fits(ctx, ptk, synth, np, torch, P, seed, crlb_f0_block, tiles):
         fits_b = ctx.fit_batch(pbs, deb)
         dt = time.perf_counter() - t0
         errs = [abs(f.coef[2] - x.truth[2]) / crlb_f0_block(x) for f, x in zip(fits_b, blocks)]
-        geo = list(ptk.pt_ctx_get_tile(ctx.handle, 400_000, P, prec))
+        geo = list(ptk.pt_ctx_last_geometry(ctx.handle))
         ach = ALG_FLOP * pairs_b / dt / 1e12
         batch[name] = {"value": pairs_b / dt, "unit": "candidate*sample/s", "seconds": dt,
                        "block_fits_per_s": len(blocks) / dt,

@@ -519,6 +519,11 @@ enum { PT_ARITH_FP64_POLY = 0, PT_ARITH_MIXED = 1, PT_ARITH_FP64_PHASOR = 2 };
 
 int pt_ctx_last_arithmetic(pt_ctx* ctx, int* arith);
 
+/* Chunk geometry (samples per lane, candidates per workgroup) of the
+ * context's most recent fit or objective evaluation; 0, 0 before the first.
+ * PT_EINVAL on null arguments. */
+int pt_ctx_last_geometry(pt_ctx* ctx, int* samples_per_lane, int* cand_per_group);
+
 /* Objective-kernel launches of the context's most recent fit (all blocks of
  * a batch share them): one per generation including generation 0, plus one
  * for the last DE step in the leading-step form; 1 for a persistent launch.
@@ -547,7 +552,10 @@ int pt_time_objective(pt_ctx* ctx, const pt_block* block, const double* pop, int
 
 /* Chunk geometry of the objective kernel used for blocks of n samples and
  * population P in the given precision: samples per lane and candidates per
- * workgroup (the autotuner's choice once it has run). */
+ * workgroup (the autotuner's choice once it has run).  It applies to single
+ * blocks and to batches up to four work units per compute unit; a larger
+ * batch (throughput-bound) uses the geometry with the most candidate·samples
+ * per lane instead (32 x 8 for P = 40), unless pt_ctx_set_tile forces one. */
 int pt_ctx_get_tile(pt_ctx* ctx, int64_t n, int P, int precision, int* samples_per_lane,
                     int* cand_per_group);
 

@@ -257,6 +257,7 @@ struct pt_ctx {
     int fp64_method = PT_FP64_AUTO;
     int last_launch = PT_LAUNCH_GRAPH;
     int last_arith = PT_ARITH_FP64_POLY;
+    Geometry last_geo{0, 0};  // geometry of the most recent fit or objective evaluation
     int64_t last_fit_launches = 0;
     int step_fusion = PT_FUSION_AUTO;
     uint64_t spin_ticks = 0;
@@ -320,6 +321,24 @@ Geometry default_geometry(int64_t n, int P) {
             const double waste = (double)(groups * c - P) / (groups * c);
             double score = (double)s * c * (1.0 - waste);
             if (units < 1024) score *= (double)units / 1024.0;
+            if (score > best_score) {
+                best_score = score;
+                best = {s, c};
+            }
+        }
+    }
+    return best;
+}
+
+// The geometry with the most candidate·samples per lane (the fewest
+// per-candidate set-up operations per sample), for throughput-bound launches.
+Geometry throughput_geometry(int P) {
+    Geometry best{4, 1};
+    double best_score = -1;
+    for (int s : kSpl) {
+        for (int c : kCpg) {
+            const int64_t groups = (P + c - 1) / c;
+            const double score = (double)s * c * (double)P / (double)(groups * c);
             if (score > best_score) {
                 best_score = score;
                 best = {s, c};
@@ -581,8 +600,20 @@ int prepare(pt_ctx* ctx, const pt_block* blocks, int nblk, const pt_de_settings*
         nmax = std::max(nmax, blocks[b].n);
     }
     pl->slope = slope;
-    // geometry from the largest block (one kernel instance per launch)
+    // geometry from the largest block (one kernel instance per launch).  A
+    // batch with more than four work units per compute unit at that geometry
+    // is throughput-bound: there the geometry with the most work per lane
+    // wins, whatever a single-block tuning chose (64 uneven blocks, P = 40,
+    // FP64: 32 x 8 0.226 s, 32 x 4 0.263 s, 16 x 8 0.269 s, 16 x 4 0.308 s;
+    // mixed: 0.257, 0.276, 0.285, 0.316 s)
     pl->geo = choose_geometry(ctx, nmax, P, pl->mixed);
+    if (nblk > 1 && !ctx->forced.spl) {
+        int64_t units = 0;
+        for (int b = 0; b < nblk; ++b)
+            units += (blocks[b].n + (int64_t)kThreads * pl->geo.spl - 1) / ((int64_t)kThreads * pl->geo.spl) *
+                     ((P + pl->geo.cpg - 1) / pl->geo.cpg);
+        if (units > 4LL * ctx->ncu) pl->geo = throughput_geometry(P);
+    }
     pl->mode = pl->mixed ? kModeMixed : kModePoly;
     std::vector<char> phasor(nblk, 0);
     int nphasor = 0;
@@ -807,6 +838,7 @@ int run_fit(pt_ctx* ctx, const pt_block* blocks, int nblk, const pt_de_settings*
     // (a batch split by arithmetic reports the phasor path, whose per-sample
     // error is the larger)
     ctx->last_arith = persistent || pl.launches.size() == 1 ? pl.mode : kModePhasor;
+    ctx->last_geo = pl.geo;
     ctx->last_fit_launches = persistent ? 1 : iters;
     if (persistent) {
         // nothing else to enqueue
@@ -1068,6 +1100,7 @@ static int eval_setup(pt_ctx* ctx, const pt_block* block, const double* pop, int
     pl->mode = ext.mode(*pl, ctx, block);
     *obj = objective_kernel(pl->dtype, pl->geo, pl->mode, pl->slope);
     ctx->last_arith = pl->mode;
+    ctx->last_geo = pl->geo;
     return PT_OK;
 }
 
@@ -1168,6 +1201,7 @@ int pt_objective_noalloc(pt_ctx* ctx, const pt_block* block, const double* pop, 
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(s));
     ctx->last_arith = pl.mode;
+    ctx->last_geo = pl.geo;
     return PT_OK;
 }
 
@@ -1478,6 +1512,13 @@ int pt_ctx_last_fit_launches(pt_ctx* ctx, int64_t* launches) {
 int pt_ctx_last_arithmetic(pt_ctx* ctx, int* arith) {
     if (!ctx || !arith) return fail(PT_EINVAL, "ctx / arith is null");
     *arith = ctx->last_arith;
+    return PT_OK;
+}
+
+int pt_ctx_last_geometry(pt_ctx* ctx, int* spl, int* cpg) {
+    if (!ctx || !spl || !cpg) return fail(PT_EINVAL, "ctx / spl / cpg is null");
+    *spl = ctx->last_geo.spl;
+    *cpg = ctx->last_geo.cpg;
     return PT_OK;
 }
 

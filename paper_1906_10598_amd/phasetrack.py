@@ -201,6 +201,7 @@ def _signatures(L):
         "pt_ctx_set_fp64_method": ([_CTX, i32], i32),
         "pt_ctx_last_launch": ([_CTX, ctypes.POINTER(i32)], i32),
         "pt_ctx_last_arithmetic": ([_CTX, ctypes.POINTER(i32)], i32),
+        "pt_ctx_last_geometry": ([_CTX, ctypes.POINTER(i32), ctypes.POINTER(i32)], i32),
         "pt_ctx_set_step_fusion": ([_CTX, i32], i32),
         "pt_ctx_set_timing": ([_CTX, i32], i32),
         "pt_ctx_kernel_stats": ([_CTX, ctypes.POINTER(i64), _DP], i32),
@@ -447,6 +448,14 @@ def pt_ctx_last_arithmetic(ctx) -> int:
     m = ctypes.c_int32()
     _check(lib().pt_ctx_last_arithmetic(ctx, ctypes.byref(m)), "pt_ctx_last_arithmetic")
     return m.value
+
+
+def pt_ctx_last_geometry(ctx):
+    """(samples per lane, candidates per workgroup) of the most recent fit or
+    objective evaluation."""
+    spl, cpg = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().pt_ctx_last_geometry(ctx, ctypes.byref(spl), ctypes.byref(cpg)), "pt_ctx_last_geometry")
+    return spl.value, cpg.value
 
 
 def pt_ctx_set_timing(ctx, on: bool):

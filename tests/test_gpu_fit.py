@@ -290,8 +290,10 @@ def test_full_64_block_batch_as_benchmarked(precision):
     # The batched workload at full size -- 64 blocks, N log-uniform in
     # [5e4, 4e5] at 50 kHz, SNR in [-5, 10] dB, own populations of 40, 1500
     # generations -- launched as the benchmark launches it: automatic launch
-    # form, and the geometry the benchmark's autotuner picks on MI355X (32 x 8
-    # FP64, 16 x 8 mixed).  Sampled outputs against the oracle one by one:
+    # form and automatic geometry, which for a batch of more than four work
+    # units per compute unit is the one with the most work per lane (32 x 8
+    # for P = 40, in both precisions).  Sampled outputs against the oracle one
+    # by one:
     # the reported objective is the oracle's chi^2 at the reported
     # coefficients (FP64 1e-10; mixed, at its optimum, mixed_rel_at_optimum,
     # which grows with the block's SNR and shrinks with its length), and
@@ -304,10 +306,11 @@ def test_full_64_block_batch_as_benchmarked(precision):
     seed = synth.config1(0).de.seed  # the benchmark's seed
     de = ptk.make_settings(pop=40, max_gens=blocks[0].de.max_gens, F=0.5, CR=0.9, seed=seed, precision=precision)
     c = ctx()
-    geo = (32, 8) if precision == ptk.PT_PREC_FP64 else (16, 8)
-    ptk.pt_ctx_set_tile(c.handle, *geo)
+    fits = c.fit_batch(pbs, de)
+    geo = ptk.pt_ctx_last_geometry(c.handle)
+    assert geo == (32, 8)
+    ptk.pt_ctx_set_tile(c.handle, *geo)  # the fits alone in the batch's geometry
     try:
-        fits = c.fit_batch(pbs, de)
         sizes = [b.n for b in blocks]
         sample = sorted({0, int(np.argmax(sizes)), int(np.argmin(sizes)), 48})
         alone = {k: c.fit_block(pbs[k], de) for k in sample}
