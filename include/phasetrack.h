@@ -564,13 +564,15 @@ int pt_ctx_get_tile(pt_ctx* ctx, int64_t n, int P, int precision, int* samples_p
  * cand_per_group: 1, 2, 4, 8. */
 int pt_ctx_set_tile(pt_ctx* ctx, int samples_per_lane, int cand_per_group);
 
-/* Time every supported geometry on a block of n samples and population P
- * (synthetic data on the device, a box of the paper's widths around one
- * carrier at the largest drift rate and drift acceleration of the
- * paper-scale synthetic blocks, 5 Hz/s and 0.05 Hz/s^2, so that each geometry is timed with the FP64
- * arithmetic it would use at the edge of such a box): short fits of 100 generations in the context's current launch
- * form and step fusion.  Remembers the fastest for that size class and
- * precision; replaces the context's last-fit record (pt_last_population).
+/* Time every supported geometry on a block of n samples and population P:
+ * short fits of 100 generations in the context's current launch form and
+ * step fusion, on synthetic data on the device in a box of the paper's
+ * widths around one carrier at the largest drift rate and drift
+ * acceleration of the paper-scale synthetic blocks (5 Hz/s, 0.05 Hz/s^2),
+ * so that each geometry is timed with the FP64 arithmetic it would use at
+ * the edge of such a box.  Remembers the fastest for that size class
+ * (floor(log2 n)) and precision, for single blocks and small batches;
+ * replaces the context's last-fit record (pt_last_population).
  * best_spl / best_cpg may be NULL. */
 int pt_ctx_autotune(pt_ctx* ctx, int64_t n, int P, int precision, void* hip_stream,
                     int* best_spl, int* best_cpg);
