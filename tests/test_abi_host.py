@@ -138,14 +138,21 @@ def _coeffs(name):
 def test_device_cosine_polynomials():
     mpmath.mp.dps = 40
     c64 = _coeffs("kCos64")
+    s64 = _coeffs("kSin64")
     c32 = _coeffs("kCos32")
+    # the phasor path's sine/cosine evaluates both polynomials in one loop
+    assert len(s64) == len(c64)
     rs = np.concatenate([np.linspace(-0.5, 0.5, 2001), [0.25, -0.25, 0.125, 0.5 - 1e-12]])
-    err64 = err32 = 0.0
+    err64 = err32 = errs64 = 0.0
     for r in rs:
         u = r * r
         p = c64[0]
         for c in c64[1:]:
             p = p * u + c
+        q = s64[0]
+        for c in s64[1:]:
+            q = q * u + c
+        errs64 = max(errs64, abs(r * q - float(mpmath.sin(2 * mpmath.pi * mpmath.mpf(r)))))
         f32 = lambda x: struct.unpack("f", struct.pack("f", x))[0]  # noqa: E731
         uf = f32(f32(r) * f32(r))
         q = f32(c32[0])
@@ -155,6 +162,7 @@ def test_device_cosine_polynomials():
         err64 = max(err64, abs(p - exact))
         err32 = max(err32, abs(q - exact))
     assert err64 < 2e-15  # unfused Horner here; the device fuses each step
+    assert errs64 < 2e-15
     assert err32 < 4e-7
 
 
