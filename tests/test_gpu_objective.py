@@ -12,8 +12,8 @@ import pytest
 
 import oracle
 import synth
-from gpu_util import (MIXED_NOISE_FREE, assert_chi2_close, block_of, ctx, mixed_rel_at_optimum, model_phase_err,
-                      phase_rounding_bound, random_population, to_dev)
+from gpu_util import (MIXED_NOISE_FREE, MODEL_PHASE_ERR, assert_chi2_close, block_of, ctx, mixed_rel_at_optimum,
+                      model_phase_err, phase_rounding_bound, random_population, to_dev)
 from paper_1906_10598_amd import phasetrack as ptk
 
 pytestmark = pytest.mark.gpu
@@ -191,6 +191,39 @@ def test_large_frequency_acceleration_falls_back_to_per_sample_path():
     pop = random_population(rng, lo, hi, 16)
     pop[0] = x
     _check(b, pop)
+
+
+@pytest.mark.parametrize("inside", [True, False])
+def test_phasor_bound_at_a_carrier_near_zero(inside):
+    # Condition (3) of the phasor arithmetic: over the whole box the carrier
+    # keeps |sin 2 pi c1| >= S 2.2e-4, i.e. f >= 28.0 Hz at 50 kHz with 16
+    # samples per lane (the span the host checks runs to N + |ref| samples, so
+    # f1 in +-0.1 Hz/s moves f by up to 0.6 Hz).  A box at f0 in [29, 31] Hz
+    # stays just inside: the phasor path runs, and on noise-free samples at
+    # the truth its per-sample model error stays within the stated
+    # 2 pi 1e-12 + 1e-11 + 1e-12 (the recurrence's rounding grows as
+    # j ulp / |sin 2 pi c1|, largest here).  A box at [26, 28] Hz reaches
+    # past it: the per-sample path runs, within 1e-12.
+    n, fs = 200_000, 50_000.0
+    ref = n / 2
+    f0 = 30.0 if inside else 27.0
+    x = np.array([0.7, 1.3, f0, 0.05, 0.0, 0.0])
+    t = (np.arange(n) - ref) / fs
+    s = x[0] * np.cos(x[1] + 2 * np.pi * (x[2] * t + x[3] * t * t / 2))
+    half = np.array([0.1, 3.0, 1.0, 0.05, 0.0, 0.0])
+    b = synth.Block(s, fs, ref, x, x - half, x + half, synth.DESettings(8, 1), 0.0, name="carrier near 0")
+    c = ctx()
+    ptk.pt_ctx_set_tile(c.handle, 16, 8)
+    try:
+        got = _eval(block_of(b, to_dev(s)), np.vstack([x]))
+        arith = ptk.pt_ctx_last_arithmetic(c.handle)
+    finally:
+        ptk.pt_ctx_set_tile(c.handle, 0, 0)
+    assert arith == (ptk.PT_ARITH_FP64_PHASOR if inside else ptk.PT_ARITH_FP64_POLY)
+    floor = MODEL_PHASE_ERR[arith]
+    print(f"[carrier {f0} Hz, arithmetic {arith}] chi2 at truth {got[0]:.3e}, bound {n * (floor * x[0]) ** 2:.3e}",
+          flush=True)
+    assert got[0] <= n * (floor * x[0]) ** 2
 
 
 def test_mixed_precision_error_stated():
