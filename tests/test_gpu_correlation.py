@@ -10,7 +10,9 @@ the path (FP64: 2e-14 plus the arithmetic's per-sample phase error, 2 pi 1e-12
 for the phasor recurrence; mixed: 5e-6, from its FP32 phase offset, FP32
 cosine and FP32 lane sums).
 """
+import json
 import math
+import os
 
 import numpy as np
 import pytest
@@ -22,6 +24,7 @@ from gpu_util import (MODEL_PHASE_ERR, block_of, ctx, model_phase_err, phase_rou
 from paper_1906_10598_amd import phasetrack as ptk
 
 pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 # cosine and summation error of each path [relative to sum |s| A]; the FP64
 # path adds its arithmetic's per-sample phase error (model_phase_err)
@@ -165,3 +168,35 @@ def test_invalid_objective_kind():
         ctx().objective(blk, to_dev(np.tile(b.truth, (4, 1))), objective=7)
     with pytest.raises(ptk.PtError):
         ctx().fit_block(blk, settings_of(b, gens=5, objective=7))
+
+
+def _correlation_of(F):
+    """C from F = 1 / (arctan C + pi/2): C = -1 / tan(1 / F), to ~4e-11 relative
+    for the C ~ 1e5 of a paper-scale block (1 / F = pi - ~1 / C)."""
+    return -1.0 / math.tan(1.0 / F)
+
+
+def test_paper_block_whole_correlation_fit_matches_oracle_fit():
+    # The whole paper-scale fit under the correlation objective (Eq. 2-2-5,
+    # amplitude fixed at the truth as Eq. 2-2-6 asks; 400 000 samples, P = 40,
+    # 2000 generations) against the oracle's whole fit of the same block,
+    # stored by tests/golden/make_paper_fit.py --kind cor (oracle only).  The
+    # trajectories part at the first selection near-tie; both reach the same
+    # optimum: f0 within 1e-6 Hz, the correlation C within 1e-9 relative.
+    # (F sits at 1/pi + 1/(pi^2 C) with C ~ 1.2e4 here, so an f0 offset d moves
+    # F by ~(2 pi T d)^2 / (24 pi^2 C): a few ulp of F at d = 4e-7 Hz, the
+    # objective's own resolution; the two fits are measured 4.3e-7 Hz apart.)
+    g = json.load(open(os.path.join(GOLD, "paper_fit_cor_seed0.json")))
+    b = synth.config1(0)
+    lo, hi = _fixed_amplitude(b)
+    assert g["n"] == b.n and g["de"]["seed"] == b.de.seed and g["kind"] == "cor"
+    assert np.array_equal(np.array(g["box"]["lo"]), lo) and np.array_equal(np.array(g["box"]["hi"]), hi)
+    f = ctx().fit_block(block_of(b, to_dev(b.samples), lo=lo, hi=hi), settings_of(b, objective=ptk.PT_OBJ_COR))
+    ox, oF = np.array(g["oracle_fit"]["x"]), g["oracle_fit"]["objective"]
+    cg, co = _correlation_of(f.objective), _correlation_of(oF)
+    print(f"[paper whole correlation fit] gpu f0 - oracle f0 {f.coef[2] - ox[2]:+.3e} Hz, C rel diff "
+          f"{(cg - co) / co:+.3e}", flush=True)
+    assert f.generations == g["oracle_fit"]["generations"] == 2000
+    assert f.flags == g["oracle_fit"]["flags"]
+    assert abs(f.coef[2] - ox[2]) < 1e-6
+    assert abs(cg - co) <= 1e-9 * co

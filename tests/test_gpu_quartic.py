@@ -10,6 +10,9 @@ Slot 6 is f3 [Hz/s^3]: phase term 2 pi f3 t^4 / 24.  Covered:
   * on a 20 s perigee-like block the quartic fit reaches the noise floor and
     recovers f3, while the cubic fit (f3 fixed at 0) leaves a large residual.
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -20,6 +23,7 @@ from gpu_util import (assert_chi2_close, block_of, crlb_f0, ctx, model_phase_err
 from paper_1906_10598_amd import phasetrack as ptk
 
 pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 MIXED_REL = 3e-7  # see the derivation beside the same bound in test_gpu_objective.py
 
@@ -104,3 +108,25 @@ def test_quartic_fit_beats_cubic_on_a_perigee_arc():
     _, _, fr, _ = ptk.pt_phase(q, t)
     c5 = oracle.derived.coefs_from_fit(q.coef[1], q.coef[2], q.coef[3], q.coef[4], q.coef[6])
     assert abs(fr[0] - float(oracle.derived.freq_hz(c5, t)[0])) < 1e-9
+
+
+def test_quartic_whole_fit_matches_oracle_fit():
+    # The whole fit of the 20 s quartic-phase block (1e6 samples, f3 free,
+    # P = 40, 2000 generations) against the oracle's whole fit and the exact
+    # least-squares minimiser, stored by tests/golden/make_paper_fit.py
+    # --kind quartic (oracle only): f0 within 1e-6 Hz, chi^2 within 1e-10
+    # relative of both, f1, f2 and f3 at the same optimum.
+    g = json.load(open(os.path.join(GOLD, "quartic_fit_seed0.json")))
+    b = synth.config_quartic(0)
+    assert g["n"] == b.n and g["de"]["seed"] == b.de.seed and g["kind"] == "quartic"
+    f = ctx().fit_block(block_of(b, to_dev(b.samples)), settings_of(b))
+    ox, oobj = np.array(g["oracle_fit"]["x"]), g["oracle_fit"]["objective"]
+    mx, mobj = np.array(g["minimiser"]["x"]), g["minimiser"]["objective"]
+    print(f"[quartic whole fit] gpu f0 - oracle {f.coef[2] - ox[2]:+.3e} Hz, - minimiser {f.coef[2] - mx[2]:+.3e} Hz, "
+          f"chi2 rel diff {(f.objective - oobj) / oobj:+.3e}, f3 {f.coef[6]:.6e} vs {ox[6]:.6e}", flush=True)
+    assert f.generations == g["oracle_fit"]["generations"] == 2000
+    assert f.flags == g["oracle_fit"]["flags"]
+    assert abs(f.coef[2] - ox[2]) < 1e-6 and abs(f.coef[2] - mx[2]) < 1e-6
+    assert abs(f.objective - oobj) <= 1e-10 * oobj and abs(f.objective - mobj) <= 1e-10 * mobj
+    for j, name in ((3, "f1"), (4, "f2"), (6, "f3")):
+        assert abs(f.coef[j] - ox[j]) < 1e-4 * (b.hi[j] - b.lo[j]), name
