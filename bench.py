@@ -28,15 +28,16 @@ PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector (published, counts packed FP32)
 # 75 TFLOP/s for either with dependent-free FMA streams); this build does not
 # form packed FP32 instructions, so the FP32 path's reachable peak is 78.6.
 PEAK_FP32_UNPACKED_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
 VALU_ISSUE_SLOTS_PER_S = 1024 * 2.4e9 / 4.0  # wave64 VALU instructions: 1024 SIMDs, one per 4 cycles
 # Algorithmic work per candidate*sample: the survey's figure for one direct
 # evaluation of Eq. (2-2-2)/(2-2-4) -- the cubic phase (3 FMA), one cosine
 # (12-16 FMA after the turn reduction), the residual FMA and the
 # square-accumulate FMA -- about 40 FP64 FLOP.  Every arithmetic computes
-# that objective and is credited the same work (the phasor path does it with
-# ~7 executed operations per candidate*sample, so its algorithmic rate is an
-# equivalent rate and can exceed the hardware peak); `executed` gives the
-# counter-measured FP64 operations of the same launches.
+# that objective and is credited the same work (the phasor path executes 12
+# to 15 FP64 operations per candidate*sample, an FMA counted as two, so its
+# algorithmic rate is an equivalent rate and can exceed the hardware peak);
+# `executed` gives the counter-measured FP64 operations of the same launches.
 ALG_FLOP = 40
 ARITH_NAME = {0: "fp64-per-sample", 1: "mixed", 2: "fp64-phasor"}
 
@@ -63,6 +64,10 @@ def executed_roofline(prof, launch_ms, peak=PEAK_FP64_TFLOPS):
                      "committed summary of the same kernel, divided by the launch time measured here"}
     if "valu" in prof:
         out["valu_issue"] = prof["valu"] / (VALU_ISSUE_SLOTS_PER_S * t)
+    if prof.get("bytes_per_launch"):
+        # achieved HBM rate: the counter traffic of the same summary over the launch time
+        out["hbm_gb_s"] = prof["bytes_per_launch"] / t / 1e9
+        out["hbm_frac"] = out["hbm_gb_s"] / PEAK_HBM_GBS
     return out
 
 
