@@ -54,6 +54,8 @@ def test_version_and_null_arguments():
     assert L.pt_phase(None, None, 0, None, None, None, None) == ptk.PT_EINVAL
     assert L.pt_connect_phase(None, 0, None, None) == ptk.PT_EINVAL
     assert L.pt_ctx_set_tile(None, 16, 4) == ptk.PT_EINVAL
+    spl, cpg = ctypes.c_int32(), ctypes.c_int32()
+    assert L.pt_ctx_last_geometry(None, ctypes.byref(spl), ctypes.byref(cpg)) == ptk.PT_EINVAL
     L.pt_ctx_destroy(None)  # ignored
 
 
