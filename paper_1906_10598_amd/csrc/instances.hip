@@ -20,13 +20,14 @@ using T = PT_INST_T;
 constexpr int S = PT_INST_S;
 
 template <int C, int M>
-ObjKernel pick_slope(bool slope, bool lead) {
-    if (lead) return slope ? k_objective<T, S, C, M, true, true> : k_objective<T, S, C, M, false, true>;
-    return slope ? k_objective<T, S, C, M, true, false> : k_objective<T, S, C, M, false, false>;
+ObjKernel pick_slope(bool slope, int lead) {
+    if (lead == 2) return slope ? k_objective<T, S, C, M, true, 2> : k_objective<T, S, C, M, false, 2>;
+    if (lead == 1) return slope ? k_objective<T, S, C, M, true, 1> : k_objective<T, S, C, M, false, 1>;
+    return slope ? k_objective<T, S, C, M, true, 0> : k_objective<T, S, C, M, false, 0>;
 }
 
 template <int C>
-ObjKernel pick_mode(int mode, bool slope, bool lead) {
+ObjKernel pick_mode(int mode, bool slope, int lead) {
     if (mode == kModeMixed) return pick_slope<C, kModeMixed>(slope, lead);
     if (mode == kModePhasor) return pick_slope<C, kModePhasor>(slope, lead);
     return pick_slope<C, kModePoly>(slope, lead);
@@ -46,7 +47,7 @@ PersistKernel ppick_mode(int mode, bool slope) {
 
 }  // namespace
 
-ObjKernel PT_NAME(objective_kernel_)(int cpg, int mode, bool slope, bool lead) {
+ObjKernel PT_NAME(objective_kernel_)(int cpg, int mode, bool slope, int lead) {
     switch (cpg) {
         case 1: return pick_mode<1>(mode, slope, lead);
         case 2: return pick_mode<2>(mode, slope, lead);

@@ -867,6 +867,19 @@ __device__ __forceinline__ Draws trial_draws_octet(const BlockDesc* __restrict__
     return draws_from(w, u0, u1, i, d->P, d->D, d->CR);
 }
 
+// Draws of one member packed into the pad slot (slot 7) of its trial row
+// (P <= 256, at most 7 active coordinates): r1, r2, r3 in bytes 0-2, the
+// crossover mask in byte 3, as the bits of a double (only stored and loaded).
+__device__ __forceinline__ double pack_draws(const Draws& w) {
+    const unsigned long long u = (unsigned long long)((unsigned)w.r1 | ((unsigned)w.r2 << 8) |
+                                                      ((unsigned)w.r3 << 16) | (w.cross << 24));
+    return __longlong_as_double((long long)u);
+}
+__device__ __forceinline__ Draws unpack_draws(double x) {
+    const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+    return Draws{(int)(u & 255u), (int)((u >> 8) & 255u), (int)((u >> 16) & 255u), (unsigned)((u >> 24) & 255u)};
+}
+
 // Trial vector y of member i from the selected population xs (P x kSlots,
 // LDS) and its draws: v = x_r1 + F (x_r2 - x_r3) with the half-way bound
 // rule on the crossed coordinates, x_i elsewhere.
@@ -1037,6 +1050,26 @@ __global__ __launch_bounds__(1024) void k_de_step(const BlockDesc* __restrict__ 
 #endif
 
 // ---------------------------------------------------------------------------
+// Inputs of a leading step: the slot it reads (tile partials, population
+// rows, trial rows and population objectives of slot p ^ 1) and P and
+// ntiles.  A one-block launch passes them as kernel arguments, which arrive
+// in scalar registers at wave launch, so the step's loads do not wait for the
+// descriptor; otherwise lead_in_of reads them from the descriptor.
+struct LeadIn {
+    const double* part;
+    const double* rows;
+    const double* trial;
+    const double* fpop;
+    int P, T;
+};
+
+__device__ __forceinline__ LeadIn lead_in_of(const BlockDesc* __restrict__ d, int L) {
+    const int p = L & 1;
+    const double *pop0 = d->pop, *pop1 = d->pop2, *tr0 = d->trial, *tr1 = d->trial2;
+    const double *fp0 = d->fpop, *fp1 = d->fpop2, *pa0 = d->partials, *pa1 = d->partials2;
+    return LeadIn{p ? pa0 : pa1, p ? pop0 : pop1, p ? tr0 : tr1, p ? fp0 : fp1, d->P, d->ntiles};
+}
+
 // Leading DE step (fits with P <= 256, blockDim = 256).  Launch L of a fit
 // (L a kernel argument) evaluates the trial population of generation L.
 // Before that, every objective workgroup of the launch repeats the DE step
@@ -1066,12 +1099,12 @@ __global__ __launch_bounds__(1024) void k_de_step(const BlockDesc* __restrict__ 
 // a compile-time count keeps the launch's geometry out of the chain of
 // dependent loads before the step's data loads.
 // ---------------------------------------------------------------------------
-template <int CPG, bool BOOK, typename RT, int RS>
+template <int CPG, bool BOOK, bool PRE, typename RT, int RS>
 __device__ __forceinline__ bool de_lead(const BlockDesc* __restrict__ d, int L, int tile, int group, Cand* cs,
-                                        double* lds, const RT (&raw)[RS]) {
+                                        double* lds, const LeadIn& in, RT (&raw)[RS]) {
     const int p = L & 1;
     constexpr int NT = kThreads;
-    const int P = d->P, i = threadIdx.x;
+    const int P = in.P, i = threadIdx.x;
     double* xs = lds;                              // P x kSlots: trial rows, then the selected rows
     double* red = xs + (size_t)P * kSlots;         // NT
     double* fr = red + NT;                         // NT
@@ -1079,21 +1112,14 @@ __device__ __forceinline__ bool de_lead(const BlockDesc* __restrict__ d, int L, 
     double* xp = reinterpret_cast<double*>(ix + NT);  // P x kSlots: population rows
     __shared__ int s_done, s_stop;
     __shared__ double s_old;
-    // both slots' pointers are read unconditionally and then selected: read
-    // through a parity-selected field address they would cost one more
-    // dependent scalar round trip before any data load
-    DeState *st0 = d->st, *st1 = d->st2;
-    double *pop0 = d->pop, *pop1 = d->pop2, *tr0 = d->trial, *tr1 = d->trial2;
-    double *fp0 = d->fpop, *fp1 = d->fpop2, *pa0 = d->partials, *pa1 = d->partials2;
-    const DeState* st_in = p ? st1 : st0;
-    DeState* st_out = p ? st0 : st1;
-    const double* rows_in = p ? pop0 : pop1;  // slot p ^ 1
-    const double* trial_in = p ? tr0 : tr1;
-    const double* fpop_in = p ? fp0 : fp1;
-    const double* part_in = p ? pa0 : pa1;
-    double* rows_out = p ? pop1 : pop0;       // slot p
-    double* trial_out = p ? tr1 : tr0;
-    double* fpop_out = p ? fp1 : fp0;
+    // the slot the step reads (in); the state and the outputs from the
+    // descriptor, both slots' pointers read unconditionally and then selected
+    // (through a parity-selected field address they would cost one more
+    // dependent scalar round trip)
+    const double* rows_in = in.rows;  // slot p ^ 1
+    const double* trial_in = in.trial;
+    const double* fpop_in = in.fpop;
+    const double* part_in = in.part;
     const int cbase = group * CPG;
     const int ncand = min(CPG, P - cbase);
 
@@ -1104,7 +1130,7 @@ __device__ __forceinline__ bool de_lead(const BlockDesc* __restrict__ d, int L, 
     // samples at 16 per lane) in one memory round trip; 24 would cost the
     // kernel its fourth wave per SIMD (143 VGPRs instead of 115)
     constexpr int kB = 17;
-    const int T = d->ntiles;
+    const int T = in.T;
     const int k = NT >= P ? NT / P : 1;
     const int pm = i / k, part = i - pm * k;
     const int cnt = (i < P * k && part < T) ? (T - part + k - 1) / k : 0;
@@ -1130,13 +1156,31 @@ __device__ __forceinline__ bool de_lead(const BlockDesc* __restrict__ d, int L, 
         rp[r] = gld(rows_in + off);
     }
     const double fo = gld(fpop_in + min(i, P - 1));
+    // PRE: this lane's trial draws, made by the previous launch's bookkeeping
+    // workgroup and kept in the pad slot of the trial rows this step reads
+    const int c = (i & 63) >> 3, j = i & 7;
+    double dpk = 0.0;
+    if constexpr (PRE) dpk = gld(trial_in + (size_t)min(cbase + c, P - 1) * kStride + kSlots);
+    // what comes from the descriptor, behind the step's loads: the lane's
+    // samples (needed only by the objective after the step), the state and
+    // the slots the step writes
+    if constexpr (!BOOK) load_lane_raw<RT, RS>(d, tile, raw);
+    DeState *st0 = d->st, *st1 = d->st2;
+    double *pop0 = d->pop, *pop1 = d->pop2, *tr0 = d->trial, *tr1 = d->trial2;
+    double *fp0 = d->fpop, *fp1 = d->fpop2;
+    const DeState* st_in = p ? st1 : st0;
+    DeState* st_out = p ? st0 : st1;
+    double* rows_out = p ? pop1 : pop0;  // slot p
+    double* trial_out = p ? tr1 : tr0;
+    double* fpop_out = p ? fp1 : fp0;
     const int st_done = gld(&st_in->done);
     const double st_old = gld(&st_in->old);
 
     // 2. while they are in flight: the random draws of this thread's trial
-    //    coordinate (candidate c = i / 8 of the group, slot j = i % 8)
-    const int c = i >> 3, j = i & 7;
-    const bool tw = !BOOK && L > 0 && c < ncand;
+    //    coordinate (candidate c = i / 8 of the group, slot j = i % 8); the
+    //    bookkeeping workgroup makes every member's draws of the next launch
+    //    and stores them in the pad slot of the trial rows it reads (PRE)
+    const bool tw = !BOOK && L > 0 && c < ncand && i < 64;
     // this thread's coordinate: its bounds (a per-lane index into the
     // descriptor, so vector loads) and its place among the active slots, read
     // with the step's other data rather than after the selection
@@ -1146,9 +1190,13 @@ __device__ __forceinline__ bool de_lead(const BlockDesc* __restrict__ d, int L, 
     const int a_j = ((am >> j) & 1u) ? __builtin_popcount(am & ((1u << j) - 1u)) : -1;
     const double Fm = d->F, fs = d->fs;
     Draws dr{0, 0, 0, 0u};
-    // (every lane of the wave makes the octet draws, so that the octets'
-    // exchanges see all their lanes; only those with tw use them)
-    if (!BOOK && L > 0 && i < 64) dr = trial_draws_octet(d, cbase + c, (uint32_t)L);
+    if constexpr (BOOK) {
+        if (i < P) gst(trial_out + (size_t)i * kStride + kSlots, pack_draws(trial_draws(d, i, (uint32_t)(L + 1))));
+    } else if constexpr (!PRE) {
+        // (every lane of the wave makes the octet draws, so that the octets'
+        // exchanges see all their lanes; only those with tw use them)
+        if (L > 0 && i < 64) dr = trial_draws_octet(d, cbase + c, (uint32_t)L);
+    }
 
     // 3. objectives of all P trials, in reduce_partials' order
     double sp = 0.0;
@@ -1229,6 +1277,7 @@ __device__ __forceinline__ bool de_lead(const BlockDesc* __restrict__ d, int L, 
     }
     if constexpr (!BOOK) {
         __syncthreads();  // selected rows complete
+        if constexpr (PRE) dr = unpack_draws(dpk);
         // 5. the group's trials, one coordinate per thread (apply_trial's
         //    arithmetic), straight into the candidates' turn-domain form
         if (tw) {
@@ -1245,7 +1294,9 @@ __device__ __forceinline__ bool de_lead(const BlockDesc* __restrict__ d, int L, 
                 }
                 cand_member(cs[c], j) = cand_value(j, y, fs);
             }
-            if (tile == 0) gst(trial_out + (size_t)m * kStride + j, y);
+            // (the pad slot carries the next launch's draws, stored by the
+            // bookkeeping workgroup)
+            if (tile == 0 && j < kSlots) gst(trial_out + (size_t)m * kStride + j, y);
         }
         __syncthreads();
         return true;
@@ -1370,13 +1421,18 @@ __device__ __forceinline__ int units_in_range(const BlockDesc* d, int x, int Ux,
 //
 // Dynamic LDS for fused != 0: the DE step's (P * kSlots + 2 * 256 doubles +
 // 256 ints), and P * kSlots doubles more for fused >= 2.
-// LEAD: the instance for the leading-step form (fused >= 2 only); the other
-// forms use the instance without it, which needs fewer registers (four waves
-// per SIMD instead of three).
-template <typename T, int S, int CPG, int MODE, bool SLOPE, bool LEAD>
+// LEAD: the instance for the leading-step form (fused >= 2 only), 1 reading
+// the step's inputs from the descriptor, 2 from the kernel arguments (one
+// block); the other forms use the instance without it (LEAD = 0), which
+// needs fewer registers.
+template <typename T, int S, int CPG, int MODE, bool SLOPE, int LEAD>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_objective(
-    const BlockDesc* __restrict__ descs, int nblk, int total_units, int fused) {
-    const int nwg = gridDim.x;  // multiple of 8
+    int fused, int nblk, int total_units, int lp, const double* __restrict__ l_part, const double* __restrict__ l_rows,
+    const double* __restrict__ l_trial, const double* __restrict__ l_fpop, const BlockDesc* __restrict__ descs) {
+    // workgroups (a multiple of 8); the one-block leading form launches the
+    // units plus one, rounded up to 8, and derives it from its arguments (the
+    // grid size is otherwise one more kernel-argument load before the step)
+    const int nwg = LEAD == 2 ? (total_units + 1 + 7) & ~7 : (int)gridDim.x;
     const int bid = blockIdx.x;
     const int Ux = nwg >> 3;
     const int unit = (bid & 7) * Ux + (bid >> 3);
@@ -1387,29 +1443,47 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 4))
         // leading-step form: unit total_units + b keeps block b's DE state
         if constexpr (LEAD) {
             if (unit < total_units + nblk) {
-                const float none[1] = {0.0f};
+                float none[1] = {0.0f};
                 const BlockDesc* db = descs + (unit - total_units);
-                de_lead<CPG, true>(db, db->gen_begin + fused - 2, 0, 0, cs, de_lds, none);
+                const int Lb = db->gen_begin + fused - 2;
+                de_lead<CPG, true, false>(db, Lb, 0, 0, cs, de_lds, lead_in_of(db, Lb), none);
             }
         }
         return;
     }
-    const BlockDesc* __restrict__ d = descs + find_block(descs, nblk, unit);
-    // leading-step form: every descriptor field read before the step's data
-    // loads, fetched together (left to the compiler, they came in three
-    // dependent scalar round trips).  The empty asm only makes the compiler
-    // hold them all in scalar registers at this point; it emits nothing.
-    if constexpr (LEAD)
-        asm volatile("" ::"s"(d->samples), "s"(d->n), "s"(d->P), "s"(d->ntiles), "s"(d->ngroups),
-                     "s"(d->unit_begin), "s"(d->gen_begin), "s"(d->st), "s"(d->st2), "s"(d->pop), "s"(d->pop2),
-                     "s"(d->trial), "s"(d->trial2), "s"(d->fpop), "s"(d->fpop2), "s"(d->partials),
-                     "s"(d->partials2));
-    // (the leading-step form reads its stop state inside de_lead, which must
-    // also run after a stop to copy the state forward)
-    if (!LEAD && d->st != nullptr && d->st->done) return;
-    const int local = unit - d->unit_begin;
-    const int tile = local / d->ngroups;
-    const int group = local - tile * d->ngroups;
+    const BlockDesc* __restrict__ d = LEAD == 2 ? descs : descs + find_block(descs, nblk, unit);
+    int tile, group, L = 0;
+    LeadIn lin{};
+    if constexpr (LEAD == 2) {
+        // one block (launch index fused - 2, first unit 0) whose step inputs
+        // came as kernel arguments, lp = P | ntiles << 9: nothing here waits
+        // for the descriptor before the step's loads are issued
+        const int P = lp & 511, ng = (P + CPG - 1) / CPG;
+        tile = unit / ng;
+        group = unit - tile * ng;
+        L = fused - 2;
+        lin = LeadIn{l_part, l_rows, l_trial, l_fpop, P, lp >> 9};
+    } else {
+        // leading-step form: every descriptor field read before the step's
+        // data loads, fetched together (left to the compiler, they came in
+        // three dependent scalar round trips).  The empty asm only makes the
+        // compiler hold them all in scalar registers here; it emits nothing.
+        if constexpr (LEAD)
+            asm volatile("" ::"s"(d->samples), "s"(d->n), "s"(d->P), "s"(d->ntiles), "s"(d->ngroups),
+                         "s"(d->unit_begin), "s"(d->gen_begin), "s"(d->st), "s"(d->st2), "s"(d->pop),
+                         "s"(d->pop2), "s"(d->trial), "s"(d->trial2), "s"(d->fpop), "s"(d->fpop2),
+                         "s"(d->partials), "s"(d->partials2));
+        // (the leading-step form reads its stop state inside de_lead, which
+        // must also run after a stop to copy the state forward)
+        if (!LEAD && d->st != nullptr && d->st->done) return;
+        const int local = unit - d->unit_begin;
+        tile = local / d->ngroups;
+        group = local - tile * d->ngroups;
+        if constexpr (LEAD) {
+            L = d->gen_begin + fused - 2;  // the block's launch index (gen_begin: its offset)
+            lin = lead_in_of(d, L);
+        }
+    }
 
     __shared__ double red[CPG][kThreads];
     __shared__ int s_last;
@@ -1420,10 +1494,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 4))
     if constexpr (LEAD) {
         // the samples' loads overlap the DE step's; they stay in their stored
         // type until then (fewer registers across the step)
-        T raw[S];
-        load_lane_raw<T, S>(d, tile, raw);
-        const int L = d->gen_begin + fused - 2;  // the block's launch index (gen_begin: its offset)
-        if (!de_lead<CPG, false>(d, L, tile, group, cs, de_lds, raw)) return;
+        T raw[S];  // loaded inside de_lead, behind the step's own loads
+        if (!de_lead<CPG, false, LEAD == 2>(d, L, tile, group, cs, de_lds, lin, raw)) return;
         unit_setup<S, CPG, MODE, SLOPE>(d, tile, group, cs, rc, nullptr);
         finish_lane<V, T, S>(d, tile, raw, sv, full, valid);
         objective_unit<S, CPG, MODE, SLOPE>(d, tile, group, sv, full, valid, cs, rc, red,

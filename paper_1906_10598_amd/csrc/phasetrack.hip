@@ -126,8 +126,10 @@ int size_class(int64_t n) {
 }
 
 // ----------------------------------------------------------------- launchers
-// lead: the instance of the leading-step form (launched with fused >= 2)
-ObjKernel objective_kernel(int dtype, Geometry g, int mode, bool slope, bool lead = false) {
+// lead: 0 the objective alone (or with the last-workgroup step); 1, 2 the
+// leading-step form (launched with fused >= 2), 2 taking the step's inputs as
+// kernel arguments (one-block fits)
+ObjKernel objective_kernel(int dtype, Geometry g, int mode, bool slope, int lead = 0) {
     const bool f64 = dtype == PT_F64;
     switch (g.spl) {
         case 4: return f64 ? objective_kernel_f64_s4(g.cpg, mode, slope, lead)
@@ -226,7 +228,26 @@ struct Plan {
         ObjKernel obj_lead;  // leading-step instance (null unless that form is planned)
     };
     std::vector<Launch> launches;
+    // One-block leading-step fits: the step's inputs as kernel arguments, per
+    // launch parity p (slot p ^ 1) -- tile partials, population rows, trial
+    // rows, population objectives -- and lp = P | ntiles << 9.  Null: every
+    // launch reads them from the descriptor.
+    struct LeadArgs {
+        const double* part = nullptr;
+        const double* rows = nullptr;
+        const double* trial = nullptr;
+        const double* fpop = nullptr;
+        int lp = 0;
+    };
+    LeadArgs lead_args[2];
 };
+
+// Launch of an objective-kernel instance (argument order of k_objective).
+void launch_objective(ObjKernel k, unsigned grid, size_t lds, hipStream_t s, const BlockDesc* d, int nblk,
+                      int units, int fused, const Plan::LeadArgs& la = Plan::LeadArgs()) {
+    hipLaunchKernelGGL(k, dim3(grid), dim3(kThreads), lds, s, fused, nblk, units, la.lp, la.part, la.rows, la.trial,
+                       la.fpop, d);
+}
 
 }  // namespace
 
@@ -279,11 +300,13 @@ struct pt_ctx {
         size_t de_lds;
         int iters, fused, base;
         std::vector<int> launches;  // (descriptor offset, blocks, arithmetic, units) per objective launch
+        std::vector<const void*> args;  // pointers the launches take as kernel arguments
         bool operator<(const GraphKey& o) const {
             return std::tie(desc, nblk, grid, total_units, spl, cpg, dtype, mixed, slope, de_threads, de_lds, iters,
-                            fused, base, launches) < std::tie(o.desc, o.nblk, o.grid, o.total_units, o.spl, o.cpg,
-                                                              o.dtype, o.mixed, o.slope, o.de_threads, o.de_lds,
-                                                              o.iters, o.fused, o.base, o.launches);
+                            fused, base, launches, args) < std::tie(o.desc, o.nblk, o.grid, o.total_units, o.spl,
+                                                                    o.cpg, o.dtype, o.mixed, o.slope, o.de_threads,
+                                                                    o.de_lds, o.iters, o.fused, o.base, o.launches,
+                                                                    o.args);
         }
     };
     // Cached graph executables, at most kMaxGraphs (the leading-step form keeps
@@ -442,9 +465,9 @@ int enqueue_generation(pt_ctx* ctx, const Plan& pl, hipStream_t s, bool timed, i
         for (size_t k = 0; k < pl.launches.size(); ++k) {
             const Plan::Launch& g = pl.launches[k];
             const int grid = pl.fused == 2 ? g.grid_lead : g.grid;
-            hipLaunchKernelGGL(pl.fused == 2 ? g.obj_lead : g.obj, dim3(grid), dim3(kThreads), pl.de_lds,
-                               k ? ctx->aux_stream : s,
-                               d + g.desc_off, g.nblk, g.total_units, f);
+            launch_objective(pl.fused == 2 ? g.obj_lead : g.obj, grid, pl.de_lds, k ? ctx->aux_stream : s,
+                             d + g.desc_off, g.nblk, g.total_units, f,
+                             pl.fused == 2 ? pl.lead_args[L & 1] : Plan::LeadArgs());
             HIPCHK(hipGetLastError());
         }
         if (fork) {
@@ -456,7 +479,7 @@ int enqueue_generation(pt_ctx* ctx, const Plan& pl, hipStream_t s, bool timed, i
     // (objective alone, then the DE step: the timed path, and the form
     // without fusion)
     for (const Plan::Launch& g : pl.launches) {
-        hipLaunchKernelGGL(g.obj, dim3(g.grid), dim3(kThreads), 0, s, d + g.desc_off, g.nblk, g.total_units, 0);
+        launch_objective(g.obj, g.grid, 0, s, d + g.desc_off, g.nblk, g.total_units, 0);
         HIPCHK(hipGetLastError());
     }
     if (timed) {
@@ -480,8 +503,16 @@ int get_graph(pt_ctx* ctx, const Plan& pl, int iters, int base, hipGraphExec_t* 
         sig.push_back(g.mode);
         sig.push_back(g.total_units);
     }
+    std::vector<const void*> args;
+    for (const Plan::LeadArgs& la : pl.lead_args) {
+        args.push_back(la.part);
+        args.push_back(la.rows);
+        args.push_back(la.trial);
+        args.push_back(la.fpop);
+        args.push_back(reinterpret_cast<const void*>((uintptr_t)(unsigned)la.lp));
+    }
     pt_ctx::GraphKey key{ctx->desc.p, pl.nblk, pl.grid, pl.total_units, pl.geo.spl, pl.geo.cpg, pl.dtype,
-                         pl.mode, (int)pl.slope, pl.de_threads, pl.de_lds, iters, (int)pl.fused, base, sig};
+                         pl.mode, (int)pl.slope, pl.de_threads, pl.de_lds, iters, (int)pl.fused, base, sig, args};
     auto it = ctx->graphs.find(key);
     if (it != ctx->graphs.end()) {
         it->second.used = ++ctx->graph_clock;
@@ -658,7 +689,7 @@ int prepare(pt_ctx* ctx, const pt_block* blocks, int nblk, const pt_de_settings*
     int fusion = ctx->step_fusion;
     if (fusion == PT_FUSION_AUTO)
         fusion = de->max_gens <= kMaxLeadGens &&
-                         lead_fits(ctx, objective_kernel(pl->dtype, pl->geo, pl->mode, pl->slope, true),
+                         lead_fits(ctx, objective_kernel(pl->dtype, pl->geo, pl->mode, pl->slope, 1),
                                    pl->de_lds + (size_t)P * kSlots * 8, units + nblk)
                      ? PT_FUSION_LEAD
                      : PT_FUSION_LAST;
@@ -723,7 +754,9 @@ int prepare(pt_ctx* ctx, const pt_block* blocks, int nblk, const pt_de_settings*
         hd[b] = d;
     }
     // objective launches: one over the main table, or (FP64 batches whose
-    // blocks differ in arithmetic) the phasor blocks and the others apart
+    // blocks differ in arithmetic) the phasor blocks and the others apart; a
+    // one-block leading-step fit passes the step's inputs as kernel arguments
+    const bool lead_fast = pl->fused == 2 && nblk == 1 && P < 512 && ntiles[0] < (1 << 22);
     pl->launches.clear();
     auto add_launch = [&](int desc_off, int n, int mode, int64_t u) {
         Plan::Launch L;
@@ -733,8 +766,9 @@ int prepare(pt_ctx* ctx, const pt_block* blocks, int nblk, const pt_de_settings*
         L.total_units = (int)u;
         L.grid = (int)((u + 7) / 8 * 8);
         L.grid_lead = (int)((u + n + 7) / 8 * 8);
-        L.obj = objective_kernel(pl->dtype, pl->geo, mode, pl->slope, false);
-        L.obj_lead = pl->fused == 2 ? objective_kernel(pl->dtype, pl->geo, mode, pl->slope, true) : nullptr;
+        L.obj = objective_kernel(pl->dtype, pl->geo, mode, pl->slope, 0);
+        L.obj_lead = pl->fused == 2 ? objective_kernel(pl->dtype, pl->geo, mode, pl->slope, lead_fast ? 2 : 1)
+                                    : nullptr;
         pl->launches.push_back(L);
     };
     int ndesc = nblk;
@@ -753,6 +787,14 @@ int prepare(pt_ctx* ctx, const pt_block* blocks, int nblk, const pt_de_settings*
             }
             add_launch(off, ndesc - off, want ? kModePhasor : kModePoly, u);
         }
+    }
+    pl->lead_args[0] = pl->lead_args[1] = Plan::LeadArgs();
+    if (lead_fast) {
+        const BlockDesc& d0 = hd[0];  // gen_begin 0: launch L has parity L & 1
+        for (int p = 0; p < 2; ++p)
+            pl->lead_args[p] = Plan::LeadArgs{p ? d0.partials : d0.partials2, p ? d0.pop : d0.pop2,
+                                              p ? d0.trial : d0.trial2, p ? d0.fpop : d0.fpop2,
+                                              P | (int)(ntiles[0] << 9)};
     }
     HIPCHK(hipMemcpyAsync(ctx->desc.p, hd, sizeof(BlockDesc) * ndesc, hipMemcpyHostToDevice, s));
     return PT_OK;
@@ -1114,7 +1156,7 @@ int pt_objective(pt_ctx* ctx, const pt_block* block, const double* pop, int P, i
     int rc = eval_setup(ctx, block, pop, P, precision, objective, s, &pl, &obj);
     if (rc) return rc;
     const BlockDesc* d = static_cast<const BlockDesc*>(ctx->desc.p);
-    hipLaunchKernelGGL(obj, dim3(pl.grid), dim3(kThreads), 0, s, d, 1, pl.total_units, 0);
+    launch_objective(obj, pl.grid, 0, s, d, 1, pl.total_units, 0);
     HIPCHK(hipGetLastError());
     hipLaunchKernelGGL(k_reduce_out, dim3(1), dim3(pl.de_threads), pl.de_threads * sizeof(double), s, d, out);
     HIPCHK(hipGetLastError());
@@ -1193,8 +1235,7 @@ int pt_objective_noalloc(pt_ctx* ctx, const pt_block* block, const double* pop, 
     HIPCHK(hipGetLastError());
     hipLaunchKernelGGL(k_pack_rows, dim3(1), dim3(256), 0, s, pop, rows, P);
     HIPCHK(hipGetLastError());
-    hipLaunchKernelGGL(obj, dim3((unsigned)((units + 7) / 8 * 8)), dim3(kThreads), 0, s, (const BlockDesc*)dd, 1,
-                       (int)units, 0);
+    launch_objective(obj, (unsigned)((units + 7) / 8 * 8), 0, s, (const BlockDesc*)dd, 1, (int)units, 0);
     HIPCHK(hipGetLastError());
     hipLaunchKernelGGL(k_reduce_out, dim3(1), dim3(pl.de_threads), pl.de_threads * sizeof(double), s,
                        (const BlockDesc*)dd, out);
@@ -1216,12 +1257,12 @@ int pt_time_objective(pt_ctx* ctx, const pt_block* block, const double* pop, int
     int rc = eval_setup(ctx, block, pop, P, precision, PT_OBJ_CHI2, s, &pl, &obj);
     if (rc) return rc;
     const BlockDesc* d = static_cast<const BlockDesc*>(ctx->desc.p);
-    hipLaunchKernelGGL(obj, dim3(pl.grid), dim3(kThreads), 0, s, d, 1, pl.total_units, 0);  // warm
+    launch_objective(obj, pl.grid, 0, s, d, 1, pl.total_units, 0);  // warm
     HIPCHK(hipGetLastError());
     hipEvent_t e0 = take_event(ctx), e1 = take_event(ctx);
     if (!e0 || !e1) return fail(PT_EDEVICE, "hipEventCreate failed");
     HIPCHK(hipEventRecord(e0, s));
-    for (int r = 0; r < reps; ++r) hipLaunchKernelGGL(obj, dim3(pl.grid), dim3(kThreads), 0, s, d, 1, pl.total_units, 0);
+    for (int r = 0; r < reps; ++r) launch_objective(obj, pl.grid, 0, s, d, 1, pl.total_units, 0);
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(e1, s));
     HIPCHK(hipEventSynchronize(e1));
@@ -2120,14 +2161,14 @@ int pt_server_step(pt_server* sv, void* hip_stream, int32_t* n_active, int32_t* 
         if (lead) {
             for (const Launch& L : launches) {
                 const int grid = (L.units + L.count + 7) / 8 * 8;  // plus one bookkeeping unit per block
-                hipLaunchKernelGGL(L.k, dim3(grid), dim3(kThreads), de_lds + (size_t)P * kSlots * 8, s,
-                                   dd + L.first, L.count, L.units, 2 + k);
+                launch_objective(L.k, grid, de_lds + (size_t)P * kSlots * 8, s, dd + L.first, L.count, L.units,
+                                 2 + k);
             }
             continue;
         }
         for (const Launch& L : launches) {
             const int grid = (L.units + 7) / 8 * 8;
-            hipLaunchKernelGGL(L.k, dim3(grid), dim3(kThreads), 0, s, dd + L.first, L.count, L.units, 0);
+            launch_objective(L.k, grid, 0, s, dd + L.first, L.count, L.units, 0);
         }
         hipLaunchKernelGGL(k_de_step, dim3(nb), dim3(de_threads), de_lds, s, dd);
     }
