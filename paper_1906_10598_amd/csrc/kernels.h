@@ -628,7 +628,12 @@ __device__ __forceinline__ void objective_unit(const BlockDesc* __restrict__ d, 
     const bool quart = d->quartic != 0;
     const double mt = (double)((int64_t)tile * (kThreads * S)) - d->ref;  // the tile's first sample
     const double m0 = mt + (double)(tid * S);                             // the lane's first sample
-    auto keep = [&](int c, double acc) { red[c][tid] = acc; };
+    // A wave none of whose lanes holds a chunk that is partly past the block's
+    // end runs the loop of full chunks, and its lanes wholly past the end drop
+    // their sums at the end (the same values as masking every sample); only
+    // the wave holding the block's one partial chunk, if any, masks per sample.
+    const bool wave_full = full || __ballot(valid != 0 && valid != S) == 0;
+    auto keep = [&](int c, double acc) { red[c][tid] = (full || cor || valid != 0) ? acc : 0.0; };
 
     if constexpr (MODE == 2) {
         // the phasor path: tile constants plus per-lane polynomial updates (the
@@ -649,7 +654,7 @@ __device__ __forceinline__ void objective_unit(const BlockDesc* __restrict__ d, 
         };
         if (cor)
             run(std::false_type{}, std::true_type{});
-        else if (full)
+        else if (wave_full)
             run(std::false_type{}, std::false_type{});
         else
             run(std::true_type{}, std::false_type{});
@@ -660,9 +665,9 @@ __device__ __forceinline__ void objective_unit(const BlockDesc* __restrict__ d, 
             const double amp0 = SLOPE ? __fma_rn(cc.Ad, m0, cc.A) : cc.A;
             double acc;
             if (quart)
-                acc = lane_sum<MODE, S, SLOPE, true>(sv, an, amp0, cc.Ad, valid, cor, full);
+                acc = lane_sum<MODE, S, SLOPE, true>(sv, an, amp0, cc.Ad, valid, cor, wave_full);
             else
-                acc = lane_sum<MODE, S, SLOPE, false>(sv, an, amp0, cc.Ad, valid, cor, full);
+                acc = lane_sum<MODE, S, SLOPE, false>(sv, an, amp0, cc.Ad, valid, cor, wave_full);
             keep(c, acc);
         }
     }
