@@ -24,10 +24,11 @@ HIPCC_FLAGS = [
     # keep the compiler from forming packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     # gfx950 preloads the first kernel arguments into scalar registers at
-    # wave launch, saving the kernel-argument load before the descriptor
-    # load (each code object keeps a prologue that loads them for firmware
-    # without preloading): 2 % on the objective launch, 1 % on a fit
-    "-mllvm", "-amdgpu-kernarg-preload-count=8",
+    # wave launch (at most 14 dwords: the objective kernel's nine, down to
+    # its descriptor pointer), saving the kernel-argument load before the
+    # descriptor load (each code object keeps a prologue that loads them for
+    # firmware without preloading): 2 % on the objective launch, 1 % on a fit
+    "-mllvm", "-amdgpu-kernarg-preload-count=9",
     "-Wall",
     "-Wno-unused-function",
 ]

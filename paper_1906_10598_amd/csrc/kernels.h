@@ -102,10 +102,19 @@ __device__ __forceinline__ void xsti(int* p, int v) {
 // ---------------------------------------------------------------------------
 // helpers
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double wave_sum(double v) {
+// Sums over the wave of N values at once: a fixed-order xor butterfly for
+// each, the N chains side by side so that their shuffles are in flight
+// together
+template <int N>
+__device__ __forceinline__ void wave_sums(double (&v)[N]) {
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    for (int off = 32; off >= 1; off >>= 1) {
+        double o[N];
+#pragma unroll
+        for (int r = 0; r < N; ++r) o[r] = __shfl_xor(v[r], off, 64);
+#pragma unroll
+        for (int r = 0; r < N; ++r) v[r] += o[r];
+    }
 }
 
 __device__ __forceinline__ int find_block(const BlockDesc* __restrict__ descs, int nblk, int unit) {
@@ -672,14 +681,25 @@ __device__ __forceinline__ void objective_unit(const BlockDesc* __restrict__ d, 
         }
     }
     __syncthreads();
-    // one FP64 partial per (candidate, tile): each wave adds one candidate's four
-    // wave-slices lane by lane, then a fixed-order shuffle butterfly
-    for (int c = wave; c < ncand; c += kThreads / 64) {
-        double v = red[c][lane];
+    // one FP64 partial per (candidate, tile): wave w takes candidates w,
+    // w + 4, ..., adds each one's four wave-slices lane by lane, then runs the
+    // fixed-order shuffle butterfly of all of them side by side (rows past
+    // the group's candidates are read, clamped, and not stored)
+    constexpr int kW = kThreads / 64, kPer = (CPG + kW - 1) / kW;
+    double v[kPer];
 #pragma unroll
-        for (int q = 1; q < kThreads / 64; ++q) v += red[c][lane + 64 * q];
-        v = wave_sum(v);
-        if (lane == 0) xst(part + (size_t)(cbase + c) * d->ntiles + tile, v);
+    for (int r = 0; r < kPer; ++r) {
+        const int c = min(wave + r * kW, CPG - 1);
+        double x = red[c][lane];
+#pragma unroll
+        for (int q = 1; q < kW; ++q) x += red[c][lane + 64 * q];
+        v[r] = x;
+    }
+    wave_sums(v);
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) {
+        const int c = wave + r * kW;
+        if (lane == 0 && c < ncand) xst(part + (size_t)(cbase + c) * d->ntiles + tile, v[r]);
     }
 }
 
@@ -872,16 +892,34 @@ __device__ __forceinline__ Draws trial_draws_octet(const BlockDesc* __restrict__
     return draws_from(w, u0, u1, i, d->P, d->D, d->CR);
 }
 
+// Quotients of small non-negative integers by an FP32 reciprocal instead of
+// the integer division sequence (tens of dependent instructions on the
+// chain before the leading step's loads).
+// floor(a / b) for 0 <= a <= 4096, b >= 1: the fractional part of
+// (a + 1/2) / b lies in [1/(2b), 1 - 1/(2b)], and the reciprocal (1 ulp)
+// and the product (1/2 ulp) move the quotient by less than 2^-11 / b.
+__device__ __forceinline__ int div_small(int a, int b) {
+    return (int)(((float)a + 0.5f) * __builtin_amdgcn_rcpf((float)b));
+}
+// floor(a / b) for 0 <= a < 2^23, b >= 1: the FP32 estimate is within one
+// of the quotient, and one remainder test corrects it.
+__device__ __forceinline__ int div_mid(int a, int b) {
+    int q = (int)((float)a * __builtin_amdgcn_rcpf((float)b));
+    const int r = a - q * b;
+    q += r >= b ? 1 : 0;
+    q -= r < 0 ? 1 : 0;
+    return q;
+}
+
 // Draws of one member packed into the pad slot (slot 7) of its trial row
 // (P <= 256, at most 7 active coordinates): r1, r2, r3 in bytes 0-2, the
-// crossover mask in byte 3, as the bits of a double (only stored and loaded).
-__device__ __forceinline__ double pack_draws(const Draws& w) {
-    const unsigned long long u = (unsigned long long)((unsigned)w.r1 | ((unsigned)w.r2 << 8) |
-                                                      ((unsigned)w.r3 << 16) | (w.cross << 24));
-    return __longlong_as_double((long long)u);
+// crossover mask in byte 3 of the low word; the high word holds the stop
+// flag the launch reading the row needs (the fit has stopped).
+__device__ __forceinline__ unsigned long long pack_draws(const Draws& w, bool done) {
+    return (unsigned long long)((unsigned)w.r1 | ((unsigned)w.r2 << 8) | ((unsigned)w.r3 << 16) | (w.cross << 24)) |
+           ((unsigned long long)done << 32);
 }
-__device__ __forceinline__ Draws unpack_draws(double x) {
-    const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+__device__ __forceinline__ Draws unpack_draws(unsigned long long u) {
     return Draws{(int)(u & 255u), (int)((u >> 8) & 255u), (int)((u >> 16) & 255u), (unsigned)((u >> 24) & 255u)};
 }
 
@@ -1136,9 +1174,17 @@ __device__ __forceinline__ bool de_lead(const BlockDesc* __restrict__ d, int L, 
     // kernel its fourth wave per SIMD (143 VGPRs instead of 115)
     constexpr int kB = 17;
     const int T = in.T;
-    const int k = NT >= P ? NT / P : 1;
-    const int pm = i / k, part = i - pm * k;
-    const int cnt = (i < P * k && part < T) ? (T - part + k - 1) / k : 0;
+    // (T < 2^21: a block holds fewer than 2^31 samples, a tile at least 2^10)
+    const int k = NT >= P ? div_small(NT, P) : 1;
+    const int pm = div_small(i, k), part = i - pm * k;
+    const int cnt = (i < P * k && part < T) ? div_mid(T - part + k - 1, k) : 0;
+    // this thread's trial coordinate (candidate c = i / 8 of the group, slot
+    // j = i % 8): its bounds, read first (per-lane indices into the
+    // descriptor, so vector loads; issued after the step's loads they would
+    // wait for them)
+    const int c = (i & 63) >> 3, j = i & 7;
+    const int jc = j < kSlots ? j : kSlots - 1;
+    const double lo_j = gld(&d->lo[jc]), hi_j = gld(&d->hi[jc]);
     const double* pr = part_in + (size_t)pm * T + part;
     double v[kB];
     // (no load sits in a branch: out-of-range ones read a valid address and
@@ -1163,9 +1209,12 @@ __device__ __forceinline__ bool de_lead(const BlockDesc* __restrict__ d, int L, 
     const double fo = gld(fpop_in + min(i, P - 1));
     // PRE: this lane's trial draws, made by the previous launch's bookkeeping
     // workgroup and kept in the pad slot of the trial rows this step reads
-    const int c = (i & 63) >> 3, j = i & 7;
-    double dpk = 0.0;
-    if constexpr (PRE) dpk = gld(trial_in + (size_t)min(cbase + c, P - 1) * kStride + kSlots);
+    // (and, in the high word, whether the fit has stopped: no dependent
+    // loads through the descriptor's state pointer)
+    unsigned long long dpk = 0ull;
+    if constexpr (PRE)
+        dpk = gld(reinterpret_cast<const unsigned long long*>(trial_in + (size_t)min(cbase + c, P - 1) * kStride +
+                                                              kSlots));
     // what comes from the descriptor, behind the step's loads: the lane's
     // samples (needed only by the objective after the step), the state and
     // the slots the step writes
@@ -1178,25 +1227,22 @@ __device__ __forceinline__ bool de_lead(const BlockDesc* __restrict__ d, int L, 
     double* rows_out = p ? pop1 : pop0;  // slot p
     double* trial_out = p ? tr1 : tr0;
     double* fpop_out = p ? fp1 : fp0;
-    const int st_done = gld(&st_in->done);
-    const double st_old = gld(&st_in->old);
+    const int st_done = PRE ? 0 : gld(&st_in->done);
+    const double st_old = BOOK ? gld(&st_in->old) : 0.0;
 
     // 2. while they are in flight: the random draws of this thread's trial
     //    coordinate (candidate c = i / 8 of the group, slot j = i % 8); the
-    //    bookkeeping workgroup makes every member's draws of the next launch
-    //    and stores them in the pad slot of the trial rows it reads (PRE)
+    //    bookkeeping workgroup makes every member's draws of the next launch,
+    //    to store them with the stop flag in the pad slot of the trial rows
+    //    that launch reads (PRE)
     const bool tw = !BOOK && L > 0 && c < ncand && i < 64;
-    // this thread's coordinate: its bounds (a per-lane index into the
-    // descriptor, so vector loads) and its place among the active slots, read
-    // with the step's other data rather than after the selection
-    const int jc = j < kSlots ? j : kSlots - 1;
-    const double lo_j = gld(&d->lo[jc]), hi_j = gld(&d->hi[jc]);
+    // this thread's coordinate's place among the active slots
     const unsigned am = (unsigned)d->amask;
     const int a_j = ((am >> j) & 1u) ? __builtin_popcount(am & ((1u << j) - 1u)) : -1;
     const double Fm = d->F, fs = d->fs;
     Draws dr{0, 0, 0, 0u};
     if constexpr (BOOK) {
-        if (i < P) gst(trial_out + (size_t)i * kStride + kSlots, pack_draws(trial_draws(d, i, (uint32_t)(L + 1))));
+        if (i < P) dr = trial_draws(d, i, (uint32_t)(L + 1));
     } else if constexpr (!PRE) {
         // (every lane of the wave makes the octet draws, so that the octets'
         // exchanges see all their lanes; only those with tw use them)
@@ -1218,11 +1264,6 @@ __device__ __forceinline__ bool de_lead(const BlockDesc* __restrict__ d, int L, 
         for (int q = 0; q < kB; ++q)
             if (base + q < cnt) sp += v[q];
     }
-    // the lane's samples (loaded before the step) must have arrived here, so
-    // their loads are issued with the step's and not after it
-#pragma unroll
-    for (int q = 0; q < RS; ++q) asm volatile("" ::"v"(raw[q]));
-    asm volatile("" ::"v"(lo_j), "v"(hi_j));
     if (i < P * k) red[i] = sp;
 #pragma unroll
     for (int r = 0; r < kR; ++r) {
@@ -1238,19 +1279,37 @@ __device__ __forceinline__ bool de_lead(const BlockDesc* __restrict__ d, int L, 
         xs[e] = gld(trial_in + off);
         xp[e] = gld(rows_in + off);
     }
-    if (i == 0) {
+    // the stop state: the bookkeeping workgroup needs it here; objective
+    // workgroups only after the selection (its loads, two dependent round
+    // trips through the descriptor, then have that much longer to arrive)
+    if (BOOK && i == 0) {
         s_done = st_done;
         s_old = st_old;
     }
     __syncthreads();
     double ft = 0.0;
     if (i < P) {
-        for (int q = 0; q < k; ++q) ft += red[i * k + q];
+        // the member's k subtotals added in order, read eight at a time (one
+        // LDS round trip per eight rather than per subtotal)
+        for (int b = 0; b < k; b += 8) {
+            double w[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) w[q] = red[i * k + min(b + q, k - 1)];
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (b + q < k) ft += w[q];
+        }
         // correlation objective, Eq. (2-2-5): F = 1 / (arctan(C) + pi/2)
         if (d->objective != 0) ft = 1.0 / (atan(ft) + 1.5707963267948966192);
     }
-    if (s_done) {
-        if (BOOK && i == 0) {
+    // (the bookkeeping workgroup's pad-slot stores, at each of its exits)
+    auto store_pad = [&](bool done) {
+        if (BOOK && i < P)
+            gst(reinterpret_cast<unsigned long long*>(trial_out + (size_t)i * kStride + kSlots), pack_draws(dr, done));
+    };
+    if (BOOK && s_done) {
+        store_pad(true);
+        if (i == 0) {
             const DeState s = *st_in;
             xsti(&st_out->gen, s.gen);
             xsti(&st_out->done, s.done);
@@ -1263,10 +1322,14 @@ __device__ __forceinline__ bool de_lead(const BlockDesc* __restrict__ d, int L, 
     }
     if (L == 0) {
         // generation 0: the initial population as stored (slot 0); no step
-        if (BOOK) return false;
+        if (BOOK) {
+            store_pad(false);
+            return false;
+        }
         if (i < ncand) cs[i] = make_cand<false>(trial_out + (size_t)(cbase + i) * kStride, d->fs);
+        if (i == 0) s_done = st_done;  // (0 for PRE: a fit starts unstopped)
         __syncthreads();
-        return true;
+        return !s_done;
     }
     const int g = L - 1;
 
@@ -1281,7 +1344,10 @@ __device__ __forceinline__ bool de_lead(const BlockDesc* __restrict__ d, int L, 
         fsel = take ? ft : fo;
     }
     if constexpr (!BOOK) {
+        // a stopped fit evaluates nothing (the selection above wrote only LDS)
+        if (i == 0) s_done = PRE ? (int)(dpk >> 32) : st_done;
         __syncthreads();  // selected rows complete
+        if (s_done) return false;
         if constexpr (PRE) dr = unpack_draws(dpk);
         // 5. the group's trials, one coordinate per thread (apply_trial's
         //    arithmetic), straight into the candidates' turn-domain form
@@ -1303,6 +1369,10 @@ __device__ __forceinline__ bool de_lead(const BlockDesc* __restrict__ d, int L, 
             // bookkeeping workgroup)
             if (tile == 0 && j < kSlots) gst(trial_out + (size_t)m * kStride + j, y);
         }
+        // the lane's samples (loaded before the step) must have arrived here,
+        // so their loads are issued with the step's and not after it
+#pragma unroll
+        for (int q = 0; q < RS; ++q) asm volatile("" ::"v"(raw[q]));
         __syncthreads();
         return true;
     }
@@ -1329,6 +1399,7 @@ __device__ __forceinline__ bool de_lead(const BlockDesc* __restrict__ d, int L, 
         for (int q = kSlots; q < kStride; ++q) gst(r + q, 0.0);
         gst(fpop_out + i, fsel);
     }
+    store_pad(flags != 0);
     if (i == 0) {
         xst(d->hist + g, bf);
         // the window rule of the next step compares with hist[g + 1 - window]
