@@ -1136,15 +1136,24 @@ __device__ __forceinline__ LeadIn lead_in_of(const BlockDesc* __restrict__ d, in
 // the final state to the other slot, so every later launch sees it.
 //
 // Returns false when there is nothing to evaluate (BOOK, or the fit has
-// stopped); otherwise the group's candidates are in cs, past a barrier.
+// stopped); otherwise the group's candidates are in cs, past a barrier, and
+// conv (the conversion of the lane's samples, raw, loaded by the step) has
+// run on every wave but the trial wave, which runs it next.
 // lds: the DE step's dynamic LDS plus P * kSlots doubles (2 P kSlots + 2 *
 // 256 doubles + 256 ints).  Workgroups of kThreads threads (k_objective's):
 // a compile-time count keeps the launch's geometry out of the chain of
 // dependent loads before the step's data loads.
 // ---------------------------------------------------------------------------
-template <int CPG, bool BOOK, bool PRE, typename RT, int RS>
+// The wave that builds a group's trials.  The others convert their lanes'
+// samples (conv) meanwhile, and the trial wave does while wave 0 makes the
+// tile constants; neither conversion waits for the samples before the
+// selection is done.
+constexpr int kTrialWave = 1;
+static_assert(kThreads >= 128, "the trial wave is the second wave");
+
+template <int CPG, bool BOOK, bool PRE, typename RT, int RS, typename Conv>
 __device__ __forceinline__ bool de_lead(const BlockDesc* __restrict__ d, int L, int tile, int group, Cand* cs,
-                                        double* lds, const LeadIn& in, RT (&raw)[RS]) {
+                                        double* lds, const LeadIn& in, RT (&raw)[RS], Conv&& conv) {
     const int p = L & 1;
     constexpr int NT = kThreads;
     const int P = in.P, i = threadIdx.x;
@@ -1219,6 +1228,13 @@ __device__ __forceinline__ bool de_lead(const BlockDesc* __restrict__ d, int L, 
     // samples (needed only by the objective after the step), the state and
     // the slots the step writes
     if constexpr (!BOOK) load_lane_raw<RT, RS>(d, tile, raw);
+    // every descriptor field the rest of the launch reads, fetched in the
+    // scalar round trip the samples' address needs anyway (read later, after
+    // a barrier, each line of the descriptor would be one more round trip;
+    // the empty asm only makes the compiler hold them here)
+    if constexpr (PRE)
+        asm volatile("" ::"s"(d->ref), "s"(d->F), "s"(d->objective), "s"(d->quartic), "s"(d->amask),
+                     "s"(d->trial), "s"(d->trial2), "s"(d->partials), "s"(d->partials2));
     DeState *st0 = d->st, *st1 = d->st2;
     double *pop0 = d->pop, *pop1 = d->pop2, *tr0 = d->trial, *tr1 = d->trial2;
     double *fp0 = d->fpop, *fp1 = d->fpop2;
@@ -1235,7 +1251,8 @@ __device__ __forceinline__ bool de_lead(const BlockDesc* __restrict__ d, int L, 
     //    bookkeeping workgroup makes every member's draws of the next launch,
     //    to store them with the stop flag in the pad slot of the trial rows
     //    that launch reads (PRE)
-    const bool tw = !BOOK && L > 0 && c < ncand && i < 64;
+    const int wave = i >> 6;
+    const bool tw = !BOOK && L > 0 && c < ncand && wave == kTrialWave;
     // this thread's coordinate's place among the active slots
     const unsigned am = (unsigned)d->amask;
     const int a_j = ((am >> j) & 1u) ? __builtin_popcount(am & ((1u << j) - 1u)) : -1;
@@ -1246,7 +1263,7 @@ __device__ __forceinline__ bool de_lead(const BlockDesc* __restrict__ d, int L, 
     } else if constexpr (!PRE) {
         // (every lane of the wave makes the octet draws, so that the octets'
         // exchanges see all their lanes; only those with tw use them)
-        if (L > 0 && i < 64) dr = trial_draws_octet(d, cbase + c, (uint32_t)L);
+        if (L > 0 && wave == kTrialWave) dr = trial_draws_octet(d, cbase + c, (uint32_t)L);
     }
 
     // 3. objectives of all P trials, in reduce_partials' order
@@ -1328,6 +1345,7 @@ __device__ __forceinline__ bool de_lead(const BlockDesc* __restrict__ d, int L, 
         }
         if (i < ncand) cs[i] = make_cand<false>(trial_out + (size_t)(cbase + i) * kStride, d->fs);
         if (i == 0) s_done = st_done;  // (0 for PRE: a fit starts unstopped)
+        if (wave != kTrialWave) conv();
         __syncthreads();
         return !s_done;
     }
@@ -1348,6 +1366,7 @@ __device__ __forceinline__ bool de_lead(const BlockDesc* __restrict__ d, int L, 
         if (i == 0) s_done = PRE ? (int)(dpk >> 32) : st_done;
         __syncthreads();  // selected rows complete
         if (s_done) return false;
+        if (wave != kTrialWave) conv();
         if constexpr (PRE) dr = unpack_draws(dpk);
         // 5. the group's trials, one coordinate per thread (apply_trial's
         //    arithmetic), straight into the candidates' turn-domain form
@@ -1369,10 +1388,6 @@ __device__ __forceinline__ bool de_lead(const BlockDesc* __restrict__ d, int L, 
             // bookkeeping workgroup)
             if (tile == 0 && j < kSlots) gst(trial_out + (size_t)m * kStride + j, y);
         }
-        // the lane's samples (loaded before the step) must have arrived here,
-        // so their loads are issued with the step's and not after it
-#pragma unroll
-        for (int q = 0; q < RS; ++q) asm volatile("" ::"v"(raw[q]));
         __syncthreads();
         return true;
     }
@@ -1522,7 +1537,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 4))
                 float none[1] = {0.0f};
                 const BlockDesc* db = descs + (unit - total_units);
                 const int Lb = db->gen_begin + fused - 2;
-                de_lead<CPG, true, false>(db, Lb, 0, 0, cs, de_lds, lead_in_of(db, Lb), none);
+                de_lead<CPG, true, false>(db, Lb, 0, 0, cs, de_lds, lead_in_of(db, Lb), none, [] {});
             }
         }
         return;
@@ -1548,7 +1563,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 4))
             asm volatile("" ::"s"(d->samples), "s"(d->n), "s"(d->P), "s"(d->ntiles), "s"(d->ngroups),
                          "s"(d->unit_begin), "s"(d->gen_begin), "s"(d->st), "s"(d->st2), "s"(d->pop),
                          "s"(d->pop2), "s"(d->trial), "s"(d->trial2), "s"(d->fpop), "s"(d->fpop2),
-                         "s"(d->partials), "s"(d->partials2));
+                         "s"(d->partials), "s"(d->partials2), "s"(d->F), "s"(d->objective));
         // (the leading-step form reads its stop state inside de_lead, which
         // must also run after a stop to copy the state forward)
         if (!LEAD && d->st != nullptr && d->st->done) return;
@@ -1568,12 +1583,13 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 4))
     bool full;
     int valid;
     if constexpr (LEAD) {
-        // the samples' loads overlap the DE step's; they stay in their stored
-        // type until then (fewer registers across the step)
+        // the samples' loads overlap the DE step's, and the step converts
+        // them into sv where each wave would otherwise idle
         T raw[S];  // loaded inside de_lead, behind the step's own loads
-        if (!de_lead<CPG, false, LEAD == 2>(d, L, tile, group, cs, de_lds, lin, raw)) return;
+        auto conv = [&] { finish_lane<V, T, S>(d, tile, raw, sv, full, valid); };
+        if (!de_lead<CPG, false, LEAD == 2>(d, L, tile, group, cs, de_lds, lin, raw, conv)) return;
+        if ((int)(threadIdx.x >> 6) == kTrialWave) conv();  // while wave 0 makes the tile constants
         unit_setup<S, CPG, MODE, SLOPE>(d, tile, group, cs, rc, nullptr);
-        finish_lane<V, T, S>(d, tile, raw, sv, full, valid);
         objective_unit<S, CPG, MODE, SLOPE>(d, tile, group, sv, full, valid, cs, rc, red,
                                             (L & 1) ? d->partials2 : d->partials);
     } else {
