@@ -102,19 +102,61 @@ __device__ __forceinline__ void xsti(int* p, int v) {
 // ---------------------------------------------------------------------------
 // helpers
 // ---------------------------------------------------------------------------
-// Sums over the wave of N values at once: a fixed-order xor butterfly for
-// each, the N chains side by side so that their shuffles are in flight
-// together
+// Sums over the wave of N values at once, each ending in every lane: pairs,
+// quads, eights and rows of 16 lanes by DPP lane moves (quad permutations,
+// half-row and row mirrors), then the two halves of each 32 and of the wave
+// by the lane-swap instructions; every step adds two values that both lanes
+// of a pair hold, so all lanes end with the same bits.  The N chains run side
+// by side.  (Register moves with a few cycles of latency, where a shuffle
+// through the LDS crossbar costs a round trip per step.)
+__device__ __forceinline__ double dpp_move(double v, int ctrl) {
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    int a, b;
+    switch (ctrl) {  // (the control is an immediate of the instruction)
+    case 0:  // quad_perm [1, 0, 3, 2]: the other lane of the pair
+        a = __builtin_amdgcn_update_dpp(0, lo, 0xB1, 0xF, 0xF, false);
+        b = __builtin_amdgcn_update_dpp(0, hi, 0xB1, 0xF, 0xF, false);
+        break;
+    case 1:  // quad_perm [2, 3, 0, 1]: the other pair of the quad
+        a = __builtin_amdgcn_update_dpp(0, lo, 0x4E, 0xF, 0xF, false);
+        b = __builtin_amdgcn_update_dpp(0, hi, 0x4E, 0xF, 0xF, false);
+        break;
+    case 2:  // row_half_mirror: the other quad of the eight
+        a = __builtin_amdgcn_update_dpp(0, lo, 0x141, 0xF, 0xF, false);
+        b = __builtin_amdgcn_update_dpp(0, hi, 0x141, 0xF, 0xF, false);
+        break;
+    default:  // row_mirror: the other eight of the row
+        a = __builtin_amdgcn_update_dpp(0, lo, 0x140, 0xF, 0xF, false);
+        b = __builtin_amdgcn_update_dpp(0, hi, 0x140, 0xF, 0xF, false);
+        break;
+    }
+    return __hiloint2double(b, a);
+}
+template <bool W32>
+__device__ __forceinline__ double swap_add(double v) {
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    // each lane gets its own value and its partner's (other row of the pair
+    // of rows, or other half of the wave), in the same order on both sides
+    const auto l = W32 ? __builtin_amdgcn_permlane32_swap(lo, lo, false, false)
+                       : __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    const auto h = W32 ? __builtin_amdgcn_permlane32_swap(hi, hi, false, false)
+                       : __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    return __hiloint2double(h[0], l[0]) + __hiloint2double(h[1], l[1]);
+}
 template <int N>
 __device__ __forceinline__ void wave_sums(double (&v)[N]) {
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
+    for (int s = 0; s < 4; ++s) {
         double o[N];
 #pragma unroll
-        for (int r = 0; r < N; ++r) o[r] = __shfl_xor(v[r], off, 64);
+        for (int r = 0; r < N; ++r) o[r] = dpp_move(v[r], s);
 #pragma unroll
         for (int r = 0; r < N; ++r) v[r] += o[r];
     }
+#pragma unroll
+    for (int r = 0; r < N; ++r) v[r] = swap_add<false>(v[r]);
+#pragma unroll
+    for (int r = 0; r < N; ++r) v[r] = swap_add<true>(v[r]);
 }
 
 __device__ __forceinline__ int find_block(const BlockDesc* __restrict__ descs, int nblk, int unit) {
