@@ -12,8 +12,9 @@ populations and the best-so-far history.  Covered: the tiny block in both
 precisions, the paper-scale block, a batch of uneven blocks sharing each
 launch, the window stop rule with blocks stopping at different generations
 (in both launch parities), a stop at generation 0 (value to reach), a
-fit with no generation after the initial one, and fits with per-launch
-timing on (which run every form as the objective alone plus the DE step).
+fit with no generation after the initial one, populations past one wave
+(P = 100, 256), and fits with per-launch timing on (which run every form as
+the objective alone plus the DE step).
 """
 import numpy as np
 import pytest
@@ -101,6 +102,24 @@ def test_stop_at_generation_zero_and_no_generations(mode):
         a, o = _fit(mode, [block_of(b, dev)], de), _fit(ptk.PT_FUSION_OFF, [block_of(b, dev)], de)
         assert a[0][0].generations == o[0][0].generations <= 1
         _same(a, o, f"fusion {mode} gens {de.max_gens} vtr {de.vtr}")
+
+
+@pytest.mark.parametrize("mode", FORMS)
+@pytest.mark.parametrize("pop", [100, 256])
+def test_populations_past_one_wave(mode, pop):
+    # P > 64: the leading step's selection spans several waves, its rows take
+    # more than one round of loads (P > 73) and fewer threads sum each member's
+    # partials (k = 256 / P); one block (arguments form) and a batch of two
+    # (descriptor form), with a window stop
+    b = synth.config0(4)
+    dev = to_dev(b.samples)
+    de = settings_of(b, gens=80, pop=pop, rel_tol=1e-6, window=10)
+    _same(_fit(mode, [block_of(b, dev)], de), _fit(ptk.PT_FUSION_OFF, [block_of(b, dev)], de),
+          f"fusion {mode} P {pop}")
+    b2 = synth.config0(5)
+    dev2 = to_dev(b2.samples)
+    pbs = [block_of(b, dev), block_of(b2, dev2)]
+    _same(_fit(mode, pbs, de), _fit(ptk.PT_FUSION_OFF, pbs, de), f"fusion {mode} P {pop} batch")
 
 
 def test_invalid_fusion_mode():
