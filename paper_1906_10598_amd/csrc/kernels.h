@@ -1257,7 +1257,13 @@ __device__ __forceinline__ bool de_lead(const BlockDesc* __restrict__ d, int L, 
         rt[r] = gld(trial_in + off);
         rp[r] = gld(rows_in + off);
     }
-    const double fo = gld(fpop_in + min(i, P - 1));
+    // the member a thread selects: for P <= 64 in an objective workgroup the
+    // trial wave's lanes select (so the trials need no barrier after the
+    // selection, only the wave's own order), otherwise thread i selects i
+    const bool one = !BOOK && P <= 64;
+    const int sm = one ? (i & 63) : i;
+    const bool selects = one ? (i >> 6) == kTrialWave && sm < P : i < P;
+    const double fo = gld(fpop_in + min(sm, P - 1));
     // PRE: this lane's trial draws, made by the previous launch's bookkeeping
     // workgroup and kept in the pad slot of the trial rows this step reads
     // (and, in the high word, whether the fit has stopped: no dependent
@@ -1347,13 +1353,13 @@ __device__ __forceinline__ bool de_lead(const BlockDesc* __restrict__ d, int L, 
     }
     __syncthreads();
     double ft = 0.0;
-    if (i < P) {
+    if (selects) {
         // the member's k subtotals added in order, read eight at a time (one
         // LDS round trip per eight rather than per subtotal)
         for (int b = 0; b < k; b += 8) {
             double w[8];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) w[q] = red[i * k + min(b + q, k - 1)];
+            for (int q = 0; q < 8; ++q) w[q] = red[sm * k + min(b + q, k - 1)];
 #pragma unroll
             for (int q = 0; q < 8; ++q)
                 if (b + q < k) ft += w[q];
@@ -1395,19 +1401,30 @@ __device__ __forceinline__ bool de_lead(const BlockDesc* __restrict__ d, int L, 
 
     // 4. selection (generation 0 accepts the initial population)
     double fsel = __builtin_inf();
-    if (i < P) {
+    if (selects) {
         const bool take = g == 0 || ft <= fo;
         if (!take) {
 #pragma unroll
-            for (int q = 0; q < kSlots; ++q) xs[i * kSlots + q] = xp[i * kSlots + q];
+            for (int q = 0; q < kSlots; ++q) xs[sm * kSlots + q] = xp[sm * kSlots + q];
         }
         fsel = take ? ft : fo;
     }
     if constexpr (!BOOK) {
-        // a stopped fit evaluates nothing (the selection above wrote only LDS)
-        if (i == 0) s_done = PRE ? (int)(dpk >> 32) : st_done;
-        __syncthreads();  // selected rows complete
-        if (s_done) return false;
+        // a stopped fit evaluates nothing (the selection above wrote only
+        // LDS); every thread holds the same stop flag
+        const int done = PRE ? (int)(dpk >> 32) : st_done;
+        if (one) {
+            if (done) return false;
+            // the trial wave's own selected rows: its LDS accesses stay in
+            // program order, which the wave-scope fences keep the compiler to
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        } else {
+            if (i == 0) s_done = done;
+            __syncthreads();  // selected rows complete
+            if (s_done) return false;
+        }
         if (wave != kTrialWave) conv();
         if constexpr (PRE) dr = unpack_draws(dpk);
         // 5. the group's trials, one coordinate per thread (apply_trial's
