@@ -1608,8 +1608,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 4))
         // one block (launch index fused - 2, first unit 0) whose step inputs
         // came as kernel arguments, lp = P | ntiles << 9: nothing here waits
         // for the descriptor before the step's loads are issued
+        // (the host takes this form only for fewer than 2^23 units, the
+        // range of div_mid)
         const int P = lp & 511, ng = (P + CPG - 1) / CPG;
-        tile = unit / ng;
+        tile = div_mid(unit, ng);
         group = unit - tile * ng;
         L = fused - 2;
         lin = LeadIn{l_part, l_rows, l_trial, l_fpop, P, lp >> 9};

@@ -756,7 +756,7 @@ int prepare(pt_ctx* ctx, const pt_block* blocks, int nblk, const pt_de_settings*
     // objective launches: one over the main table, or (FP64 batches whose
     // blocks differ in arithmetic) the phasor blocks and the others apart; a
     // one-block leading-step fit passes the step's inputs as kernel arguments
-    const bool lead_fast = pl->fused == 2 && nblk == 1 && P < 512 && ntiles[0] < (1 << 22);
+    const bool lead_fast = pl->fused == 2 && nblk == 1 && P < 512 && ntiles[0] < (1 << 22) && units < (1 << 23);
     pl->launches.clear();
     auto add_launch = [&](int desc_off, int n, int mode, int64_t u) {
         Plan::Launch L;
