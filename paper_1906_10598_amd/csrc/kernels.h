@@ -666,8 +666,10 @@ __device__ __forceinline__ void unit_setup(const BlockDesc* __restrict__ d, int 
 // MODE: 0 = FP64 with per-sample cosine polynomial, 1 = mixed precision,
 // 2 = FP64 phasor recurrence.  The group's candidates are in cs (and rc)
 // (unit_setup); part: the partial sums to write.  red: LDS for the lane
-// sums (CPG x kThreads doubles).
-template <int S, int CPG, int MODE, bool SLOPE, typename V>
+// sums (CPG x kThreads doubles).  COHST: the partials are read inside the
+// launch (coherent stores); the leading-step form reads them only in the
+// next launch, whose boundary orders plain stores.
+template <int S, int CPG, int MODE, bool SLOPE, typename V, bool COHST = true>
 __device__ __forceinline__ void objective_unit(const BlockDesc* __restrict__ d, int tile, int group,
                                                const V (&sv)[S], bool full, int valid, const Cand* cs,
                                                const RotConst* rc, double (*red)[kThreads], double* part) {
@@ -741,7 +743,13 @@ __device__ __forceinline__ void objective_unit(const BlockDesc* __restrict__ d, 
 #pragma unroll
     for (int r = 0; r < kPer; ++r) {
         const int c = wave + r * kW;
-        if (lane == 0 && c < ncand) xst(part + (size_t)(cbase + c) * d->ntiles + tile, v[r]);
+        if (lane == 0 && c < ncand) {
+            double* dst = part + (size_t)(cbase + c) * d->ntiles + tile;
+            if constexpr (COHST)
+                xst(dst, v[r]);
+            else
+                gst(dst, v[r]);
+        }
     }
 }
 
@@ -1651,8 +1659,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 4))
         if (!de_lead<CPG, false, LEAD == 2>(d, L, tile, group, cs, de_lds, lin, raw, conv)) return;
         if ((int)(threadIdx.x >> 6) == kTrialWave) conv();  // while wave 0 makes the tile constants
         unit_setup<S, CPG, MODE, SLOPE>(d, tile, group, cs, rc, nullptr);
-        objective_unit<S, CPG, MODE, SLOPE>(d, tile, group, sv, full, valid, cs, rc, red,
-                                            (L & 1) ? d->partials2 : d->partials);
+        objective_unit<S, CPG, MODE, SLOPE, V, false>(d, tile, group, sv, full, valid, cs, rc, red,
+                                                      (L & 1) ? d->partials2 : d->partials);
     } else {
         load_lane<V, T, S>(d, tile, sv, full, valid);
         unit_setup<S, CPG, MODE, SLOPE>(d, tile, group, cs, rc, d->trial);
