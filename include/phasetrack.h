@@ -454,7 +454,9 @@ double pt_server_clock(pt_server* srv);
  *     grid-wide barrier, no per-generation launches).  Needs P <= 256 and a
  *     grid that fits on the device at once.
  *   PT_LAUNCH_GRAPH: per generation one objective launch and one DE-step
- *     launch, replayed from captured HIP graphs of 50 generations.
+ *     launch (or one launch with the step fused, see pt_ctx_set_step_fusion),
+ *     replayed from captured HIP graphs of 50 generations (250 for fits
+ *     without a window rule).
  *   PT_LAUNCH_AUTO (default): graph.  On MI355X the per-block barrier of
  *     the persistent grid costs about as much as graph-replayed launches,
  *     which run back to back, so the graph path is the faster default.

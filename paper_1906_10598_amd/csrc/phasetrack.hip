@@ -53,11 +53,12 @@ int fail(int code, const char* fmt, ...) {
         if (e_ != hipSuccess) return fail(PT_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
     } while (0)
 
-constexpr int kChunk = 50;  // generations per captured graph
+constexpr int kChunk = 50;       // generations per captured graph
+constexpr int kChunkLong = 250;  // ... for fits without a window rule
 constexpr int kMaxLeadGens = 20000;  // longest fit PT_FUSION_AUTO runs in the leading-step form
 // the leading-step form takes a launch's buffer slot from its parity, so every
 // graph must start at an even launch
-static_assert(kChunk % 2 == 0, "graph chunks must hold an even number of launches");
+static_assert(kChunk % 2 == 0 && kChunkLong % 2 == 0, "graph chunks must hold an even number of launches");
 
 struct DevBuf {
     void* p = nullptr;
@@ -889,7 +890,10 @@ int run_fit(pt_ctx* ctx, const pt_block* blocks, int nblk, const pt_de_settings*
             if ((rc = enqueue_generation(ctx, pl, s, true, k))) return rc;
     } else {
         hipGraphExec_t ex = nullptr;
-        const int full = iters / kChunk, rem = iters % kChunk;
+        // fits without a window rule need no stop checks between chunks:
+        // longer chunks, fewer graph launches
+        const int chunk = pl.window ? kChunk : kChunkLong;
+        const int full = iters / chunk, rem = iters % chunk;
         DeState* hst = static_cast<DeState*>(ctx->hstate.p);
         const int ns = lead ? 2 * nblk : nblk;  // leading-step form: either slot may hold the stop
         auto stopped = [&](const DeState* h) {
@@ -899,7 +903,7 @@ int run_fit(pt_ctx* ctx, const pt_block* blocks, int nblk, const pt_de_settings*
         };
         bool all = false;
         for (int c = 0; c < full && !all; ++c) {
-            if ((c == 0 || lead) && (rc = get_graph(ctx, pl, kChunk, c * kChunk, &ex))) return rc;
+            if ((c == 0 || lead) && (rc = get_graph(ctx, pl, chunk, c * chunk, &ex))) return rc;
             HIPCHK(hipGraphLaunch(ex, s));
             if (pl.window && c + 1 < full) {
                 // Stop launching once every block has met its stop rule.  The
@@ -917,7 +921,7 @@ int run_fit(pt_ctx* ctx, const pt_block* blocks, int nblk, const pt_de_settings*
             }
         }
         for (int k = 0; k < rem && !all; ++k)
-            if ((rc = enqueue_generation(ctx, pl, s, false, full * kChunk + k))) return rc;
+            if ((rc = enqueue_generation(ctx, pl, s, false, full * chunk + k))) return rc;
     }
     hipLaunchKernelGGL(k_finalize, dim3(nblk), dim3(64), 0, s, d, static_cast<FitRecord*>(ctx->rec.p));
     HIPCHK(hipGetLastError());

@@ -147,15 +147,17 @@ def test_timed_fit_equals_two_launch_form(mode):
 
 
 def test_graph_cache_eviction_keeps_fits_bitwise():
-    # the leading-step form captures one graph per 50-generation chunk (the
-    # launch index is a kernel argument); a fit of 13 000 generations needs 260
-    # of them, more than a context caches (256), so the cache evicts its least
-    # recently used quarter in the middle of the fit (after waiting for the
-    # device, since the fit's earlier chunks are still queued) and again during
-    # the next fit, which finds its first chunks evicted
+    # the leading-step form captures one graph per chunk (the launch index is
+    # a kernel argument), of 50 generations when the window rule is on; a fit
+    # of 13 000 generations needs 260 of them, more than a context caches
+    # (256), so the cache evicts its least recently used quarter in the middle
+    # of the fit (after waiting for the device, since the fit's earlier chunks
+    # are still queued) and again during the next fit, which finds its first
+    # chunks evicted.  (The window spans the whole fit, so the rule, on, never
+    # stops it early.)
     b = synth.config0(2)
     dev = to_dev(b.samples)
-    de = settings_of(b, gens=13_000, rel_tol=0.0, window=0)
+    de = settings_of(b, gens=13_000, rel_tol=1e-300, window=13_000)
     with ptk.Context(0) as c:
         ptk.pt_ctx_set_step_fusion(c.handle, ptk.PT_FUSION_LEAD)
         first = c.fit_block(block_of(b, dev), de)
